@@ -1,0 +1,160 @@
+/*
+ * lhdm.h -- C ABI of the MI355X (gfx950) nonnegative least-squares library.
+ *
+ * Problem (Section 2, problem (NNLS)): given a dense A (m x n) and b (m),
+ *     minimise ||A x - b||_2  subject to  x >= 0.
+ * Solvers: Lawson-Hanson (Algorithm 1, `lh_solve`) and Lawson-Hanson with
+ * Deviation Maximization (Algorithm 3 with the column selection of Algorithm 2,
+ * `lhdm_solve`, `lhdm_solve_batched`), both returning the primal x, the dual
+ * w = A^T (b - A x) and the ordered passive set P (Theorem 1, KKT conditions).
+ * `lhdm_backward` differentiates x*(A, b) through the final passive set.
+ *
+ * Conventions shared by every entry point
+ *   - All matrices are float64, column-major, with leading dimension lda >= m.
+ *   - Pointers marked [dev] are device pointers on the current HIP device,
+ *     pointers marked [host] are host pointers.  The caller owns every buffer it
+ *     passes; the library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work is
+ *     enqueued on it.  Every entry point returns after its results are written
+ *     (it synchronises `stream`).
+ *   - Workspace: `ws` [dev] of at least the size returned by the matching
+ *     *_workspace_bytes query, aligned to 256 bytes.  If ws is NULL the library
+ *     allocates a workspace itself and keeps it cached per device until
+ *     lhdm_release() is called.
+ *   - Return value: 0 on success, a negative LHDM_E* code if the call itself
+ *     failed (nothing was solved; outputs are unspecified).  The per-instance
+ *     outcome is reported in lhdm_info.status (LHDM_STATUS_*).
+ *   - No exception crosses this interface.
+ */
+#ifndef LHDM_H
+#define LHDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* call-level errors (negative return values) */
+#define LHDM_EINVAL     (-1)   /* bad size, pointer or parameter */
+#define LHDM_EWORKSPACE (-2)   /* workspace too small or misaligned */
+#define LHDM_EHIP       (-3)   /* a HIP runtime call failed; see lhdm_last_hip_error() */
+#define LHDM_EUNSUPPORTED (-4) /* size beyond what this build supports */
+
+/* per-instance outcome (lhdm_info.status) */
+#define LHDM_STATUS_OK        0  /* KKT conditions hold at kkt_tol */
+#define LHDM_STATUS_MAXITER   1  /* iteration limit reached; x is the last feasible iterate */
+#define LHDM_STATUS_NONFINITE 2  /* A or b holds a NaN or Inf; x = 0 */
+#define LHDM_STATUS_RANK      3  /* no numerically independent column with positive dual left */
+
+/* Solver parameters [host].  tau1, tau2, delta and kmax are the thresholds of
+ * Algorithm 2 (delta is the tau_c of the Algorithm 3 signature); the defaults are
+ * the values used throughout the paper's experiments (Section 5): tau1 = 0.6,
+ * tau2 = 0.15, delta = 0.9, kmax = 32.  kkt_tol scales the outer-loop stopping
+ * test: stop when max_{j in Z} w_j <= kkt_tol * max_j ||a_j||_2 * ||b||_2.
+ * max_outer / max_inner <= 0 select 3n.  flags: reserved, pass 0. */
+typedef struct lhdm_params {
+    double  tau1;
+    double  tau2;
+    double  delta;
+    double  kkt_tol;
+    int32_t kmax;        /* 1 <= kmax <= 64 */
+    int32_t max_outer;
+    int32_t max_inner;
+    int32_t flags;
+} lhdm_params;
+
+/* Per-instance result, written to device memory [dev]. */
+typedef struct lhdm_info {
+    int32_t status;        /* LHDM_STATUS_* */
+    int32_t outer_iters;   /* accepted outer steps */
+    int32_t inner_iters;   /* inner (feasibility) iterations */
+    int32_t jloop_drops;   /* columns dropped by the feasibility loop on J */
+    int32_t n_passive;     /* |P| at exit */
+    int32_t reserved;
+    double  kkt_residual;  /* max(max_Z w+, max_P |w|) / (max_j ||a_j|| ||b||) */
+    double  objective;     /* ||b - A x||^2 */
+} lhdm_info;
+
+/* Fill p with the defaults above (kkt_tol = 1e-9). */
+void lhdm_default_params(lhdm_params* p);
+
+/* Bytes of workspace needed by lhdm_solve / lh_solve for an m x n instance. */
+size_t lhdm_workspace_bytes(int32_t m, int32_t n, const lhdm_params* p);
+
+/* LHDM solve of one instance (Algorithm 3; selection by Algorithm 2; block
+ * append by the Householder updating of Algorithm 4 in compact-WY form; removal
+ * by the Givens downdating of Algorithm 5).
+ *   A [dev] m x n, lda >= m;  b [dev] m.
+ *   x [dev] n (out): the solution, exactly 0 outside P.
+ *   w [dev] n (out, may be NULL): the dual A^T (b - A x) at exit.
+ *   passive [dev] n (out, may be NULL): P in insertion order, padded with -1.
+ *   info [dev] (out, may be NULL).
+ * Returns LHDM_EINVAL for m < 1, n < 1, lda < m, NULL A/b/x, tau1 or tau2
+ * outside (0, 1], delta outside (0, 1], kmax outside [1, 64]. */
+int lhdm_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda,
+               const double* b, const lhdm_params* p, double* x, double* w,
+               int32_t* passive, lhdm_info* info, void* ws, size_t ws_bytes);
+
+/* Plain Lawson-Hanson (Algorithm 1): one column per outer step with a rank-one
+ * Householder append.  Same arguments and outputs as lhdm_solve. */
+int lh_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda,
+             const double* b, double kkt_tol, int32_t max_outer, double* x,
+             double* w, int32_t* passive, lhdm_info* info, void* ws, size_t ws_bytes);
+
+/* Bytes of workspace for lhdm_solve_batched over `batch` instances with the
+ * given sizes (m, n are [host] arrays of length batch). */
+size_t lhdm_batched_workspace_bytes(int32_t batch, const int32_t* m, const int32_t* n,
+                                    const lhdm_params* p);
+
+/* Many independent instances of uneven size in one persistent launch: one
+ * workgroup solves one instance at a time, instances are taken largest-first
+ * from a device work queue.
+ *   m, n, a_off, b_off, x_off: [host] arrays of length batch.  Instance i reads
+ *   A_pool + a_off[i] (column-major, lda = m[i]) and b_pool + b_off[i], and writes
+ *   x_pool + x_off[i] (n[i] values) and passive_pool + x_off[i] (n[i] values,
+ *   may be NULL).  use_lh = 1 runs plain LH instead of LHDM.
+ *   infos [dev] batch entries (may be NULL). */
+int lhdm_solve_batched(void* stream, int32_t batch, const int32_t* m, const int32_t* n,
+                       const int64_t* a_off, const double* A_pool,
+                       const int64_t* b_off, const double* b_pool,
+                       const int64_t* x_off, double* x_pool, int32_t* passive_pool,
+                       const lhdm_params* p, int32_t use_lh, lhdm_info* infos,
+                       void* ws, size_t ws_bytes);
+
+/* Bytes of workspace for lhdm_backward. */
+size_t lhdm_backward_workspace_bytes(int32_t batch, const int32_t* m, const int32_t* n);
+
+/* Derivative of x*(A, b) through the final passive set (not in the paper: the
+ * least-squares map x_P = argmin ||A_P y - b|| of Section 2.1 at the returned P,
+ * with x_Z = 0, differentiated exactly).  For upstream gradient g = dL/dx:
+ *   lambda = (A_P^T A_P)^{-1} g_P          (via a Householder QR of A_P)
+ *   grad_b = A_P lambda
+ *   grad_A[:, P] = r lambda^T - (A_P lambda) x_P^T,  r = b - A_P x_P
+ *   grad_A[:, Z] = 0.
+ * Layout as in lhdm_solve_batched: [host] size/offset arrays, [dev] pools.
+ * passive_pool holds each instance's P (as returned by the forward call, -1
+ * padded); grad_A_pool is fully overwritten (lda = m[i]); grad_b_pool gets m[i]
+ * values at b_off[i]. */
+int lhdm_backward(void* stream, int32_t batch, const int32_t* m, const int32_t* n,
+                  const int64_t* a_off, const double* A_pool,
+                  const int64_t* b_off, const double* b_pool,
+                  const int64_t* x_off, const double* x_pool, const int32_t* passive_pool,
+                  const double* grad_x_pool, double* grad_A_pool, double* grad_b_pool,
+                  void* ws, size_t ws_bytes);
+
+/* Text for a status or error code. */
+const char* lhdm_status_string(int code);
+
+/* The last hipError_t seen by a call that returned LHDM_EHIP (0 if none). */
+int lhdm_last_hip_error(void);
+
+/* Free workspaces the library allocated itself (ws == NULL calls). */
+void lhdm_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LHDM_H */

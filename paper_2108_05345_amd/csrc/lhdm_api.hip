@@ -1,0 +1,346 @@
+// C ABI of the gfx950 LH / LHDM library (declarations and contracts in lhdm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "lhdm.h"
+#include "lhdm_host.hpp"
+#include "lhdm_device.hpp"
+#include "lhdm_wg.hpp"
+#include "lhdm_large.hpp"
+#include "lhdm_backward.hpp"
+
+namespace lhdm {
+
+// ---------------------------------------------------------------------------
+// kernels of the workgroup engine
+// ---------------------------------------------------------------------------
+struct ProbIn {
+    const double* A;
+    long long lda;
+    const double* b;
+    double* x;
+    double* w;
+    int* passive;
+    lhdm_info* info;
+    int m, n;
+};
+
+// Persistent batched solve: each workgroup owns one workspace slot and takes
+// instances from the queue `order` (largest first) until it is exhausted.
+__global__ __launch_bounds__(WG) void wg_solve_kernel(const ProbIn* __restrict__ ins, int nprob,
+                                                      const int* __restrict__ order, int* counter,
+                                                      char* slots, size_t slot_stride, DevParams prm) {
+    __shared__ WgShared sh;
+    __shared__ int sidx;
+    char* base = slots + (size_t)blockIdx.x * slot_stride;
+    while (true) {
+        if (threadIdx.x == 0) sidx = atomicAdd(counter, 1);
+        __syncthreads();
+        const int idx = sidx;
+        __syncthreads();
+        if (idx >= nprob) break;
+        const ProbIn in = ins[order[idx]];
+        Prob p;
+        p.A = in.A;
+        p.lda = in.lda;
+        p.b = in.b;
+        p.x = in.x;
+        p.w = in.w;
+        p.passive = in.passive;
+        p.info = in.info;
+        carve_slot(p, base, in.m, in.n, prm.kmax);
+        Wg wg(p, prm, sh);
+        wg.run();
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+static bool params_ok(const lhdm_params* p) {
+    if (!p) return false;
+    if (!(p->tau1 > 0.0 && p->tau1 <= 1.0)) return false;
+    if (!(p->tau2 > 0.0 && p->tau2 <= 1.0)) return false;
+    if (!(p->delta > 0.0 && p->delta <= 1.0)) return false;
+    if (!(p->kkt_tol >= 0.0)) return false;
+    if (p->kmax < 1 || p->kmax > KM) return false;
+    return true;
+}
+
+static DevParams dev_params(const lhdm_params* p, int n, int lh) {
+    DevParams d;
+    d.tau1 = p->tau1;
+    d.tau2 = p->tau2;
+    d.delta = p->delta;
+    d.kkt_tol = p->kkt_tol;
+    d.kmax = lh ? 1 : p->kmax;
+    d.max_outer = p->max_outer > 0 ? p->max_outer : 3 * n;
+    d.max_inner = p->max_inner > 0 ? p->max_inner : 3 * n;
+    d.lh = lh;
+    return d;
+}
+
+// Layout of the workgroup-engine workspace:
+// [ProbIn x batch | order x batch | counter | slots x nslot]
+struct WgLayout {
+    size_t off_in, off_order, off_counter, off_slots, slot_stride, total;
+    int nslot;
+};
+
+static int wg_slots_for(int batch) {
+    static int cus = -1;
+    if (cus < 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) cus = 256;
+        else cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_solve_kernel, WG, 0) != hipSuccess || occ < 1)
+        occ = 1;
+    return std::max(1, std::min(batch, cus * occ));
+}
+
+static WgLayout wg_layout(int batch, int mmax, int nmax, int kmax) {
+    WgLayout L;
+    L.nslot = wg_slots_for(batch);
+    size_t o = 0;
+    L.off_in = o;
+    o += pad256(sizeof(ProbIn) * (size_t)batch);
+    L.off_order = o;
+    o += pad256(sizeof(int) * (size_t)batch);
+    L.off_counter = o;
+    o += 256;
+    L.off_slots = o;
+    L.slot_stride = slot_bytes(mmax, nmax, kmax);
+    o += L.slot_stride * (size_t)L.nslot;
+    L.total = o;
+    return L;
+}
+
+static int run_wg_engine(hipStream_t st, const std::vector<ProbIn>& ins, const std::vector<int>& mm,
+                         const std::vector<int>& nn, const DevParams& prm, void* ws, size_t ws_bytes) {
+    const int batch = (int)ins.size();
+    const int mmax = *std::max_element(mm.begin(), mm.end());
+    const int nmax = *std::max_element(nn.begin(), nn.end());
+    WgLayout L = wg_layout(batch, mmax, nmax, prm.kmax);
+    if (ws == nullptr) {
+        int rc = cached_workspace(L.total, &ws);
+        if (rc) return rc;
+    } else if (ws_bytes < L.total || ((uintptr_t)ws & 255)) {
+        return LHDM_EWORKSPACE;
+    }
+    char* base = (char*)ws;
+    // largest instances first (longest-processing-time order for the queue)
+    std::vector<int> order(batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (long long)mm[a] * nn[a] > (long long)mm[b] * nn[b];
+    });
+    HIPCHK(hipMemcpyAsync(base + L.off_in, ins.data(), sizeof(ProbIn) * batch, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + L.off_order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(base + L.off_counter, 0, sizeof(int), st));
+    hipLaunchKernelGGL(wg_solve_kernel, dim3(L.nslot), dim3(WG), 0, st, (const ProbIn*)(base + L.off_in), batch,
+                       (const int*)(base + L.off_order), (int*)(base + L.off_counter), base + L.off_slots,
+                       L.slot_stride, prm);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+static bool use_wg_engine(int m, int n) {
+    // a single workgroup streams A once per outer step: fine while A is small
+    return m <= MMAX_WG && (long long)m * n <= (1LL << 18);
+}
+
+static int solve_one(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                     const DevParams& prm, double* x, double* w, int32_t* passive, lhdm_info* info, void* ws,
+                     size_t ws_bytes) {
+    if (m < 1 || n < 1 || lda < m || !A || !b || !x) return LHDM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (!use_wg_engine(m, n)) {
+        return large_solve(st, m, n, A, lda, b, prm, x, w, passive, info, ws, ws_bytes);
+    }
+    // w is required by the engine; use the workspace tail when the caller passes NULL
+    std::vector<ProbIn> ins(1);
+    ins[0].A = A;
+    ins[0].lda = lda;
+    ins[0].b = b;
+    ins[0].x = x;
+    ins[0].w = w;
+    ins[0].passive = passive;
+    ins[0].info = info;
+    ins[0].m = m;
+    ins[0].n = n;
+    WgLayout L = wg_layout(1, m, n, prm.kmax);
+    const size_t extra = pad256(sizeof(double) * (size_t)n);
+    if (ws == nullptr) {
+        int rc = cached_workspace(L.total + extra, &ws);
+        if (rc) return rc;
+        ws_bytes = L.total + extra;
+    }
+    if (ws_bytes < L.total + extra || ((uintptr_t)ws & 255)) return LHDM_EWORKSPACE;
+    if (!w) ins[0].w = (double*)((char*)ws + L.total);
+    std::vector<int> mm{m}, nn{n};
+    return run_wg_engine(st, ins, mm, nn, prm, ws, L.total);
+}
+
+}  // namespace lhdm
+
+using namespace lhdm;
+
+extern "C" {
+
+void lhdm_default_params(lhdm_params* p) {
+    if (!p) return;
+    p->tau1 = 0.6;
+    p->tau2 = 0.15;
+    p->delta = 0.9;
+    p->kkt_tol = 1e-9;
+    p->kmax = 32;
+    p->max_outer = 0;
+    p->max_inner = 0;
+    p->flags = 0;
+}
+
+size_t lhdm_workspace_bytes(int32_t m, int32_t n, const lhdm_params* p) {
+    if (m < 1 || n < 1) return 0;
+    const int kmax = p ? p->kmax : 32;
+    if (use_wg_engine(m, n)) {
+        WgLayout L = wg_layout(1, m, n, kmax < 1 ? 1 : kmax);
+        return L.total + pad256(sizeof(double) * (size_t)n);
+    }
+    return large_workspace_bytes(m, n, kmax < 1 ? 1 : kmax);
+}
+
+int lhdm_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, const double* b,
+               const lhdm_params* p, double* x, double* w, int32_t* passive, lhdm_info* info, void* ws,
+               size_t ws_bytes) {
+    lhdm_params def;
+    if (!p) {
+        lhdm_default_params(&def);
+        p = &def;
+    }
+    if (!params_ok(p)) return LHDM_EINVAL;
+    return solve_one(stream, m, n, A, lda, b, dev_params(p, n, 0), x, w, passive, info, ws, ws_bytes);
+}
+
+int lh_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, const double* b, double kkt_tol,
+             int32_t max_outer, double* x, double* w, int32_t* passive, lhdm_info* info, void* ws,
+             size_t ws_bytes) {
+    lhdm_params p;
+    lhdm_default_params(&p);
+    p.kkt_tol = kkt_tol;
+    p.max_outer = max_outer;
+    p.kmax = 1;
+    if (!(kkt_tol >= 0.0)) return LHDM_EINVAL;
+    return solve_one(stream, m, n, A, lda, b, dev_params(&p, n, 1), x, w, passive, info, ws, ws_bytes);
+}
+
+size_t lhdm_batched_workspace_bytes(int32_t batch, const int32_t* m, const int32_t* n, const lhdm_params* p) {
+    if (batch < 1 || !m || !n) return 0;
+    int mmax = 1, nmax = 1;
+    size_t wextra = 0;
+    for (int i = 0; i < batch; ++i) {
+        mmax = std::max(mmax, (int)m[i]);
+        nmax = std::max(nmax, (int)n[i]);
+        wextra += (size_t)std::max(0, (int)n[i]);
+    }
+    const int kmax = p ? std::max(1, (int)p->kmax) : 32;
+    WgLayout L = wg_layout(batch, mmax, nmax, kmax);
+    return L.total + pad256(sizeof(double) * wextra);
+}
+
+int lhdm_solve_batched(void* stream, int32_t batch, const int32_t* m, const int32_t* n, const int64_t* a_off,
+                       const double* A_pool, const int64_t* b_off, const double* b_pool, const int64_t* x_off,
+                       double* x_pool, int32_t* passive_pool, const lhdm_params* p, int32_t use_lh,
+                       lhdm_info* infos, void* ws, size_t ws_bytes) {
+    lhdm_params def;
+    if (!p) {
+        lhdm_default_params(&def);
+        p = &def;
+    }
+    if (batch < 1 || !m || !n || !a_off || !b_off || !x_off || !A_pool || !b_pool || !x_pool) return LHDM_EINVAL;
+    if (!params_ok(p)) return LHDM_EINVAL;
+    std::vector<int> mm(batch), nn(batch);
+    int nmax = 1;
+    for (int i = 0; i < batch; ++i) {
+        if (m[i] < 1 || n[i] < 1) return LHDM_EINVAL;
+        if (m[i] > MMAX_WG) return LHDM_EUNSUPPORTED;
+        mm[i] = m[i];
+        nn[i] = n[i];
+        nmax = std::max(nmax, (int)n[i]);
+    }
+    const size_t need = lhdm_batched_workspace_bytes(batch, m, n, p);
+    if (ws == nullptr) {
+        int rc = cached_workspace(need, &ws);
+        if (rc) return rc;
+        ws_bytes = need;
+    }
+    if (ws_bytes < need || ((uintptr_t)ws & 255)) return LHDM_EWORKSPACE;
+    const int kmax = use_lh ? 1 : p->kmax;
+    WgLayout L = wg_layout(batch, *std::max_element(mm.begin(), mm.end()), nmax, kmax);
+    double* wpool = (double*)((char*)ws + L.total);
+    std::vector<ProbIn> ins(batch);
+    size_t wo = 0;
+    for (int i = 0; i < batch; ++i) {
+        ins[i].A = A_pool + a_off[i];
+        ins[i].lda = m[i];
+        ins[i].b = b_pool + b_off[i];
+        ins[i].x = x_pool + x_off[i];
+        ins[i].w = wpool + wo;
+        wo += n[i];
+        ins[i].passive = passive_pool ? passive_pool + x_off[i] : nullptr;
+        ins[i].info = infos ? infos + i : nullptr;
+        ins[i].m = m[i];
+        ins[i].n = n[i];
+    }
+    DevParams prm = dev_params(p, nmax, use_lh ? 1 : 0);
+    prm.max_outer = p->max_outer > 0 ? p->max_outer : 3 * nmax;
+    prm.max_inner = p->max_inner > 0 ? p->max_inner : 3 * nmax;
+    return run_wg_engine((hipStream_t)stream, ins, mm, nn, prm, ws, L.total);
+}
+
+size_t lhdm_backward_workspace_bytes(int32_t batch, const int32_t* m, const int32_t* n) {
+    return backward_workspace_bytes(batch, m, n);
+}
+
+int lhdm_backward(void* stream, int32_t batch, const int32_t* m, const int32_t* n, const int64_t* a_off,
+                  const double* A_pool, const int64_t* b_off, const double* b_pool, const int64_t* x_off,
+                  const double* x_pool, const int32_t* passive_pool, const double* grad_x_pool,
+                  double* grad_A_pool, double* grad_b_pool, void* ws, size_t ws_bytes) {
+    if (ws == nullptr && batch > 0 && m && n) {
+        ws_bytes = backward_workspace_bytes(batch, m, n);
+        int rc = cached_workspace(ws_bytes, &ws);
+        if (rc) return rc;
+    }
+    return backward_run((hipStream_t)stream, batch, m, n, a_off, A_pool, b_off, b_pool, x_off, x_pool,
+                        passive_pool, grad_x_pool, grad_A_pool, grad_b_pool, ws, ws_bytes);
+}
+
+const char* lhdm_status_string(int code) {
+    switch (code) {
+        case LHDM_STATUS_OK: return "ok: KKT conditions hold at the requested tolerance";
+        case LHDM_STATUS_MAXITER: return "iteration limit reached";
+        case LHDM_STATUS_NONFINITE: return "non-finite input";
+        case LHDM_STATUS_RANK: return "no numerically independent column with positive dual left";
+        case LHDM_EINVAL: return "invalid argument";
+        case LHDM_EWORKSPACE: return "workspace too small or misaligned";
+        case LHDM_EHIP: return "HIP runtime error";
+        case LHDM_EUNSUPPORTED: return "size not supported by this build";
+        default: return "unknown code";
+    }
+}
+
+int lhdm_last_hip_error(void) { return g_last_hip; }
+
+void lhdm_release(void) { release_workspaces(); }
+
+}  // extern "C"

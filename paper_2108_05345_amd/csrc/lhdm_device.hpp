@@ -1,0 +1,173 @@
+// Shared device-side definitions of the gfx950 LH / LHDM library.
+//
+// Problem: min ||A x - b||_2 s.t. x >= 0 (Section 2).  State kept on the device
+// for one instance (the design differs from the paper's Matlab code: see the
+// per-field comments):
+//   Q   m x m, column-major: the full orthogonal factor, kept explicitly.  Its
+//       first n_P columns span range(A_P); blocked Householder appends update it
+//       by compact-WY products and Givens removals rotate pairs of its columns.
+//   R   n_P x n_P upper triangular, column-major, leading dimension kc = min(m,n);
+//       logical column c is the passive column P[c] (columns are compacted on
+//       removal, rows are positional).
+//   bt  Q^T b (m entries).
+//   u2  squared norms of the projections of the columns of A onto range(A_P)^perp
+//       (the vector u of Algorithm 3, squared), maintained incrementally.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lhdm.h"
+
+namespace lhdm {
+
+constexpr int WG = 256;              // threads per workgroup in every kernel
+constexpr int NW = WG / 64;          // waves per workgroup
+constexpr int KM = 64;               // largest supported kmax
+constexpr double DEP_TOL = 1e-12;    // projected norm <= DEP_TOL ||a_j||: numerically dependent
+constexpr double RECOMP_FRAC = 1e-4; // u2 below this fraction of ||a_j||^2: recompute exactly
+constexpr int YMAX = 2048;           // largest min(m, n) of the workgroup engine
+constexpr int MMAX_WG = 2048;        // largest m of the workgroup engine
+
+struct DevParams {
+    double tau1, tau2, delta, kkt_tol;
+    int kmax, max_outer, max_inner, lh;
+};
+
+// One instance: caller buffers plus its workspace slice.
+struct Prob {
+    const double* A;
+    long long lda;
+    const double* b;
+    double* x;
+    double* w;
+    int* passive;      // may be null
+    lhdm_info* info;   // may be null
+    int m, n, kc, kq;  // kc = min(m, n); kq = columns of the panel buffers (>= 2)
+    double* Q;         // m * m
+    double* R;         // kc * kc
+    double* bt;        // m
+    double* r;         // m
+    double* u2;        // n
+    double* an2;       // n
+    double* G;         // m * kq : projected candidates / Householder panel
+    double* V;         // m * kq : explicit Householder vectors (zeros above the unit diagonal)
+    double* W;         // m * kq : WY scratch
+    double* Qadd;      // m * kq : the columns of Q appended in this outer step
+    double* T;         // kq * kq : compact-WY factor, also the Gram matrix of the candidates
+    double* rot;       // 2 * kc  : rotations of one column of the downdate
+    int* P;            // kc : ordered passive set
+    int* pos;          // n  : position in P, or -1
+    int* excl;         // n  : excluded for the current outer step
+    int* rm;           // kc : removal positions of an inner iteration
+};
+
+// Bytes of one instance's workspace slice (each array padded to 256 bytes).
+__host__ __device__ inline size_t pad256(size_t b) { return (b + 255) & ~size_t(255); }
+
+__host__ __device__ inline int panel_cols(int kmax) { return kmax < 2 ? 2 : kmax; }
+
+__host__ __device__ inline size_t slot_bytes(int m, int n, int kmax) {
+    const size_t kc = (size_t)(m < n ? m : n);
+    const size_t kq = (size_t)panel_cols(kmax);
+    size_t s = 0;
+    s += pad256(sizeof(double) * (size_t)m * m);       // Q
+    s += pad256(sizeof(double) * kc * kc);             // R
+    s += 2 * pad256(sizeof(double) * (size_t)m);       // bt, r
+    s += 2 * pad256(sizeof(double) * (size_t)n);       // u2, an2
+    s += 4 * pad256(sizeof(double) * (size_t)m * kq);  // G, V, W, Qadd
+    s += pad256(sizeof(double) * kq * kq);             // T
+    s += pad256(sizeof(double) * 2 * kc);              // rot
+    s += 2 * pad256(sizeof(int) * kc);                 // P, rm
+    s += 2 * pad256(sizeof(int) * (size_t)n);          // pos, excl
+    return s;
+}
+
+__host__ __device__ inline void carve_slot(Prob& p, char* base, int m, int n, int kmax) {
+    const size_t kc = (size_t)(m < n ? m : n);
+    const size_t kq = (size_t)panel_cols(kmax);
+    p.m = m;
+    p.n = n;
+    p.kc = (int)kc;
+    p.kq = (int)kq;
+    char* c = base;
+    auto take = [&](size_t bytes) { char* r = c; c += pad256(bytes); return r; };
+    p.Q = (double*)take(sizeof(double) * (size_t)m * m);
+    p.R = (double*)take(sizeof(double) * kc * kc);
+    p.bt = (double*)take(sizeof(double) * m);
+    p.r = (double*)take(sizeof(double) * m);
+    p.u2 = (double*)take(sizeof(double) * n);
+    p.an2 = (double*)take(sizeof(double) * n);
+    p.G = (double*)take(sizeof(double) * (size_t)m * kq);
+    p.V = (double*)take(sizeof(double) * (size_t)m * kq);
+    p.W = (double*)take(sizeof(double) * (size_t)m * kq);
+    p.Qadd = (double*)take(sizeof(double) * (size_t)m * kq);
+    p.T = (double*)take(sizeof(double) * kq * kq);
+    p.rot = (double*)take(sizeof(double) * 2 * kc);
+    p.P = (int*)take(sizeof(int) * kc);
+    p.rm = (int*)take(sizeof(int) * kc);
+    p.pos = (int*)take(sizeof(int) * n);
+    p.excl = (int*)take(sizeof(int) * n);
+}
+
+// ---------------------------------------------------------------------------
+// wave / workgroup reductions (fixed association order: results are identical
+// in every lane and reproducible run to run)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return __shfl(v, 0, 64);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return __shfl(v, 0, 64);
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+    return __shfl(v, 0, 64);
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_down(v, o, 64));
+    return __shfl(v, 0, 64);
+}
+
+// larger value first, lower index on ties
+__device__ __forceinline__ bool better(double va, int ia, double vb, int ib) {
+    return va > vb || (va == vb && ia < ib);
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_down(v, o, 64);
+        const int oi = __shfl_down(i, o, 64);
+        if (better(ov, oi, v, i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+    v = __shfl(v, 0, 64);
+    i = __shfl(i, 0, 64);
+}
+
+// Rotation G = [[c, s], [-s, c]] with G [a, b]^T = [r, 0]^T (Algorithm 5's givens).
+__device__ __forceinline__ void givens(double a, double b, double& c, double& s, double& r) {
+    if (b == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        r = a;
+        return;
+    }
+    r = hypot(a, b);
+    c = a / r;
+    s = b / r;
+}
+
+}  // namespace lhdm

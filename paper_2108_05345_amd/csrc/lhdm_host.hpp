@@ -1,0 +1,84 @@
+// Host-side helpers shared by the entry points: the last HIP error seen and a
+// per-device cached workspace for calls that pass ws == NULL.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "lhdm.h"
+
+namespace lhdm {
+
+inline thread_local int g_last_hip = 0;
+
+inline void set_last_hip_error(int e) { g_last_hip = e; }
+
+#define HIPCHK(expr)                              \
+    do {                                          \
+        hipError_t e__ = (expr);                  \
+        if (e__ != hipSuccess) {                  \
+            ::lhdm::set_last_hip_error((int)e__); \
+            return LHDM_EHIP;                     \
+        }                                         \
+    } while (0)
+
+struct CachedWs {
+    int device = -1;
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+inline std::mutex& ws_mutex() {
+    static std::mutex mu;
+    return mu;
+}
+
+inline std::vector<CachedWs>& ws_cache() {
+    static std::vector<CachedWs> v;
+    return v;
+}
+
+// Library-owned workspace of at least `bytes` on the current device.
+inline int cached_workspace(size_t bytes, void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(ws_mutex());
+    for (auto& c : ws_cache())
+        if (c.device == dev) {
+            if (c.bytes < bytes) {
+                HIPCHK(hipDeviceSynchronize());
+                HIPCHK(hipFree(c.ptr));
+                c.ptr = nullptr;
+                c.bytes = 0;
+                HIPCHK(hipMalloc(&c.ptr, bytes));
+                c.bytes = bytes;
+            }
+            *out = c.ptr;
+            return 0;
+        }
+    CachedWs c;
+    c.device = dev;
+    HIPCHK(hipMalloc(&c.ptr, bytes));
+    c.bytes = bytes;
+    ws_cache().push_back(c);
+    *out = c.ptr;
+    return 0;
+}
+
+inline void release_workspaces() {
+    std::lock_guard<std::mutex> lk(ws_mutex());
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) cur = 0;
+    for (auto& c : ws_cache()) {
+        if (!c.ptr) continue;
+        (void)hipSetDevice(c.device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(c.ptr);
+    }
+    (void)hipSetDevice(cur);
+    ws_cache().clear();
+}
+
+}  // namespace lhdm

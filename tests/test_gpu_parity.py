@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar (from the requirements of the solver): identical passive set where the
+minimiser is unique, x within 1e-10 relative (max-norm), KKT residual <= 1e-9.
+Where the two follow the same path (no rounding-level near-ties) the ordered
+passive set and the iteration counters agree as well.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import make_c1, make_c3, make_c4_batch, make_c5_batch, make_small
+
+pytestmark = pytest.mark.gpu
+
+XTOL = 1e-10
+KKT = 1e-9
+
+
+@pytest.fixture(scope="module")
+def lhdm():
+    import paper_2108_05345_amd as mod
+    from paper_2108_05345_amd import _lib
+    _lib.load()   # fails loudly if the HIP library is missing
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return mod
+
+
+def _dev(A, b):
+    d = torch.device("cuda:0")
+    return (torch.from_numpy(np.asfortranarray(A)).to(d), torch.from_numpy(np.ascontiguousarray(b)).to(d))
+
+
+def _rel(x, xo):
+    return float(np.abs(x - xo).max() / max(np.abs(xo).max(), 1e-300))
+
+
+def _passive(res):
+    P = res.passive.cpu().numpy()
+    return [int(j) for j in P if j >= 0]
+
+
+SUPP_THR = 1e-12   # support = entries above this fraction of max|x| (rounding-level entries excluded)
+SEP = 1e-8         # a solution is well separated when every passive entry exceeds SEP * max|x|
+
+
+def _supp(x):
+    return sorted(int(j) for j in np.nonzero(x > SUPP_THR * np.abs(x).max(initial=0.0))[0])
+
+
+def _check(res, x_o, info_o, *, same_path=True, unique=True, tag=""):
+    """Compare one GPU result with the oracle's.
+
+    In zero-residual instances an appended column can have an exactly-zero
+    least-squares coefficient; its sign, and so the decisions of the feasibility
+    loops, is then set by rounding and legitimately differs between summation
+    orders.  Path identity (ordered P, iteration counters) is therefore required
+    only when the oracle's solution is well separated from zero."""
+    x = res.x.cpu().numpy()
+    print(f"[{tag}] gpu info {res.info} | oracle outer={info_o['outer_iters']} inner={info_o['inner_iters']} "
+          f"jd={info_o['jloop_drops']} nP={info_o['n_passive']}", flush=True)
+    assert res.info["status"] == info_o["status"] == 0
+    assert (x >= 0).all()
+    assert res.info["kkt_residual"] <= KKT
+    P = _passive(res)
+    assert res.info["n_passive"] == len(P)
+    assert all(x[j] > 0 for j in P)
+    assert np.count_nonzero(x) == len(P)
+    if unique:
+        assert _supp(x) == _supp(x_o), tag
+        assert _rel(x, x_o) <= XTOL, (tag, _rel(x, x_o))
+    Po = info_o["passive"]
+    separated = len(Po) == 0 or float(np.min(x_o[Po])) > SEP * float(np.abs(x_o).max())
+    if same_path and separated:
+        assert P == Po, tag
+        for key in ("outer_iters", "inner_iters", "jloop_drops"):
+            assert res.info[key] == info_o[key], (tag, key)
+    return separated
+
+
+@pytest.mark.parametrize("seed", list(range(1000, 1016)))
+def test_c1_lhdm_and_lh(lhdm, seed):
+    inst = make_c1(seed)
+    A, b = _dev(inst.A, inst.b)
+    xo, io = oracle.oracle_lhdm(inst.A, inst.b)
+    _check(lhdm.solve(A, b), xo, io, tag=f"c1-lhdm-{seed}")
+    xo, io = oracle.oracle_lh(inst.A, inst.b)
+    _check(lhdm.lh_solve(A, b), xo, io, tag=f"c1-lh-{seed}")
+    # planted recovery
+    np.testing.assert_allclose(lhdm.solve(A, b).x.cpu().numpy(), inst.x_true, atol=1e-12)
+
+
+RAGGED = [
+    # (m, n, k, kind, noise, seed): uniform A with noise -> positive residual (unique)
+    (37, 91, 9, "uniform", 1e-2, 1),
+    (64, 200, 20, "uniform", 1e-2, 2),
+    (130, 333, 33, "uniform", 1e-2, 3),
+    (200, 517, 52, "uniform", 1e-2, 4),
+    (257, 300, 30, "uniform", 1e-2, 5),
+    (300, 120, 40, "gauss", 1e-1, 6),     # overdetermined, full column rank
+    (130, 333, 20, "gauss", 0.0, 7),      # noiseless planted sparse
+    (71, 513, 7, "gauss", 0.0, 8),
+]
+
+
+@pytest.mark.parametrize("case", RAGGED, ids=[f"{c[0]}x{c[1]}-{c[3]}" for c in RAGGED])
+def test_ragged_unique_instances(lhdm, case):
+    m, n, k, kind, noise, seed = case
+    inst = make_small(m, n, k, seed, kind=kind, noise_std=noise)
+    A, b = _dev(inst.A, inst.b)
+    for delta in (0.9, 0.5, 0.2):
+        xo, io = oracle.oracle_lhdm(inst.A, inst.b, delta=delta)
+        _check(lhdm.solve(A, b, delta=delta), xo, io, tag=f"{m}x{n}-d{delta}")
+    xo, io = oracle.oracle_lh(inst.A, inst.b)
+    _check(lhdm.lh_solve(A, b), xo, io, tag=f"{m}x{n}-lh")
+
+
+@pytest.mark.parametrize("delta", [0.2, 0.5, 0.8])
+def test_scaled_c3_delta_sweep(lhdm, delta):
+    # the large Gaussian family scaled down (k/n kept): zero-residual, non-unique
+    # minimiser; both sides are compared on their path and the KKT conditions
+    inst = make_c3(3000, m=160, n=640, k=32)
+    A, b = _dev(inst.A, inst.b)
+    xo, io = oracle.oracle_lhdm(inst.A, inst.b, delta=delta)
+    _check(lhdm.solve(A, b, delta=delta), xo, io, unique=False, same_path=True, tag=f"c3s-d{delta}")
+
+
+def test_kmax_variants(lhdm):
+    inst = make_small(90, 260, 25, 11, kind="uniform", noise_std=1e-2)
+    A, b = _dev(inst.A, inst.b)
+    for kmax in (1, 2, 5, 17, 64):
+        xo, io = oracle.oracle_lhdm(inst.A, inst.b, kmax=kmax)
+        _check(lhdm.solve(A, b, kmax=kmax), xo, io, tag=f"kmax{kmax}")
+
+
+def test_batched_c4_subset(lhdm):
+    insts = make_c4_batch(count=48)
+    As, bs = zip(*[_dev(i.A, i.b) for i in insts])
+    for use_lh in (False, True):
+        res = lhdm.solve_batched(list(As), list(bs), use_lh=use_lh)
+        for inst, r in zip(insts, res):
+            if use_lh:
+                xo, io = oracle.oracle_lh(inst.A, inst.b)
+            else:
+                xo, io = oracle.oracle_lhdm(inst.A, inst.b)
+            _check(r, xo, io, same_path=False, tag=f"c4-{inst.name}-lh{int(use_lh)}")
+
+
+def test_backward_against_reference(lhdm):
+    insts = make_c5_batch(count=3, m=96, n=192)
+    for inst in insts:
+        A, b = _dev(inst.A, inst.b)
+        Ar = A.clone().requires_grad_(True)
+        br = b.clone().requires_grad_(True)
+        t = torch.from_numpy(inst.t).to(A.device)
+        x, passive = lhdm.LHDMFunction.apply(Ar, br)
+        ((x - t) ** 2).sum().backward()
+        P = [int(j) for j in passive.cpu().numpy() if j >= 0]
+        xn = x.detach().cpu().numpy()
+        gA, gb = oracle.nnls_grad_reference(inst.A, inst.b, xn, P, 2 * (xn - inst.t))
+        scale = max(np.abs(gA).max(), 1.0)
+        assert np.abs(Ar.grad.cpu().numpy() - gA).max() <= 1e-8 * scale
+        assert np.abs(br.grad.cpu().numpy() - gb).max() <= 1e-8 * max(np.abs(gb).max(), 1.0)
+
+
+def test_degenerate_inputs(lhdm):
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((10, 6))
+    Ad, bd = _dev(A, np.zeros(10))
+    r = lhdm.solve(Ad, bd)
+    assert r.info["status"] == 0 and r.info["n_passive"] == 0 and float(r.x.abs().max()) == 0.0
+    A2 = A.copy()
+    A2[3, 2] = np.nan
+    r = lhdm.solve(*_dev(A2, rng.standard_normal(10)))
+    assert r.info["status"] == oracle.STATUS_NONFINITE and float(r.x.abs().max()) == 0.0
+    A3 = np.concatenate([A, A[:, :2], np.zeros((10, 1))], axis=1)
+    b3 = rng.standard_normal(10)
+    r = lhdm.solve(*_dev(A3, b3))
+    xb, objb = oracle.brute_force_nnls(A3, b3)
+    assert r.info["status"] == 0
+    assert abs(r.info["objective"] - objb) <= 1e-10 * max(1.0, objb)
+    A4 = rng.standard_normal((3, 12))
+    b4 = rng.standard_normal(3)
+    for fn in (lhdm.solve, lhdm.lh_solve):
+        r = fn(*_dev(A4, b4))
+        xb, objb = oracle.brute_force_nnls(A4, b4)
+        assert abs(r.info["objective"] - objb) <= 1e-10 * max(1.0, objb)
+    a1 = rng.standard_normal((9, 1))
+    b1 = rng.standard_normal(9)
+    r = lhdm.solve(*_dev(a1, b1))
+    ref = max(0.0, float(a1[:, 0] @ b1) / float(a1[:, 0] @ a1[:, 0]))
+    assert abs(float(r.x[0]) - ref) <= 1e-14 * max(1.0, ref)
+
+
+def test_tiny_brute_force(lhdm):
+    rng = np.random.default_rng(17)
+    for t in range(12):
+        m = int(rng.integers(3, 12))
+        n = int(rng.integers(2, 11))
+        A = rng.standard_normal((m, n))
+        b = rng.standard_normal(m)
+        xb, objb = oracle.brute_force_nnls(A, b)
+        for fn in (lhdm.solve, lhdm.lh_solve):
+            r = fn(*_dev(A, b))
+            assert r.info["status"] == 0
+            assert abs(r.info["objective"] - objb) <= 1e-10 * max(1.0, objb)
+
+
+def test_deterministic(lhdm):
+    inst = make_small(120, 400, 30, 21, kind="uniform", noise_std=1e-2)
+    A, b = _dev(inst.A, inst.b)
+    r1 = lhdm.solve(A, b)
+    r2 = lhdm.solve(A, b)
+    assert torch.equal(r1.x, r2.x) and torch.equal(r1.passive, r2.passive)
