@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""NNLS solves/sec at KKT tol 1e-9 on one MI355X: LHDM against plain LH on the same GPU.
+
+Workload: the large Gaussian instance, m = 4096, n = 16384, A ~ N(0, 1/m), an
+820-sparse planted x with |N(0,1)| + 0.1 values, noise std 1e-3, seed 3000
+(generated on the host, uploaded to HBM before timing).  LHDM runs with
+tau1 = 0.6, tau2 = 0.15, kmax = 32 and delta = 0.8 (the largest value of the
+delta sweep); plain LH on the same instance gives the speedup.  One step = one
+complete solve (every step of the method, initialisation to KKT).
+
+Prints one JSON line.  Extra objects: ``roofline`` for the dominant kernel (the
+dual GEMV fused with the projected-norm update, timed live with HIP events),
+``cpu_baseline`` (the CPU oracle on a bounded sample of the same solve) and
+``lh`` (the plain Lawson-Hanson timing).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "NNLS solves/sec at KKT tol 1e-9: LHDM vs plain LH, same GPU; batched + backward"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dual_gemv_c3_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2108_05345_amd", "csrc", "lhdm_large.hpp")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dual kernel from committed rocprofv3 counters,
+    or None when they were taken on a different version of the kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha256_16") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(inst, delta, outer_total, max_outer):
+    """The CPU oracle on a bounded sample: the first `max_outer` outer steps of the
+    same LHDM solve, scaled by the fraction of the GPU solve's outer steps."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    _, info = oracle.oracle_lhdm(inst.A, inst.b, delta=delta, max_outer=max_outer)
+    dt = time.perf_counter() - t0
+    done = info["outer_iters"]
+    frac = done / max(outer_total, 1)
+    return {"value": frac / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {done} of {outer_total} outer steps of the same LHDM solve (delta={delta}) "
+                      f"in {dt:.1f} s on the host, scaled by {done}/{outer_total}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lh-steps", type=int, default=1)
+    ap.add_argument("--delta", type=float, default=0.8)
+    ap.add_argument("--cpu-outer", type=int, default=3, help="outer steps of the oracle sample (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2108_05345_amd as lhdm
+    from paper_2108_05345_amd import _lib
+    from workloads import make_c3
+
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    inst = make_c3(3000)
+    m, n = inst.A.shape
+    A = torch.from_numpy(np.asfortranarray(inst.A)).to(dev)
+    b = torch.from_numpy(inst.b).to(dev)
+    assert A.stride() == (1, m)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+
+    for _ in range(args.warmup):
+        r = lhdm.solve(A, b, delta=args.delta)
+        log("warmup lhdm", r.info)
+    torch.cuda.synchronize()
+
+    import ctypes
+    lib.lhdm_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        r = lhdm.solve(A, b, delta=args.delta)
+        infos.append(r.info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, kl, kb = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    lib.lhdm_profile_read(ctypes.byref(kms), ctypes.byref(kl), ctypes.byref(kb))
+    lib.lhdm_profile_enable(0)
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    value = args.steps / (t1 - t0)
+    log("lhdm", infos[-1], f"{ms_per_step:.1f} ms/solve")
+
+    lh_value = lh_ms = None
+    lh_info = None
+    if args.lh_steps > 0:
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.lh_steps):
+            rl = lhdm.lh_solve(A, b)
+            lh_info = rl.info
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        lh_ms = 1e3 * (t3 - t2) / args.lh_steps
+        lh_value = args.lh_steps / (t3 - t2)
+        log("lh", lh_info, f"{lh_ms:.1f} ms/solve")
+
+    roof = None
+    if kl.value > 0:
+        avg_ms = kms.value / kl.value
+        bytes_per = kb.value / kl.value
+        achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic()
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "lg_colmat_dot (dual w = A^T r fused with the projected-norm update)",
+                "launches": int(kl.value), "avg_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": bytes_per}
+
+    cpu = None
+    if args.cpu_outer > 0:
+        cpu = cpu_baseline(inst, args.delta, infos[-1]["outer_iters"], args.cpu_outer)
+        log("cpu baseline", cpu)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "gauss-4096x16384-k820-noise1e-3-seed3000", "m": m, "n": n,
+                   "method": "lhdm", "tau1": 0.6, "tau2": 0.15, "delta": args.delta, "kmax": 32,
+                   "kkt_tol": 1e-9},
+        "lhdm_info": infos[-1],
+        "lh": None if lh_value is None else {"value": lh_value, "unit": "solves/s", "ms_per_solve": lh_ms,
+                                             "info": lh_info},
+        "speedup_vs_lh": None if lh_value is None else value / lh_value,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

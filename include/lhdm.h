@@ -48,12 +48,18 @@ extern "C" {
 #define LHDM_STATUS_NONFINITE 2  /* A or b holds a NaN or Inf; x = 0 */
 #define LHDM_STATUS_RANK      3  /* no numerically independent column with positive dual left */
 
+/* lhdm_params.flags: engine selection (default 0 = automatic). */
+#define LHDM_FLAG_ENGINE_WORKGROUP 1  /* one workgroup per instance (m <= 2048) */
+#define LHDM_FLAG_ENGINE_DEVICE    2  /* one instance over the whole GPU */
+
 /* Solver parameters [host].  tau1, tau2, delta and kmax are the thresholds of
  * Algorithm 2 (delta is the tau_c of the Algorithm 3 signature); the defaults are
  * the values used throughout the paper's experiments (Section 5): tau1 = 0.6,
  * tau2 = 0.15, delta = 0.9, kmax = 32.  kkt_tol scales the outer-loop stopping
  * test: stop when max_{j in Z} w_j <= kkt_tol * max_j ||a_j||_2 * ||b||_2.
- * max_outer / max_inner <= 0 select 3n.  flags: reserved, pass 0. */
+ * max_outer / max_inner <= 0 select 3n.  flags: LHDM_FLAG_* (0 = automatic engine:
+ * the one-workgroup engine for m <= 2048 and m*n <= 2^18, the whole-device
+ * engine otherwise; lhdm_solve_batched always uses the one-workgroup engine). */
 typedef struct lhdm_params {
     double  tau1;
     double  tau2;
@@ -143,6 +149,16 @@ int lhdm_backward(void* stream, int32_t batch, const int32_t* m, const int32_t* 
                   const int64_t* x_off, const double* x_pool, const int32_t* passive_pool,
                   const double* grad_x_pool, double* grad_A_pool, double* grad_b_pool,
                   void* ws, size_t ws_bytes);
+
+/* Timing of the dominant kernel: the dual w = A^T r fused with the projected-
+ * norm update (lg_colmat_dot in the whole-device engine).  When enabled, every
+ * launch of it is bracketed by HIP events on the solve's stream; the elapsed
+ * times are collected at the library's own stream synchronisations.
+ * lhdm_profile_enable(1) resets the counters.  lhdm_profile_read reports the
+ * summed kernel time [ms], the number of launches and the algorithmic bytes
+ * those launches move (8 m n for A plus the vectors read and written). */
+void lhdm_profile_enable(int on);
+int lhdm_profile_read(double* total_ms, int64_t* launches, double* bytes);
 
 /* Text for a status or error code. */
 const char* lhdm_status_string(int code);

@@ -107,11 +107,17 @@ def _single(A, b, method: str, params: LhdmParams) -> Result:
     return Result(x, w, passive, _info_dicts(info, 1)[0])
 
 
+ENGINES = {"auto": 0, "workgroup": 1, "device": 2}
+
+
 def solve(A: torch.Tensor, b: torch.Tensor, *, tau1=0.6, tau2=0.15, delta=0.9, kmax=32, kkt_tol=1e-9,
-          max_outer=0, max_inner=0) -> Result:
-    """LHDM solve of min ||A x - b|| s.t. x >= 0 (Algorithm 3 with Algorithm 2)."""
+          max_outer=0, max_inner=0, engine="auto") -> Result:
+    """LHDM solve of min ||A x - b|| s.t. x >= 0 (Algorithm 3 with Algorithm 2).
+
+    ``engine``: "auto", "workgroup" (one workgroup per instance, m <= 2048) or
+    "device" (one instance over the whole GPU)."""
     p = default_params(tau1=tau1, tau2=tau2, delta=delta, kmax=kmax, kkt_tol=kkt_tol, max_outer=max_outer,
-                       max_inner=max_inner)
+                       max_inner=max_inner, flags=ENGINES[engine])
     return _single(A, b, "lhdm", p)
 
 

@@ -70,6 +70,9 @@ SIGNATURES = {
     "lhdm_backward_workspace_bytes": (_sz, [_i32, _pi32, _pi32]),
     "lhdm_backward": (ctypes.c_int, [_vp, _i32, _pi32, _pi32, _pi64, _vp, _pi64, _vp, _pi64, _vp, _vp, _vp,
                                      _vp, _vp, _vp, _sz]),
+    "lhdm_profile_enable": (None, [ctypes.c_int]),
+    "lhdm_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_double)]),
     "lhdm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lhdm_last_hip_error": (ctypes.c_int, []),
     "lhdm_release": (None, []),

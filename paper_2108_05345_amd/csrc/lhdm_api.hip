@@ -160,12 +160,20 @@ static bool use_wg_engine(int m, int n) {
     return m <= MMAX_WG && (long long)m * n <= (1LL << 18);
 }
 
+static bool pick_wg(int m, int n, int flags) {
+    if (flags & LHDM_FLAG_ENGINE_DEVICE) return false;
+    if (flags & LHDM_FLAG_ENGINE_WORKGROUP) return true;
+    return use_wg_engine(m, n);
+}
+
 static int solve_one(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, const double* b,
-                     const DevParams& prm, double* x, double* w, int32_t* passive, lhdm_info* info, void* ws,
-                     size_t ws_bytes) {
+                     const DevParams& prm, int flags, double* x, double* w, int32_t* passive, lhdm_info* info,
+                     void* ws, size_t ws_bytes) {
     if (m < 1 || n < 1 || lda < m || !A || !b || !x) return LHDM_EINVAL;
+    if ((flags & LHDM_FLAG_ENGINE_WORKGROUP) && (flags & LHDM_FLAG_ENGINE_DEVICE)) return LHDM_EINVAL;
+    if ((flags & LHDM_FLAG_ENGINE_WORKGROUP) && m > MMAX_WG) return LHDM_EUNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
-    if (!use_wg_engine(m, n)) {
+    if (!pick_wg(m, n, flags)) {
         return large_solve(st, m, n, A, lda, b, prm, x, w, passive, info, ws, ws_bytes);
     }
     // w is required by the engine; use the workspace tail when the caller passes NULL
@@ -213,7 +221,7 @@ void lhdm_default_params(lhdm_params* p) {
 size_t lhdm_workspace_bytes(int32_t m, int32_t n, const lhdm_params* p) {
     if (m < 1 || n < 1) return 0;
     const int kmax = p ? p->kmax : 32;
-    if (use_wg_engine(m, n)) {
+    if (pick_wg(m, n, p ? p->flags : 0) && m <= MMAX_WG) {
         WgLayout L = wg_layout(1, m, n, kmax < 1 ? 1 : kmax);
         return L.total + pad256(sizeof(double) * (size_t)n);
     }
@@ -229,7 +237,7 @@ int lhdm_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda,
         p = &def;
     }
     if (!params_ok(p)) return LHDM_EINVAL;
-    return solve_one(stream, m, n, A, lda, b, dev_params(p, n, 0), x, w, passive, info, ws, ws_bytes);
+    return solve_one(stream, m, n, A, lda, b, dev_params(p, n, 0), p->flags, x, w, passive, info, ws, ws_bytes);
 }
 
 int lh_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, const double* b, double kkt_tol,
@@ -241,7 +249,7 @@ int lh_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, c
     p.max_outer = max_outer;
     p.kmax = 1;
     if (!(kkt_tol >= 0.0)) return LHDM_EINVAL;
-    return solve_one(stream, m, n, A, lda, b, dev_params(&p, n, 1), x, w, passive, info, ws, ws_bytes);
+    return solve_one(stream, m, n, A, lda, b, dev_params(&p, n, 1), 0, x, w, passive, info, ws, ws_bytes);
 }
 
 size_t lhdm_batched_workspace_bytes(int32_t batch, const int32_t* m, const int32_t* n, const lhdm_params* p) {
@@ -340,6 +348,24 @@ const char* lhdm_status_string(int code) {
 }
 
 int lhdm_last_hip_error(void) { return g_last_hip; }
+
+void lhdm_profile_enable(int on) {
+    KernelProfile& k = kprof();
+    k.on = on != 0;
+    k.ms = 0.0;
+    k.launches = 0;
+    k.bytes = 0.0;
+    k.pending.clear();
+    k.next = 0;
+}
+
+int lhdm_profile_read(double* total_ms, int64_t* launches, double* bytes) {
+    KernelProfile& k = kprof();
+    if (total_ms) *total_ms = k.ms;
+    if (launches) *launches = k.launches;
+    if (bytes) *bytes = k.bytes;
+    return 0;
+}
 
 void lhdm_release(void) { release_workspaces(); }
 

@@ -7,8 +7,8 @@
 //       first n_P columns span range(A_P); blocked Householder appends update it
 //       by compact-WY products and Givens removals rotate pairs of its columns.
 //   R   n_P x n_P upper triangular, column-major, leading dimension kc = min(m,n);
-//       logical column c is the passive column P[c] (columns are compacted on
-//       removal, rows are positional).
+//       logical column c (the passive column P[c]) lives in physical column
+//       slot[c], so removals never move data; rows are positional.
 //   bt  Q^T b (m entries).
 //   u2  squared norms of the projections of the columns of A onto range(A_P)^perp
 //       (the vector u of Algorithm 3, squared), maintained incrementally.
@@ -60,6 +60,10 @@ struct Prob {
     int* pos;          // n  : position in P, or -1
     int* excl;         // n  : excluded for the current outer step
     int* rm;           // kc : removal positions of an inner iteration
+    int* slot;         // kc : physical column of R holding logical column c (a permutation;
+                       //      slots [n_P, kc) are the free ones)
+    double* ybuf;      // kc : least-squares solution by position (large-instance engine)
+    double* Vt;        // m * kq : V stored row-major (large-instance engine)
 };
 
 // Bytes of one instance's workspace slice (each array padded to 256 bytes).
@@ -78,7 +82,7 @@ __host__ __device__ inline size_t slot_bytes(int m, int n, int kmax) {
     s += 4 * pad256(sizeof(double) * (size_t)m * kq);  // G, V, W, Qadd
     s += pad256(sizeof(double) * kq * kq);             // T
     s += pad256(sizeof(double) * 2 * kc);              // rot
-    s += 2 * pad256(sizeof(int) * kc);                 // P, rm
+    s += 3 * pad256(sizeof(int) * kc);                 // P, rm, slot
     s += 2 * pad256(sizeof(int) * (size_t)n);          // pos, excl
     return s;
 }
@@ -106,8 +110,11 @@ __host__ __device__ inline void carve_slot(Prob& p, char* base, int m, int n, in
     p.rot = (double*)take(sizeof(double) * 2 * kc);
     p.P = (int*)take(sizeof(int) * kc);
     p.rm = (int*)take(sizeof(int) * kc);
+    p.slot = (int*)take(sizeof(int) * kc);
     p.pos = (int*)take(sizeof(int) * n);
     p.excl = (int*)take(sizeof(int) * n);
+    p.ybuf = nullptr;
+    p.Vt = nullptr;
 }
 
 // ---------------------------------------------------------------------------

@@ -81,4 +81,62 @@ inline void release_workspaces() {
     ws_cache().clear();
 }
 
+// Event timing of the dominant kernel (see lhdm_profile_enable).
+struct KernelProfile {
+    bool on = false;
+    double ms = 0.0;
+    long long launches = 0;
+    double bytes = 0.0;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, double>> pending;   // (event index of the start, bytes)
+    int next = 0;
+};
+
+inline KernelProfile& kprof() {
+    static KernelProfile k;
+    return k;
+}
+
+// Record the start event of a timed launch; returns the event slot or -1.
+inline int kprof_begin(hipStream_t st) {
+    KernelProfile& k = kprof();
+    if (!k.on) return -1;
+    if (k.pool.empty()) {
+        k.pool.resize(2048);
+        for (auto& e : k.pool)
+            if (hipEventCreate(&e) != hipSuccess) {
+                k.pool.clear();
+                k.on = false;
+                return -1;
+            }
+    }
+    if (k.next + 2 > (int)k.pool.size()) return -1;   // drained at the next synchronisation
+    const int i = k.next;
+    k.next += 2;
+    (void)hipEventRecord(k.pool[i], st);
+    return i;
+}
+
+inline void kprof_end(hipStream_t st, int i, double bytes) {
+    KernelProfile& k = kprof();
+    if (i < 0) return;
+    (void)hipEventRecord(k.pool[i + 1], st);
+    k.pending.push_back({i, bytes});
+}
+
+// Called after the stream has been synchronised.
+inline void kprof_drain() {
+    KernelProfile& k = kprof();
+    for (auto& pr : k.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, k.pool[pr.first], k.pool[pr.first + 1]) == hipSuccess) {
+            k.ms += ms;
+            k.launches += 1;
+            k.bytes += pr.second;
+        }
+    }
+    k.pending.clear();
+    k.next = 0;
+}
+
 }  // namespace lhdm

@@ -1,16 +1,1072 @@
-// Large-instance engine (placeholder until the multi-workgroup kernels land).
+// Large-instance engine: one instance spread over the whole GPU.
+//
+// The outer/inner loops of Algorithm 3 run on the host; every step runs in a
+// kernel.  Bandwidth- and FLOP-heavy steps are multi-workgroup kernels:
+//   * lg_colmat_dot  -- X^T D for a column-major X and a few vectors D, on the
+//                       FP64 matrix cores (v_mfma_f64_16x16x4f64).  Used for the
+//                       dual w = A^T r fused with the update of the projected
+//                       column norms, and for the candidate projection Q^T A_J.
+//   * lg_qupdate     -- Q[:, n_P:m] <- Q[:, n_P:m] (I - V T V^T) (compact WY).
+//   * lg_trsv        -- R y = (Q^T b)[:n_P], row blocks chained by device flags.
+//   * lg_givens      -- Algorithm 5 on R: column blocks chained by device flags.
+//   * lg_qrot        -- the same rotations applied to the columns of Q.
+//   * lg_residual    -- r = b - A_P x_P.
+// The selection, deviation maximization, panel factorisation, feasibility
+// loop on J and the step length run in single-workgroup kernels that reuse
+// the workgroup engine's step functions on the shared control block Ctl.
 #pragma once
+
+#include <climits>
+#include <vector>
 
 #include "lhdm_device.hpp"
 #include "lhdm_host.hpp"
+#include "lhdm_wg.hpp"
 
 namespace lhdm {
 
-static size_t large_workspace_bytes(int m, int n, int kmax) { return 0; }
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-static int large_solve(hipStream_t, int, int, const double*, long long, const double*, const DevParams&, double*,
-                       double*, int*, lhdm_info*, void*, size_t) {
-    return LHDM_EUNSUPPORTED;
+constexpr int TB = 64;          // rows per block of the chained triangular solve
+constexpr int GB = 64;          // new columns per block of the chained downdate
+constexpr int RQ = 64;          // largest number of removals handled in one downdating sweep
+constexpr int RES_CHUNKS = 64;  // column chunks of the residual kernel
+constexpr long long SPIN_LIMIT = 1LL << 26;
+
+struct LgExtra {
+    int inner_done;   // set by lg_inner: no more inner iterations this outer step
+    int restart;      // the outer step appended nothing (feasibility loop emptied J)
+    int err;          // a chained kernel gave up waiting (should never happen)
+    int first;        // first removed position of the current downdate
+    int ndown;        // number of new columns from `first` on
+    int totrot;       // rotations of the current downdate
+    int nrecomp;      // columns flagged for an exact norm recomputation
+    int nvec;         // vectors of the dual update (r, added, dropped or trailing)
+    int kadd;         // added directions in the dual update
+    int exact;        // 1: norms recomputed from the trailing columns of Q
+    int pending;      // removals left over from a sweep capped at RQ positions
+    int seg_start[RQ + 1];
+    int seg_off[RQ + 1];
+};
+
+struct LgArgs {
+    Prob p;
+    DevParams prm;
+    Ctl* ctl;
+    LgExtra* ex;
+    double* Dt;       // m x 64 row-major vectors for lg_colmat_dot
+    double* rotbuf;   // 2 * kc * RQ rotation pairs
+    int* ocol;        // kc: old logical column of each new column of the downdate
+    int* lcnt;        // kc: rotations of each new column
+    int* roff;        // kc: offset of its rotations
+    int* flags_t;     // kc/TB + 1 epochs of the triangular solve
+    int* flags_g;     // kc/GB + 1 epochs of the downdate
+    int* recomp;      // n: columns whose projected norm is recomputed exactly
+    double* rpart;    // RES_CHUNKS * m residual partial sums
+};
+
+// --------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------
+__device__ inline void ctl_load(WgShared& s, const Ctl* g) {
+    int* d = reinterpret_cast<int*>(static_cast<Ctl*>(&s));
+    const int* src = reinterpret_cast<const int*>(g);
+    for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int)); i += blockDim.x) d[i] = src[i];
+    __syncthreads();
+}
+
+__device__ inline void ctl_store(const WgShared& s, Ctl* g) {
+    __syncthreads();
+    const int* src = reinterpret_cast<const int*>(static_cast<const Ctl*>(&s));
+    int* d = reinterpret_cast<int*>(g);
+    for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int)); i += blockDim.x) d[i] = src[i];
+    __syncthreads();
+}
+
+__device__ inline int load_acquire(const int* f) {
+    return __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void store_release(int* f, int v) {
+    __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double load_coherent(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *f == epoch; gives up (and flags an error) after SPIN_LIMIT polls so
+// that every wave always exits.
+__device__ inline void spin_wait(const int* f, int epoch, int* err) {
+    long long it = 0;
+    while (load_acquire(f) != epoch) {
+        if (++it > SPIN_LIMIT) {
+            atomicExch(err, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// --------------------------------------------------------------------------
+// initialisation
+// --------------------------------------------------------------------------
+// w = A^T b, ||a_j||^2, and the per-column state; one wave per column.
+__global__ __launch_bounds__(WG) void lg_init_cols(LgArgs a, unsigned long long* anmax_bits, int* bad) {
+    const Prob& p = a.p;
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * NW + (threadIdx.x >> 6);
+    if (j >= p.n) return;
+    const double* col = p.A + (size_t)j * p.lda;
+    double ab = 0.0, aa = 0.0;
+    for (int i = lane; i < p.m; i += 64) {
+        const double v = col[i];
+        ab += v * p.b[i];
+        aa += v * v;
+    }
+    ab = wave_sum(ab);
+    aa = wave_sum(aa);
+    if (lane == 0) {
+        p.w[j] = ab;
+        p.an2[j] = aa;
+        p.u2[j] = aa;
+        p.pos[j] = -1;
+        p.excl[j] = 0;
+        p.x[j] = 0.0;
+        if (!isfinite(ab) || !isfinite(aa)) atomicOr(bad, 1);
+        else atomicMax(anmax_bits, (unsigned long long)__double_as_longlong(aa));
+    }
+}
+
+__global__ __launch_bounds__(WG) void lg_fill_identity(double* Q, int m) {
+    const size_t mm = (size_t)m * m;
+    for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < mm; e += (size_t)gridDim.x * WG)
+        Q[e] = ((e % m) == (e / m)) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(WG) void lg_init_ctl(LgArgs a, const unsigned long long* anmax_bits, const int* bad) {
+    __shared__ WgShared s;
+    Prob p = a.p;
+    Wg wg(p, a.prm, s);
+    double bb = 0.0;
+    for (int i = threadIdx.x; i < p.m; i += WG) {
+        const double v = p.b[i];
+        bb += v * v;
+        p.bt[i] = v;
+        p.r[i] = v;
+    }
+    bb = wg.sum(bb);
+    for (int c = threadIdx.x; c < p.kc; c += WG) p.slot[c] = c;
+    if (threadIdx.x == 0) {
+        const double anmax = __longlong_as_double((long long)*anmax_bits);
+        s.anmax = sqrt(anmax);
+        s.bnorm = sqrt(bb);
+        s.tol_w = a.prm.kkt_tol * s.anmax * s.bnorm;
+        s.nP = 0;
+        s.status = (*bad || !isfinite(bb)) ? LHDM_STATUS_NONFINITE : LHDM_STATUS_OK;
+        s.outer = s.inner = s.jdrops = 0;
+        s.any_excl = 0;
+        s.done = (s.status != LHDM_STATUS_OK);
+        s.k = 0;
+        s.kr = 0;
+        a.ex->err = 0;
+        a.ex->nrecomp = 0;
+    }
+    ctl_store(s, a.ctl);
+}
+
+// --------------------------------------------------------------------------
+// single-workgroup steps
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void lg_select(LgArgs a) {
+    __shared__ WgShared s;
+    ctl_load(s, a.ctl);
+    Wg wg(a.p, a.prm, s);
+    wg.select();
+    if (threadIdx.x == 0) s.nP0 = s.nP;
+    ctl_store(s, a.ctl);
+}
+
+// Dt[row * 64 + t] = A[row, J[t]] (t < ncol), zero-padded to 64 columns.
+__global__ __launch_bounds__(WG) void lg_gather_cand(LgArgs a) {
+    const Prob& p = a.p;
+    const int nc = a.ctl->ncol;
+    const size_t tot = (size_t)p.m * 64;
+    for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < tot; e += (size_t)gridDim.x * WG) {
+        const int row = (int)(e / 64), t = (int)(e % 64);
+        a.Dt[e] = (t < nc) ? p.A[(size_t)a.ctl->J[t] * p.lda + row] : 0.0;
+    }
+}
+
+// Deviation maximization (or the single LH column), panel QR with bt carried
+// along, compact WY, new R columns and the feasibility loop on J.
+__global__ __launch_bounds__(WG) void lg_panel(LgArgs a) {
+    __shared__ WgShared s;
+    ctl_load(s, a.ctl);
+    Wg wg(a.p, a.prm, s);
+    const Prob& p = a.p;
+    if (s.ncol > 1) {
+        wg.deviation_maximization();
+    } else {
+        if (threadIdx.x == 0) s.k = 1;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s.kr = s.k;
+    __syncthreads();
+    wg.panel_qr();
+    if (s.kr > 1) {
+        wg.form_wy();
+    } else {
+        for (int i = threadIdx.x; i < p.m; i += WG) p.V[i] = (i < s.nP) ? 0.0 : p.G[i];
+        if (threadIdx.x == 0) p.T[0] = s.tau[0];
+        __syncthreads();
+    }
+    // row-major copy of V for the WY update of Q
+    const int kr = s.kr, kq = p.kq;
+    for (size_t e = threadIdx.x; e < (size_t)p.m * kq; e += WG) {
+        const int row = (int)(e / kq), t = (int)(e % kq);
+        p.Vt[e] = (t < kr) ? p.V[(size_t)t * p.m + row] : 0.0;
+    }
+    wg.append_r();
+    if (threadIdx.x == 0) s.j1 = s.J[0];
+    __syncthreads();
+    wg.jloop();
+    if (threadIdx.x == 0) {
+        a.ex->restart = (s.k == 0);
+        if (s.k == 0) {
+            p.excl[s.j1] = 1;
+            s.any_excl = 1;
+        }
+    }
+    ctl_store(s, a.ctl);
+}
+
+// Commit the accepted block: P grows by J, snapshot of the added columns of Q.
+__global__ __launch_bounds__(WG) void lg_commit(LgArgs a) {
+    __shared__ WgShared s;
+    ctl_load(s, a.ctl);
+    if (s.k == 0) return;
+    const Prob& p = a.p;
+    if (s.any_excl) {
+        for (int j = threadIdx.x; j < p.n; j += WG) p.excl[j] = 0;
+    }
+    const int m = p.m, r0 = s.nP, k = s.k;
+    for (size_t e = threadIdx.x; e < (size_t)m * k; e += WG) {
+        const int t = (int)(e / m), i = (int)(e % m);
+        p.Qadd[(size_t)t * m + i] = p.Q[(size_t)(r0 + t) * m + i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 0; t < k; ++t) {
+            p.P[r0 + t] = s.J[t];
+            p.pos[s.J[t]] = r0 + t;
+        }
+        s.any_excl = 0;
+        s.nP = r0 + k;
+        s.nPa = r0 + k;
+        s.outer += 1;
+        a.ex->inner_done = 0;
+    }
+    ctl_store(s, a.ctl);
+}
+
+// One inner iteration's bookkeeping: stop test, step length, new iterate,
+// removal set, and the per-column layout of the downdate.  A downdating sweep
+// handles at most RQ positions; further removals of the same iteration (their
+// x is already 0) are swept by the next call before any new step is taken.
+__global__ __launch_bounds__(WG) void lg_inner(LgArgs a) {
+    __shared__ WgShared s;
+    ctl_load(s, a.ctl);
+    LgExtra* ex = a.ex;
+    if (s.k == 0) {
+        if (threadIdx.x == 0) ex->inner_done = 1;
+        return;
+    }
+    Wg wg(a.p, a.prm, s);
+    const Prob& p = a.p;
+    if (ex->pending) {
+        wg.collect_removals();
+    } else {
+        double mn = INFINITY;
+        for (int c = threadIdx.x; c < s.nP; c += WG) mn = fmin(mn, p.ybuf[c]);
+        mn = wg.vmin(mn);
+        if (mn > 0.0) {
+            if (threadIdx.x == 0) ex->inner_done = 1;
+            return;
+        }
+        if (s.inner >= a.prm.max_inner) {
+            if (threadIdx.x == 0) {
+                ex->inner_done = 1;
+                a.ctl->status = LHDM_STATUS_MAXITER;
+            }
+            return;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s.inner += 1;
+        wg.inner_step();
+    }
+    if (threadIdx.x == 0) {
+        ex->pending = s.q > RQ;
+        if (s.q > RQ) s.q = RQ;
+    }
+    __syncthreads();
+    const int q = s.q, nP = s.nP;
+    if (q == 0) {   // nothing to remove (cannot happen after a step: its argmin is removed)
+        if (threadIdx.x == 0) {
+            ex->first = 0;
+            ex->ndown = 0;
+            ex->totrot = 0;
+            ex->pending = 0;
+            ex->inner_done = 0;
+        }
+        ctl_store(s, a.ctl);
+        return;
+    }
+    if (threadIdx.x == 0) {
+        const int first = p.rm[0];
+        ex->first = first;
+        ex->ndown = nP - q - first;
+        // segment t (1..q): kept columns between removal t-1 and removal t carry t rotations
+        int off = 0;
+        for (int t = 1; t <= q; ++t) {
+            const int start_new = p.rm[t - 1] - (t - 1);   // new index of the first kept column after rm[t-1]
+            const int end_old = (t < q) ? p.rm[t] : nP;
+            ex->seg_start[t] = start_new;
+            ex->seg_off[t] = off;
+            off += t * (end_old - p.rm[t - 1] - 1);
+        }
+        ex->totrot = off;
+        ex->inner_done = 0;
+    }
+    __syncthreads();
+    for (int op = p.rm[0] + threadIdx.x; op < nP; op += WG) {
+        int lo = 0, hi = q;   // number of removed positions < op (binary search)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (p.rm[mid] < op) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < q && p.rm[lo] == op) continue;
+        const int L = lo;
+        const int c = op - L;
+        const int idx = c - ex->first;
+        a.ocol[idx] = op;
+        a.lcnt[idx] = L;
+        a.roff[idx] = ex->seg_off[L] + L * (c - ex->seg_start[L]);
+    }
+    ctl_store(s, a.ctl);
+}
+
+__global__ __launch_bounds__(WG) void lg_compact(LgArgs a) {
+    __shared__ WgShared s;
+    ctl_load(s, a.ctl);
+    Wg wg(a.p, a.prm, s);
+    wg.compact();
+    ctl_store(s, a.ctl);
+}
+
+__global__ __launch_bounds__(WG) void lg_copy_x(LgArgs a) {
+    const Ctl* c = a.ctl;
+    if (c->k == 0) return;
+    const Prob& p = a.p;
+    const int nP = c->nP;
+    for (int i = blockIdx.x * WG + threadIdx.x; i < nP; i += gridDim.x * WG) p.x[p.P[i]] = p.ybuf[i];
+}
+
+__global__ __launch_bounds__(WG) void lg_finalize(LgArgs a) {
+    __shared__ WgShared s;
+    ctl_load(s, a.ctl);
+    Wg wg(a.p, a.prm, s);
+    wg.finalize();
+}
+
+// --------------------------------------------------------------------------
+// X^T D on the FP64 matrix cores.
+// X: column-major (ld ldx), rows [0, m), columns [0, ncols).  D: row-major
+// m x 16*NT (Dt).  Each workgroup owns 16 columns; its four waves take
+// interleaved 32-row steps.  MFMA operand mapping (v_mfma_f64_16x16x4f64):
+// A operand lane l = A[l % 16][l / 16], B operand lane l = B[l / 16][l % 16],
+// result lane l register v = D[4 v + l / 16][l % 16].  Lane l feeds column
+// (l & 15) of the tile and row r0 + 8*(l >> 4) + s of the s-th instruction, on
+// both operands, so each lane streams 64 contiguous bytes of its column per step.
+// --------------------------------------------------------------------------
+enum { MODE_PROJ = 0, MODE_DUAL = 1 };
+
+struct ColmatArgs {
+    const double* X;
+    long long ldx;
+    int m, ncols;
+    const double* Dt;
+    int ldd;         // row stride of Dt (>= 16 NT)
+    int nvec;        // vectors in this launch (<= 16 NT)
+    int mode;
+    // MODE_PROJ: out[t * ldo + j]
+    double* out;
+    int ldo;
+    // MODE_DUAL
+    int v0;          // global index of the first vector of this launch
+    int vtot;        // total vectors over all launches
+    int kadd;        // vectors 1..kadd are added directions (subtracted)
+    int exact;       // 1: u2 recomputed from scratch
+    const int* skip; // launch is a no-op when *skip != 0 (may be null)
+    Prob p;
+    int* recomp;
+    int* nrecomp;
+};
+
+template <int NT>
+__global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
+    if (a.skip && *a.skip) return;
+    __shared__ double part[NW][NT][4][64];
+    __shared__ double Ct[16][16 * NT + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j0 = blockIdx.x * 16;
+    const int col = j0 + (lane & 15);
+    const int kk = lane >> 4;
+    const bool colok = col < a.ncols;
+    const double* xc = a.X + (size_t)(colok ? col : 0) * a.ldx;
+    d4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int r0 = wv * 32; r0 < a.m; r0 += 32 * NW) {
+        const int rb = r0 + 8 * kk;
+        double av[8];
+        if (colok && rb + 8 <= a.m) {
+            const double2* src = reinterpret_cast<const double2*>(xc + rb);
+            if ((((uintptr_t)(xc + rb)) & 15) == 0) {
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const double2 v = src[h];
+                    av[2 * h] = v.x;
+                    av[2 * h + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 8; ++s) av[s] = xc[rb + s];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) av[s] = (colok && rb + s < a.m) ? xc[rb + s] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int row = rb + s;
+                const double bv = (row < a.m) ? a.Dt[(size_t)row * a.ldd + t * 16 + (lane & 15)] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[wv][t][v][lane] = acc[t][v];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NT * 4 * 64; idx += WG) {
+        const int t = idx / 256, v = (idx / 64) % 4, l = idx % 64;
+        double sum = part[0][t][v][l];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) sum += part[w][t][v][l];
+        // result layout of v_mfma_f64_16x16x4f64: lane l, register v holds
+        // row (column of X) 4*v + l/16 and column (vector) l%16
+        Ct[4 * v + (l >> 4)][t * 16 + (l & 15)] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x >= 16) return;
+    const int j = j0 + threadIdx.x;
+    if (j >= a.ncols) return;
+    const double* c = Ct[threadIdx.x];
+    if (a.mode == MODE_PROJ) {
+        for (int t = 0; t < a.nvec; ++t) a.out[(size_t)t * a.ldo + j] = c[t];
+        return;
+    }
+    // MODE_DUAL: w_j and the projected-norm update
+    const Prob& p = a.p;
+    int t0 = 0;
+    double u2;
+    if (a.v0 == 0) {
+        p.w[j] = c[0];
+        t0 = 1;
+        u2 = a.exact ? 0.0 : p.u2[j];
+    } else {
+        u2 = p.u2[j];
+    }
+    for (int t = t0; t < a.nvec; ++t) {
+        const int gv = a.v0 + t;
+        const double d = c[t];
+        if (!a.exact && gv <= a.kadd) u2 -= d * d;
+        else u2 += d * d;
+    }
+    if (a.v0 + a.nvec >= a.vtot) {
+        u2 = fmax(u2, 0.0);
+        if (!a.exact && p.pos[j] < 0 && u2 < RECOMP_FRAC * p.an2[j]) {
+            const int slotn = atomicAdd(a.nrecomp, 1);
+            a.recomp[slotn] = j;
+        }
+    }
+    p.u2[j] = u2;
+}
+
+// Vectors of the dual update, row-major m x 64: vector gv of the whole set is
+// r (gv = 0), an added column of Q (1..kadd) or a dropped/trailing column of Q.
+__global__ __launch_bounds__(WG) void lg_gather_dual(LgArgs a, int v0) {
+    const LgExtra* ex = a.ex;
+    if (a.ex->restart) return;
+    const Prob& p = a.p;
+    const int nP = a.ctl->nP, m = p.m;
+    const size_t tot = (size_t)m * 64;
+    for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < tot; e += (size_t)gridDim.x * WG) {
+        const int row = (int)(e / 64), t = (int)(e % 64);
+        const int gv = v0 + t;
+        double v = 0.0;
+        if (gv < ex->nvec) {
+            if (gv == 0) v = p.r[row];
+            else if (ex->exact) v = p.Q[(size_t)(nP + gv - 1) * m + row];
+            else if (gv <= ex->kadd) v = p.Qadd[(size_t)(gv - 1) * m + row];
+            else v = p.Q[(size_t)(nP + gv - 1 - ex->kadd) * m + row];
+        }
+        a.Dt[e] = v;
+    }
+}
+
+// Dt[:, 0] = r, other columns 0 (dual refresh when the solve stops early).
+__global__ __launch_bounds__(WG) void lg_gather_r(LgArgs a) {
+    const size_t tot = (size_t)a.p.m * 64;
+    for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < tot; e += (size_t)gridDim.x * WG)
+        a.Dt[e] = ((e % 64) == 0) ? a.p.r[e / 64] : 0.0;
+}
+
+// Sizes of the dual update (exact mode when the trailing columns are fewer).
+__global__ void lg_dual_plan(LgArgs a) {
+    if (threadIdx.x != 0) return;
+    LgExtra* ex = a.ex;
+    const Ctl* c = a.ctl;
+    if (ex->restart) return;
+    const int m = a.p.m, nP = c->nP, kadd = c->k, ndrop = c->nPa - c->nP;
+    ex->exact = (m - nP) <= kadd + ndrop;
+    ex->kadd = kadd;
+    ex->nvec = 1 + (ex->exact ? (m - nP) : (kadd + ndrop));
+    ex->nrecomp = 0;
+}
+
+// Exact u2 for flagged columns: sum over the trailing columns of Q.
+__global__ __launch_bounds__(WG) void lg_recompute(LgArgs a) {
+    const LgExtra* ex = a.ex;
+    if (ex->restart) return;
+    const int cnt = ex->nrecomp;
+    const Prob& p = a.p;
+    const int lane = threadIdx.x & 63;
+    const int nP = a.ctl->nP;
+    for (int e = blockIdx.x * NW + (threadIdx.x >> 6); e < cnt; e += gridDim.x * NW) {
+        const int j = a.recomp[e];
+        const double* col = p.A + (size_t)j * p.lda;
+        double u2 = 0.0;
+        for (int t = nP; t < p.m; ++t) {
+            const double* q = p.Q + (size_t)t * p.m;
+            double d = 0.0;
+            for (int i = lane; i < p.m; i += 64) d += col[i] * q[i];
+            d = wave_sum(d);
+            u2 += d * d;
+        }
+        if (lane == 0) p.u2[j] = u2;
+    }
+}
+
+// r = b - A_P x_P in two passes: partial sums over column chunks, then a
+// fixed-order reduction.
+__global__ __launch_bounds__(WG) void lg_residual_part(LgArgs a) {
+    const Ctl* c = a.ctl;
+    if (a.ex->restart) return;
+    const Prob& p = a.p;
+    const int nP = c->nP;
+    const int row = blockIdx.x * WG + threadIdx.x;
+    const int chunk = blockIdx.y;
+    if (row >= p.m) return;
+    const int per = (nP + RES_CHUNKS - 1) / RES_CHUNKS;
+    const int c0 = chunk * per, c1 = min(nP, c0 + per);
+    double acc = 0.0;
+    for (int cc = c0; cc < c1; ++cc) {
+        const int j = p.P[cc];
+        acc += p.A[(size_t)j * p.lda + row] * p.x[j];
+    }
+    a.rpart[(size_t)chunk * p.m + row] = acc;
+}
+
+__global__ __launch_bounds__(WG) void lg_residual_sum(LgArgs a) {
+    if (a.ex->restart) return;
+    const Prob& p = a.p;
+    const int row = blockIdx.x * WG + threadIdx.x;
+    if (row >= p.m) return;
+    double acc = 0.0;
+    for (int ch = 0; ch < RES_CHUNKS; ++ch) acc += a.rpart[(size_t)ch * p.m + row];
+    p.r[row] = p.b[row] - acc;
+}
+
+// --------------------------------------------------------------------------
+// Q[:, nP0:m] <- Q[:, nP0:m] (I - V T V^T) with kr reflectors, 16 rows of Q
+// per workgroup.  Pass 1: W = Q_t V on the matrix cores (the four waves split
+// the columns of Q_t), W2 = W T.  Pass 2: Q_t -= W2 V^T, computed transposed
+// so that each store covers 16 consecutive rows of a column of Q.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int kr = ctl->kr, r0 = ctl->nP0, m = p.m, kq = p.kq;
+    if (kr == 0) return;
+    __shared__ double part[NW][4][4][64];
+    __shared__ double Wt[16][KM + 1];
+    __shared__ double W2[16][KM + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * 16;
+    const int ntile = (kr + 15) / 16;
+    const int myrow = i0 + (lane & 15);
+    d4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = r0 + 4 * wv; l0 < m; l0 += 4 * NW) {
+        const int l = l0 + (lane >> 4);
+        const double av = (myrow < m && l < m) ? p.Q[(size_t)l * m + myrow] : 0.0;   // A[M=row][K=l]
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t < ntile) {
+                const int sc = t * 16 + (lane & 15);
+                const double bv = (l < m && sc < kr) ? p.Vt[(size_t)l * kq + sc] : 0.0;   // B[K=l][N=s]
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[wv][t][v][lane] = acc[t][v];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < ntile * 256; idx += WG) {
+        const int t = idx / 256, v = (idx / 64) % 4, l = idx % 64;
+        double sum = part[0][t][v][l];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) sum += part[w][t][v][l];
+        Wt[4 * v + (l >> 4)][t * 16 + (l & 15)] = sum;   // row 4v + l/16, reflector t*16 + l%16
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * kr; e += WG) {
+        const int rr = e / kr, sc = e % kr;
+        double sum = 0.0;
+        for (int l = 0; l <= sc; ++l) sum += Wt[rr][l] * p.T[(size_t)sc * kq + l];
+        W2[rr][sc] = sum;
+    }
+    __syncthreads();
+    for (int c0 = r0 + 16 * wv; c0 < m; c0 += 16 * NW) {
+        d4 o = d4{0.0, 0.0, 0.0, 0.0};
+        const int cc = c0 + (lane & 15);
+        for (int s0 = 0; s0 < kr; s0 += 4) {
+            const int sc = s0 + (lane >> 4);
+            const double av = (sc < kr && cc < m) ? p.V[(size_t)sc * m + cc] : 0.0;   // A[M=col][K=s]
+            const double bv = (sc < kr) ? W2[lane & 15][sc] : 0.0;                    // B[K=s][N=row]
+            o = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, o, 0, 0, 0);
+        }
+        const int rr = i0 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c2 = c0 + 4 * v + (lane >> 4);
+            if (rr < m && c2 < m) p.Q[(size_t)c2 * m + rr] -= o[v];
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// R y = bt[0:nP]: workgroup g solves row block nb-1-g after the blocks below
+// it have published their part of y (device-scope flags with epochs).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
+    const Ctl* ctl = a.ctl;
+    if (ctl->k == 0) return;
+    const Prob& p = a.p;
+    const int nP = ctl->nP;
+    const int nb = (nP + TB - 1) / TB;
+    const int g = blockIdx.x;
+    if (g >= nb) return;
+    const int b = nb - 1 - g;
+    const int r0 = b * TB, nr = min(nP, r0 + TB) - r0;
+    const int tid = threadIdx.x, row = tid & 63, grp = tid >> 6;
+    __shared__ double part[NW][TB];
+    __shared__ double Rd[TB][TB + 1];
+    // diagonal block into LDS (R does not change during the solve)
+    for (int e = tid; e < TB * TB; e += WG) {
+        const int cc = e / TB, rr = e % TB;
+        Rd[rr][cc] = (cc < nr && rr <= cc) ? p.R[(size_t)p.slot[r0 + cc] * p.kc + r0 + rr] : 0.0;
+    }
+    double acc = 0.0;
+    for (int cb = nb - 1; cb > b; --cb) {
+        if (tid == 0) spin_wait(&a.flags_t[cb], epoch, &a.ex->err);
+        __syncthreads();
+        const int c0 = cb * TB, c1 = min(nP, c0 + TB);
+        for (int cc = c0 + grp; cc < c1; cc += NW) {
+            const double yc = load_coherent(&p.ybuf[cc]);
+            if (row < nr) acc += p.R[(size_t)p.slot[cc] * p.kc + r0 + row] * yc;
+        }
+    }
+    part[grp][row] = acc;
+    __syncthreads();
+    if (grp != 0) return;
+    double v = 0.0;
+    if (row < nr) v = p.bt[r0 + row] - (((part[0][row] + part[1][row]) + part[2][row]) + part[3][row]);
+    for (int j = nr - 1; j >= 0; --j) {
+        const double cand = v / Rd[row][row];
+        const double yj = __shfl(cand, j, 64);
+        if (row == j) v = yj;
+        else if (row < j) v -= Rd[row][j] * yj;
+    }
+    if (row < nr) p.ybuf[r0 + row] = v;
+    __threadfence();
+    if (row == 0) store_release(&a.flags_t[b], epoch);
+}
+
+// --------------------------------------------------------------------------
+// Algorithm 5 on R.  Block b (one wave) owns new columns first + 64 b .. +64:
+// it applies, in order, the rotations published by every earlier block to its
+// columns, then generates its own column by column (bottom-up within a column)
+// and publishes them.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
+    const LgExtra* ex = a.ex;
+    const Prob& p = a.p;
+    const int nd = ex->ndown, first = ex->first;
+    const int nb = (nd + GB - 1) / GB;
+    const int b = blockIdx.x;
+    if (b >= nb) return;
+    const int lane = threadIdx.x;
+    const int idx = b * GB + lane;
+    const bool valid = idx < nd;
+    __shared__ double rc[RQ], rs[RQ];
+    double* col = nullptr;
+    if (valid) col = p.R + (size_t)p.slot[a.ocol[idx]] * p.kc;
+    for (int bb = 0; bb < b; ++bb) {
+        if (lane == 0) spin_wait(&a.flags_g[bb], epoch, &a.ex->err);
+        __syncthreads();
+        const int e1 = min(nd, (bb + 1) * GB);
+        for (int e = bb * GB; e < e1; ++e) {
+            const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
+            for (int gg = 0; gg < l2; ++gg) {
+                const double cs = load_coherent(&a.rotbuf[2 * (off + gg)]);
+                const double sn = load_coherent(&a.rotbuf[2 * (off + gg) + 1]);
+                if (valid) {
+                    const int i = occ - gg;
+                    const double x0 = col[i - 1], x1 = col[i];
+                    col[i - 1] = cs * x0 + sn * x1;
+                    col[i] = -sn * x0 + cs * x1;
+                }
+            }
+        }
+    }
+    const int e1 = min(nd, (b + 1) * GB);
+    for (int e = b * GB; e < e1; ++e) {
+        const int t = e - b * GB;
+        const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
+        if (lane == t) {
+            for (int gg = 0; gg < l2; ++gg) {
+                const int i = occ - gg;
+                const double x0 = col[i - 1], x1 = col[i];
+                double cs, sn, rr;
+                givens(x0, x1, cs, sn, rr);
+                col[i - 1] = cs * x0 + sn * x1;
+                col[i] = 0.0;
+                rc[gg] = cs;
+                rs[gg] = sn;
+                a.rotbuf[2 * (off + gg)] = cs;
+                a.rotbuf[2 * (off + gg) + 1] = sn;
+            }
+        }
+        __syncthreads();
+        if (valid && lane > t) {
+            for (int gg = 0; gg < l2; ++gg) {
+                const int i = occ - gg;
+                const double cs = rc[gg], sn = rs[gg];
+                const double x0 = col[i - 1], x1 = col[i];
+                col[i - 1] = cs * x0 + sn * x1;
+                col[i] = -sn * x0 + cs * x1;
+            }
+        }
+        __syncthreads();
+    }
+    __threadfence();
+    if (lane == 0) store_release(&a.flags_g[b], epoch);
+}
+
+// The downdate's rotations applied to the columns of Q (one thread per row of Q)
+// and to bt (one extra thread).
+__global__ __launch_bounds__(WG) void lg_qrot(LgArgs a) {
+    const LgExtra* ex = a.ex;
+    const Prob& p = a.p;
+    const int m = p.m, nd = ex->ndown;
+    const int row = blockIdx.x * WG + threadIdx.x;
+    if (row > m) return;
+    double* base;
+    size_t stride;
+    if (row < m) {
+        base = p.Q + row;
+        stride = (size_t)m;
+    } else {
+        base = p.bt;
+        stride = 1;
+    }
+    for (int e = 0; e < nd; ++e) {
+        const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
+        for (int gg = 0; gg < l2; ++gg) {
+            const int i = occ - gg;
+            const double cs = a.rotbuf[2 * (off + gg)], sn = a.rotbuf[2 * (off + gg) + 1];
+            double* pa = base + (size_t)(i - 1) * stride;
+            double* pb = base + (size_t)i * stride;
+            const double x0 = *pa, x1 = *pb;
+            *pa = cs * x0 + sn * x1;
+            *pb = -sn * x0 + cs * x1;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// host driver
+// --------------------------------------------------------------------------
+struct LargeLayout {
+    size_t slot, ybuf, Vt, Dt, rot, ocol, lcnt, roff, flt, flg, recomp, rpart, ctl, ex, misc, wfall, total;
+};
+
+static LargeLayout large_layout(int m, int n, int kmax) {
+    LargeLayout L;
+    const size_t kc = (size_t)(m < n ? m : n);
+    const size_t kq = (size_t)panel_cols(kmax);
+    size_t o = 0;
+    auto put = [&](size_t& off, size_t bytes) {
+        off = o;
+        o += pad256(bytes);
+    };
+    put(L.flt, sizeof(int) * (kc / TB + 2));   // flag buffers first: fixed offsets for a given kc
+    put(L.flg, sizeof(int) * (kc / GB + 2));
+    put(L.slot, slot_bytes(m, n, kmax));
+    put(L.ybuf, sizeof(double) * kc);
+    put(L.Vt, sizeof(double) * (size_t)m * kq);
+    put(L.Dt, sizeof(double) * (size_t)m * 64);
+    put(L.rot, sizeof(double) * 2 * kc * RQ);
+    put(L.ocol, sizeof(int) * kc);
+    put(L.lcnt, sizeof(int) * kc);
+    put(L.roff, sizeof(int) * kc);
+    put(L.recomp, sizeof(int) * (size_t)n);
+    put(L.rpart, sizeof(double) * (size_t)RES_CHUNKS * m);
+    put(L.ctl, sizeof(Ctl));
+    put(L.ex, sizeof(LgExtra));
+    put(L.misc, 256);
+    put(L.wfall, sizeof(double) * (size_t)n);
+    L.total = o;
+    return L;
+}
+
+static size_t large_workspace_bytes(int m, int n, int kmax) { return large_layout(m, n, kmax).total; }
+
+static int colmat_launch(hipStream_t st, const ColmatArgs& ca) {
+    const int grid = (ca.ncols + 15) / 16;
+    if (grid == 0 || ca.nvec <= 0) return 0;
+    const int nt = (ca.nvec + 15) / 16;
+    if (nt <= 1) hipLaunchKernelGGL(lg_colmat_dot<1>, dim3(grid), dim3(WG), 0, st, ca);
+    else if (nt == 2) hipLaunchKernelGGL(lg_colmat_dot<2>, dim3(grid), dim3(WG), 0, st, ca);
+    else if (nt == 3) hipLaunchKernelGGL(lg_colmat_dot<3>, dim3(grid), dim3(WG), 0, st, ca);
+    else hipLaunchKernelGGL(lg_colmat_dot<4>, dim3(grid), dim3(WG), 0, st, ca);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+// Host copy of the control words read at each decision point.
+struct Mirror {
+    Ctl ctl;
+    int ex_head[16];   // the leading int fields of LgExtra
+};
+
+static int large_solve(hipStream_t st, int m, int n, const double* A, long long lda, const double* b,
+                       const DevParams& prm, double* x, double* w, int* passive, lhdm_info* info, void* ws,
+                       size_t ws_bytes) {
+    const LargeLayout L = large_layout(m, n, prm.kmax);
+    if (ws == nullptr) {
+        int rc = cached_workspace(L.total, &ws);
+        if (rc) return rc;
+        ws_bytes = L.total;
+    }
+    if (ws_bytes < L.total || ((uintptr_t)ws & 255)) return LHDM_EWORKSPACE;
+    char* base = (char*)ws;
+    LgArgs a;
+    Prob& p = a.p;
+    p.A = A;
+    p.lda = lda;
+    p.b = b;
+    p.x = x;
+    p.w = w ? w : (double*)(base + L.wfall);
+    p.passive = passive;
+    p.info = info;
+    carve_slot(p, base + L.slot, m, n, prm.kmax);
+    p.ybuf = (double*)(base + L.ybuf);
+    p.Vt = (double*)(base + L.Vt);
+    a.prm = prm;
+    a.ctl = (Ctl*)(base + L.ctl);
+    a.ex = (LgExtra*)(base + L.ex);
+    a.Dt = (double*)(base + L.Dt);
+    a.rotbuf = (double*)(base + L.rot);
+    a.ocol = (int*)(base + L.ocol);
+    a.lcnt = (int*)(base + L.lcnt);
+    a.roff = (int*)(base + L.roff);
+    a.flags_t = (int*)(base + L.flt);
+    a.flags_g = (int*)(base + L.flg);
+    a.recomp = (int*)(base + L.recomp);
+    a.rpart = (double*)(base + L.rpart);
+    unsigned long long* anmax_bits = (unsigned long long*)(base + L.misc);
+    int* bad = (int*)(base + L.misc + 8);
+
+    // The chained kernels wait for flag == epoch.  Epochs only grow while the
+    // same flag buffers (same workspace, same kc) are reused; anything else
+    // clears the flags and restarts the epochs.
+    static thread_local void* last_ws = nullptr;
+    static thread_local int last_kc = -1;
+    static thread_local int ep_t = 0, ep_g = 0;
+    if (last_ws != ws || last_kc != p.kc || ep_t > (1 << 30) || ep_g > (1 << 30)) {
+        HIPCHK(hipMemsetAsync(base + L.flt, 0, pad256(sizeof(int) * (p.kc / TB + 2)), st));
+        HIPCHK(hipMemsetAsync(base + L.flg, 0, pad256(sizeof(int) * (p.kc / GB + 2)), st));
+        ep_t = ep_g = 0;
+        last_ws = ws;
+        last_kc = p.kc;
+    }
+    static thread_local Mirror* mir = nullptr;
+    if (!mir) HIPCHK(hipHostMalloc((void**)&mir, sizeof(Mirror), hipHostMallocDefault));
+
+    auto read_ctl = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(&mir->ctl, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(mir->ex_head, a.ex, sizeof(mir->ex_head), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        kprof_drain();
+        const LgExtra* hx = reinterpret_cast<const LgExtra*>(mir->ex_head);
+        if (hx->err) return LHDM_EHIP;
+        return 0;
+    };
+    auto ex_h = [&]() { return reinterpret_cast<const LgExtra*>(mir->ex_head); };
+
+    HIPCHK(hipMemsetAsync(base + L.misc, 0, 256, st));
+    HIPCHK(hipMemsetAsync(a.ex, 0, sizeof(LgExtra), st));
+    hipLaunchKernelGGL(lg_init_cols, dim3((n + NW - 1) / NW), dim3(WG), 0, st, a, anmax_bits, bad);
+    hipLaunchKernelGGL(lg_fill_identity, dim3(1024), dim3(WG), 0, st, p.Q, m);
+    hipLaunchKernelGGL(lg_init_ctl, dim3(1), dim3(WG), 0, st, a, (const unsigned long long*)anmax_bits,
+                       (const int*)bad);
+    HIPCHK(hipGetLastError());
+    int rc = read_ctl();
+    if (rc) return rc;
+
+    const int ggrid = 256;
+    const int tgrid = (p.kc + TB - 1) / TB;
+    const int rgrid = (m + WG - 1) / WG;
+    bool stop = mir->ctl.status != LHDM_STATUS_OK;
+    while (!stop) {
+        hipLaunchKernelGGL(lg_select, dim3(1), dim3(WG), 0, st, a);
+        HIPCHK(hipGetLastError());
+        if ((rc = read_ctl())) return rc;
+        if (mir->ctl.done) break;
+        // candidate projection G = Q^T A_J
+        hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, st, a);
+        {
+            ColmatArgs ca{};
+            ca.X = p.Q;
+            ca.ldx = m;
+            ca.m = m;
+            ca.ncols = m;
+            ca.Dt = a.Dt;
+            ca.ldd = 64;
+            ca.mode = MODE_PROJ;
+            ca.out = p.G;
+            ca.ldo = m;
+            ca.p = p;
+            ca.nvec = mir->ctl.ncol;
+            if ((rc = colmat_launch(st, ca))) return rc;
+        }
+        hipLaunchKernelGGL(lg_panel, dim3(1), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_qupdate, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, st, a);
+        ++ep_t;
+        hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t);
+        HIPCHK(hipGetLastError());
+        bool restart = false;
+        while (true) {
+            hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, st, a);
+            HIPCHK(hipGetLastError());
+            if ((rc = read_ctl())) return rc;
+            if (ex_h()->restart) {
+                restart = true;
+                break;
+            }
+            if (ex_h()->inner_done) {
+                if (mir->ctl.status == LHDM_STATUS_MAXITER) stop = true;
+                break;
+            }
+            ++ep_g;
+            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ep_g);
+            hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + WG - 1) / WG), dim3(WG), 0, st, a);
+            hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a);
+            ++ep_t;
+            hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t);
+            HIPCHK(hipGetLastError());
+        }
+        if (restart) continue;
+        if (!stop) hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_residual_sum, dim3(rgrid), dim3(WG), 0, st, a);
+        HIPCHK(hipGetLastError());
+        if (stop) break;
+        // dual w = A^T r fused with the projected-norm update
+        const int nP = mir->ctl.nP, kadd = mir->ctl.k, ndrop = mir->ctl.nPa - mir->ctl.nP;
+        const int exact = (m - nP) <= kadd + ndrop;
+        const int nvec = 1 + (exact ? (m - nP) : (kadd + ndrop));
+        hipLaunchKernelGGL(lg_dual_plan, dim3(1), dim3(64), 0, st, a);
+        for (int v0 = 0; v0 < nvec; v0 += 64) {
+            hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, st, a, v0);
+            ColmatArgs ca{};
+            ca.X = A;
+            ca.ldx = lda;
+            ca.m = m;
+            ca.ncols = n;
+            ca.Dt = a.Dt;
+            ca.ldd = 64;
+            ca.mode = MODE_DUAL;
+            ca.nvec = std::min(64, nvec - v0);
+            ca.v0 = v0;
+            ca.vtot = nvec;
+            ca.kadd = kadd;
+            ca.exact = exact;
+            ca.p = p;
+            ca.recomp = a.recomp;
+            ca.nrecomp = &a.ex->nrecomp;
+            // algorithmic bytes: A once, the vector block, w written, u2 read and written
+            const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
+            const int ev = kprof_begin(st);
+            if ((rc = colmat_launch(st, ca))) return rc;
+            kprof_end(st, ev, bytes);
+        }
+        hipLaunchKernelGGL(lg_recompute, dim3(64), dim3(WG), 0, st, a);
+        HIPCHK(hipGetLastError());
+    }
+    if (stop && mir->ctl.status == LHDM_STATUS_MAXITER) {
+        // x is the last feasible iterate: refresh w for it
+        hipLaunchKernelGGL(lg_gather_r, dim3(ggrid), dim3(WG), 0, st, a);
+        ColmatArgs ca{};
+        ca.X = A;
+        ca.ldx = lda;
+        ca.m = m;
+        ca.ncols = n;
+        ca.Dt = a.Dt;
+        ca.ldd = 64;
+        ca.mode = MODE_PROJ;
+        ca.out = p.w;
+        ca.ldo = n;
+        ca.nvec = 1;
+        ca.p = p;
+        if ((rc = colmat_launch(st, ca))) return rc;
+    }
+    hipLaunchKernelGGL(lg_finalize, dim3(1), dim3(WG), 0, st, a);
+    HIPCHK(hipGetLastError());
+    if ((rc = read_ctl())) return rc;
+    return 0;
 }
 
 }  // namespace lhdm

@@ -12,19 +12,25 @@
 
 namespace lhdm {
 
-struct WgShared {
+// Control state of one solve.  The workgroup engine keeps it in LDS for the
+// whole solve; the large-instance engine keeps it in global memory between
+// launches and copies it into LDS inside each single-workgroup kernel.
+struct Ctl {
+    double tol_w, anmax, bnorm;
+    int nP, nP0, nPa, status, outer, inner, jdrops, ncol, k, kr, done, q, any_excl, j1;
+    int J[KM];
+    double tau[KM];          // Householder scalars of the panel
+    double beta[KM];         // diagonal of the new R block
+};
+
+struct WgShared : Ctl {
     double rd[NW];
     int ri[NW];
     double mr[KM + 1][NW];   // per-wave partial sums of a vector of dot products
     double vec[KM + 1];      // reduced vector of dot products
-    double tau[KM];          // Householder scalars of the panel
-    double beta[KM];         // diagonal of the new R block
     double y[YMAX];          // least-squares solution by passive position
     double c[YMAX];          // right-hand side being reduced by the triangular solve
     int cnt[WG];             // prefix counts for compaction
-    double tol_w, anmax, bnorm;
-    int nP, nP0, nPa, status, outer, inner, jdrops, ncol, k, done, q, any_excl;
-    int J[KM];
 };
 
 struct Wg {
@@ -32,9 +38,11 @@ struct Wg {
     const DevParams& prm;
     WgShared& s;
     int tid, lane, wid;
+    double* yv;   // least-squares solution by position: LDS (workgroup engine) or global
 
     __device__ Wg(Prob& p_, const DevParams& prm_, WgShared& s_)
-        : p(p_), prm(prm_), s(s_), tid(threadIdx.x), lane(threadIdx.x & 63), wid(threadIdx.x >> 6) {}
+        : p(p_), prm(prm_), s(s_), tid(threadIdx.x), lane(threadIdx.x & 63), wid(threadIdx.x >> 6),
+          yv(p_.ybuf ? p_.ybuf : s_.y) {}
 
     // ---------------- workgroup reductions ----------------
     __device__ double sum(double v) {
@@ -112,7 +120,7 @@ struct Wg {
     }
 
     __device__ double& Qat(int i, int j) { return p.Q[(size_t)j * p.m + i]; }
-    __device__ double& Rat(int i, int j) { return p.R[(size_t)j * p.kc + i]; }
+    __device__ double& Rat(int i, int j) { return p.R[(size_t)p.slot[j] * p.kc + i]; }
     __device__ const double* Acol(int j) { return p.A + (size_t)j * p.lda; }
 
     // ---------------- a0: initialisation (Algorithm 3, first lines) ----------------
@@ -153,6 +161,7 @@ struct Wg {
         bad = imax(bad);
         const size_t mm = (size_t)m * m;
         for (size_t e = tid; e < mm; e += WG) p.Q[e] = ((e % m) == (e / m)) ? 1.0 : 0.0;
+        for (int c = tid; c < p.kc; c += WG) p.slot[c] = c;
         if (tid == 0) {
             s.anmax = sqrt(anmax);
             s.bnorm = sqrt(bb);
@@ -314,7 +323,7 @@ struct Wg {
     // extra column (Algorithm 4); G keeps the reflectors below the diagonal,
     // s.beta the new diagonal of R, s.tau the reflector scalars.
     __device__ void panel_qr() {
-        const int m = p.m, k = s.k, r0 = s.nP;
+        const int m = p.m, k = s.kr, r0 = s.nP;
         for (int t = 0; t < k; ++t) {
             const int rt = r0 + t;
             double* g = p.G + (size_t)t * m;
@@ -358,7 +367,7 @@ struct Wg {
     // Explicit V (zeros above the unit diagonal, rows >= n_P) and the compact-WY
     // factor T with H_0 H_1 ... H_{k-1} = I - V T V^T (forward, columnwise).
     __device__ void form_wy() {
-        const int m = p.m, k = s.k, r0 = s.nP, kq = p.kq;
+        const int m = p.m, k = s.kr, r0 = s.nP, kq = p.kq;
         for (int t = 0; t < k; ++t) {
             const double* g = p.G + (size_t)t * m;
             double* v = p.V + (size_t)t * m;
@@ -401,7 +410,7 @@ struct Wg {
 
     // New R columns: [Q_P^T a_J ; R_JJ].
     __device__ void append_r() {
-        const int m = p.m, k = s.k, r0 = s.nP;
+        const int m = p.m, k = s.kr, r0 = s.nP;
         for (int t = 0; t < k; ++t) {
             const double* g = p.G + (size_t)t * m;
             for (int i = tid; i < r0 + t + 1; i += WG) {
@@ -416,7 +425,7 @@ struct Wg {
 
     // Q[:, n_P:m] <- Q[:, n_P:m] (I - V T V^T)  (rows of Q are independent).
     __device__ void update_q() {
-        const int m = p.m, k = s.k, r0 = s.nP, kq = p.kq;
+        const int m = p.m, k = s.kr, r0 = s.nP, kq = p.kq;
         for (int i = tid; i < m; i += WG) {
             double wrow[KM];
 #pragma unroll
@@ -451,7 +460,7 @@ struct Wg {
     __device__ void jloop() {
         if (tid == 0) {
             const int r0 = s.nP;
-            int k = s.k;
+            int k = s.kr;
             while (k > 0) {
                 double yy[KM];
                 for (int i = 0; i < k; ++i) yy[i] = p.bt[r0 + i];
@@ -478,7 +487,7 @@ struct Wg {
         for (int j = nP - 1; j >= 0; --j) {
             __syncthreads();
             const double yj = s.c[j] / Rat(j, j);
-            if (tid == 0) s.y[j] = yj;
+            if (tid == 0) yv[j] = yj;
             for (int i = tid; i < j; i += WG) s.c[i] -= yj * Rat(i, j);
         }
         __syncthreads();
@@ -491,7 +500,7 @@ struct Wg {
         const int nP = s.nP;
         double al = INFINITY;
         for (int c = tid; c < nP; c += WG) {
-            const double yc = s.y[c];
+            const double yc = yv[c];
             if (yc <= 0.0) {
                 const double xc = p.x[p.P[c]];
                 al = fmin(al, xc / (xc - yc));
@@ -500,18 +509,25 @@ struct Wg {
         al = vmin(al);
         const int chunk = (nP + WG - 1) / WG;
         const int c0 = tid * chunk, c1 = min(nP, c0 + chunk);
-        int mine = 0;
         for (int c = c0; c < c1; ++c) {
             const int j = p.P[c];
-            const double xc = p.x[j], yc = s.y[c];
+            const double xc = p.x[j], yc = yv[c];
             double xn = xc + al * (yc - xc);
             if (yc <= 0.0 && xc / (xc - yc) == al) xn = 0.0;
-            if (xn <= 0.0) {
-                xn = 0.0;
-                ++mine;
-            }
+            if (xn <= 0.0) xn = 0.0;
             p.x[j] = xn;
         }
+        collect_removals();
+    }
+
+    // p.rm[0..s.q) = ascending passive positions whose x is <= 0.
+    __device__ void collect_removals() {
+        const int nP = s.nP;
+        const int chunk = (nP + WG - 1) / WG;
+        const int c0 = tid * chunk, c1 = min(nP, c0 + chunk);
+        int mine = 0;
+        for (int c = c0; c < c1; ++c)
+            if (p.x[p.P[c]] <= 0.0) ++mine;
         s.cnt[tid] = mine;
         __syncthreads();
         if (tid == 0) {
@@ -594,25 +610,32 @@ struct Wg {
                     Qat(row, i) = -sn * a + cs * bb;
                 }
             }
-            // move the finished column to its new position
-            if (c != oc)
-                for (int i = tid; i <= c; i += WG) Rat(i, c) = Rat(i, oc);
             __syncthreads();
         }
-        // compact the passive list
+        compact();
+    }
+
+    // Drop the removed positions from P; their R slots move behind the kept ones
+    // (slot stays a permutation, free slots at [n_P, kc)).
+    __device__ void compact() {
+        const int q = s.q, nP = s.nP;
         if (tid == 0) {
             int w = 0, t = 0;
             for (int c = 0; c < nP; ++c) {
                 const int j = p.P[c];
+                const int sl = p.slot[c];
                 if (t < q && p.rm[t] == c) {
                     p.pos[j] = -1;
+                    p.rm[t] = sl;          // reuse rm to hold the freed slots
                     ++t;
                     continue;
                 }
                 p.P[w] = j;
+                p.slot[w] = sl;
                 p.pos[j] = w;
                 ++w;
             }
+            for (int t2 = 0; t2 < q; ++t2) p.slot[w + t2] = p.rm[t2];
             s.nP = w;
         }
         __syncthreads();
@@ -623,7 +646,7 @@ struct Wg {
         const int m = p.m, nP = s.nP;
         for (int i = tid; i < m; i += WG) {
             double acc = p.b[i];
-            for (int c = 0; c < nP; ++c) acc -= p.A[(size_t)p.P[c] * p.lda + i] * s.y[c];
+            for (int c = 0; c < nP; ++c) acc -= p.A[(size_t)p.P[c] * p.lda + i] * yv[c];
             p.r[i] = acc;
         }
         __syncthreads();
@@ -755,8 +778,10 @@ struct Wg {
                 if (tid == 0) s.k = 1;
                 __syncthreads();
             }
+            if (tid == 0) s.kr = s.k;
+            __syncthreads();
             panel_qr();
-            if (s.k > 1) form_wy();
+            if (s.kr > 1) form_wy();
             else {
                 // one reflector: V = [0; 1; v], T = tau
                 const int m = p.m, r0 = s.nP;
@@ -800,7 +825,7 @@ struct Wg {
             bool stop = false;
             while (true) {
                 double mn = INFINITY;
-                for (int c = tid; c < s.nP; c += WG) mn = fmin(mn, s.y[c]);
+                for (int c = tid; c < s.nP; c += WG) mn = fmin(mn, yv[c]);
                 mn = vmin(mn);
                 if (mn > 0.0) break;
                 if (s.inner >= prm.max_inner) {
@@ -819,7 +844,7 @@ struct Wg {
                 refresh_dual();
                 break;
             }
-            for (int c = tid; c < s.nP; c += WG) p.x[p.P[c]] = s.y[c];
+            for (int c = tid; c < s.nP; c += WG) p.x[p.P[c]] = yv[c];
             __syncthreads();
             residual();
             dual_and_norms(k);

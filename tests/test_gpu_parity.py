@@ -57,7 +57,7 @@ def _check(res, x_o, info_o, *, same_path=True, unique=True, tag=""):
     least-squares coefficient; its sign, and so the decisions of the feasibility
     loops, is then set by rounding and legitimately differs between summation
     orders.  Path identity (ordered P, iteration counters) is therefore required
-    only when the oracle's solution is well separated from zero."""
+    only when both solutions are well separated from zero."""
     x = res.x.cpu().numpy()
     print(f"[{tag}] gpu info {res.info} | oracle outer={info_o['outer_iters']} inner={info_o['inner_iters']} "
           f"jd={info_o['jloop_drops']} nP={info_o['n_passive']}", flush=True)
@@ -72,7 +72,11 @@ def _check(res, x_o, info_o, *, same_path=True, unique=True, tag=""):
         assert _supp(x) == _supp(x_o), tag
         assert _rel(x, x_o) <= XTOL, (tag, _rel(x, x_o))
     Po = info_o["passive"]
-    separated = len(Po) == 0 or float(np.min(x_o[Po])) > SEP * float(np.abs(x_o).max())
+
+    def sep(xx, PP):
+        return len(PP) == 0 or float(np.min(xx[PP])) > SEP * float(np.abs(xx).max())
+
+    separated = sep(x_o, Po) and sep(x, P)
     if same_path and separated:
         assert P == Po, tag
         for key in ("outer_iters", "inner_iters", "jloop_drops"):
@@ -80,16 +84,34 @@ def _check(res, x_o, info_o, *, same_path=True, unique=True, tag=""):
     return separated
 
 
-@pytest.mark.parametrize("seed", list(range(1000, 1016)))
-def test_c1_lhdm_and_lh(lhdm, seed):
+ENGINES = ["workgroup", "device"]
+
+
+def _lh(lhdm, A, b, engine):
+    # plain LH: the C-ABI lh_solve (automatic engine) or LHDM with kmax = 1 on a forced engine
+    if engine == "auto":
+        return lhdm.lh_solve(A, b)
+    return lhdm.solve(A, b, kmax=1, engine=engine)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("seed", list(range(1000, 1012)))
+def test_c1_lhdm_and_lh(lhdm, seed, engine):
     inst = make_c1(seed)
     A, b = _dev(inst.A, inst.b)
     xo, io = oracle.oracle_lhdm(inst.A, inst.b)
-    _check(lhdm.solve(A, b), xo, io, tag=f"c1-lhdm-{seed}")
+    _check(lhdm.solve(A, b, engine=engine), xo, io, tag=f"c1-lhdm-{seed}-{engine}")
     xo, io = oracle.oracle_lh(inst.A, inst.b)
-    _check(lhdm.lh_solve(A, b), xo, io, tag=f"c1-lh-{seed}")
+    _check(_lh(lhdm, A, b, engine), xo, io, tag=f"c1-lh-{seed}-{engine}")
     # planted recovery
-    np.testing.assert_allclose(lhdm.solve(A, b).x.cpu().numpy(), inst.x_true, atol=1e-12)
+    np.testing.assert_allclose(lhdm.solve(A, b, engine=engine).x.cpu().numpy(), inst.x_true, atol=1e-12)
+
+
+def test_c1_lh_entry_point(lhdm):
+    inst = make_c1(1000)
+    A, b = _dev(inst.A, inst.b)
+    xo, io = oracle.oracle_lh(inst.A, inst.b)
+    _check(lhdm.lh_solve(A, b), xo, io, tag="c1-lh-abi")
 
 
 RAGGED = [
@@ -105,34 +127,82 @@ RAGGED = [
 ]
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("case", RAGGED, ids=[f"{c[0]}x{c[1]}-{c[3]}" for c in RAGGED])
-def test_ragged_unique_instances(lhdm, case):
+def test_ragged_unique_instances(lhdm, case, engine):
     m, n, k, kind, noise, seed = case
     inst = make_small(m, n, k, seed, kind=kind, noise_std=noise)
     A, b = _dev(inst.A, inst.b)
     for delta in (0.9, 0.5, 0.2):
         xo, io = oracle.oracle_lhdm(inst.A, inst.b, delta=delta)
-        _check(lhdm.solve(A, b, delta=delta), xo, io, tag=f"{m}x{n}-d{delta}")
+        _check(lhdm.solve(A, b, delta=delta, engine=engine), xo, io, tag=f"{m}x{n}-d{delta}-{engine}")
     xo, io = oracle.oracle_lh(inst.A, inst.b)
-    _check(lhdm.lh_solve(A, b), xo, io, tag=f"{m}x{n}-lh")
+    _check(_lh(lhdm, A, b, engine), xo, io, tag=f"{m}x{n}-lh-{engine}")
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("delta", [0.2, 0.5, 0.8])
-def test_scaled_c3_delta_sweep(lhdm, delta):
+def test_scaled_c3_delta_sweep(lhdm, delta, engine):
     # the large Gaussian family scaled down (k/n kept): zero-residual, non-unique
     # minimiser; both sides are compared on their path and the KKT conditions
     inst = make_c3(3000, m=160, n=640, k=32)
     A, b = _dev(inst.A, inst.b)
     xo, io = oracle.oracle_lhdm(inst.A, inst.b, delta=delta)
-    _check(lhdm.solve(A, b, delta=delta), xo, io, unique=False, same_path=True, tag=f"c3s-d{delta}")
+    _check(lhdm.solve(A, b, delta=delta, engine=engine), xo, io, unique=False, same_path=True,
+           tag=f"c3s-d{delta}-{engine}")
 
 
-def test_kmax_variants(lhdm):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_kmax_variants(lhdm, engine):
     inst = make_small(90, 260, 25, 11, kind="uniform", noise_std=1e-2)
     A, b = _dev(inst.A, inst.b)
     for kmax in (1, 2, 5, 17, 64):
         xo, io = oracle.oracle_lhdm(inst.A, inst.b, kmax=kmax)
-        _check(lhdm.solve(A, b, kmax=kmax), xo, io, tag=f"kmax{kmax}")
+        _check(lhdm.solve(A, b, kmax=kmax, engine=engine), xo, io, tag=f"kmax{kmax}-{engine}")
+
+
+def test_device_engine_multiblock_sizes(lhdm):
+    # sizes spanning several row blocks of the chained triangular solve and
+    # several column blocks of the chained downdate, with ragged tails
+    for (m, n, k, seed) in ((333, 700, 60, 31), (517, 1100, 90, 32)):
+        inst = make_small(m, n, k, seed, kind="uniform", noise_std=1e-2)
+        A, b = _dev(inst.A, inst.b)
+        xo, io = oracle.oracle_lhdm(inst.A, inst.b)
+        _check(lhdm.solve(A, b, engine="device"), xo, io, same_path=False, tag=f"dev-{m}x{n}")
+        xo, io = oracle.oracle_lh(inst.A, inst.b)
+        _check(lhdm.solve(A, b, kmax=1, engine="device"), xo, io, same_path=False, tag=f"dev-lh-{m}x{n}")
+
+
+def test_c2_full_size(lhdm):
+    # the 1024 x 4096 unit-column Gaussian instance, noiseless 128-sparse: unique
+    from workloads import make_c2
+    inst = make_c2(2000)
+    A, b = _dev(inst.A, inst.b)
+    xo, io = oracle.oracle_lhdm(inst.A, inst.b)
+    r = lhdm.solve(A, b)
+    _check(r, xo, io, tag="c2-lhdm")
+    np.testing.assert_allclose(r.x.cpu().numpy(), inst.x_true, atol=1e-10)
+    xo, io = oracle.oracle_lh(inst.A, inst.b)
+    _check(lhdm.lh_solve(A, b), xo, io, tag="c2-lh")
+
+
+@pytest.mark.parametrize("delta", [0.8])
+def test_c3_full_size_properties(lhdm, delta):
+    # 4096 x 16384: KKT at 1e-9, feasibility, and the final passive least-squares
+    # subproblem re-solved by LAPACK on the returned passive set
+    inst = make_c3(3000)
+    A, b = _dev(inst.A, inst.b)
+    for name, res in (("lhdm", lhdm.solve(A, b, delta=delta)),):
+        print(f"[c3-{name}] {res.info}", flush=True)
+        assert res.info["status"] == 0
+        assert res.info["kkt_residual"] <= KKT
+        x = res.x.cpu().numpy()
+        P = _passive(res)
+        assert (x >= 0).all() and all(x[j] > 0 for j in P)
+        rep = oracle.kkt_report(inst.A, inst.b, x)
+        assert rep["kkt"] <= KKT
+        xs, *_ = np.linalg.lstsq(inst.A[:, P], inst.b, rcond=None)
+        assert np.abs(xs - x[P]).max() <= 1e-8 * np.abs(xs).max()
 
 
 def test_batched_c4_subset(lhdm):
