@@ -64,6 +64,7 @@ struct Prob {
                        //      slots [n_P, kc) are the free ones)
     double* ybuf;      // kc : least-squares solution by position (large-instance engine)
     double* Vt;        // m * kq : V stored row-major (large-instance engine)
+    int* itmp;         // 2 * kc : scratch of the passive-set compaction
 };
 
 // Bytes of one instance's workspace slice (each array padded to 256 bytes).
@@ -83,6 +84,7 @@ __host__ __device__ inline size_t slot_bytes(int m, int n, int kmax) {
     s += pad256(sizeof(double) * kq * kq);             // T
     s += pad256(sizeof(double) * 2 * kc);              // rot
     s += 3 * pad256(sizeof(int) * kc);                 // P, rm, slot
+    s += pad256(sizeof(int) * 2 * kc);                 // itmp
     s += 2 * pad256(sizeof(int) * (size_t)n);          // pos, excl
     return s;
 }
@@ -111,6 +113,7 @@ __host__ __device__ inline void carve_slot(Prob& p, char* base, int m, int n, in
     p.P = (int*)take(sizeof(int) * kc);
     p.rm = (int*)take(sizeof(int) * kc);
     p.slot = (int*)take(sizeof(int) * kc);
+    p.itmp = (int*)take(sizeof(int) * 2 * kc);
     p.pos = (int*)take(sizeof(int) * n);
     p.excl = (int*)take(sizeof(int) * n);
     p.ybuf = nullptr;

@@ -63,6 +63,9 @@ struct LgArgs {
     int* flags_g;     // kc/GB + 1 epochs of the downdate
     int* recomp;      // n: columns whose projected norm is recomputed exactly
     double* rpart;    // RES_CHUNKS * m residual partial sums
+    double* gpart;    // partial Gram matrices (ceil(m / 256) blocks of 64 x 64)
+    double* selv;     // 3 * NSEL partial maxima of the selection
+    int* seli;        // NSEL partial argmax indices
 };
 
 // --------------------------------------------------------------------------
@@ -83,23 +86,30 @@ __device__ inline void ctl_store(const WgShared& s, Ctl* g) {
     __syncthreads();
 }
 
-__device__ inline int load_acquire(const int* f) {
-    return __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Cross-workgroup hand-off in the chained kernels.  Data and flags move with
+// relaxed system-scope accesses (sc0 sc1: they bypass the non-coherent caches,
+// no whole-cache writeback or invalidate is issued); the producer waits for its
+// data stores to complete before it stores the flag.
+__device__ inline double sys_ld(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline void sys_st(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline int sys_ldi(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM); }
+__device__ inline void sys_sti(int* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM); }
+
+// Publish: all of this wave's earlier stores complete, then the flag.
+__device__ inline void publish(int* f, int epoch) {
+    __builtin_amdgcn_s_waitcnt(0);
+    sys_sti(f, epoch);
 }
 
-__device__ inline void store_release(int* f, int v) {
-    __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline double load_coherent(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wait until *f == epoch; gives up (and flags an error) after SPIN_LIMIT polls so
-// that every wave always exits.
+// Wave-uniform wait until *f == epoch; gives up (and flags an error) after
+// SPIN_LIMIT polls so that every wave always exits.
 __device__ inline void spin_wait(const int* f, int epoch, int* err) {
     long long it = 0;
-    while (load_acquire(f) != epoch) {
+    while (sys_ldi(f) != epoch) {
         if (++it > SPIN_LIMIT) {
             atomicExch(err, 1);
             break;
@@ -178,11 +188,153 @@ __global__ __launch_bounds__(WG) void lg_init_ctl(LgArgs a, const unsigned long 
 // --------------------------------------------------------------------------
 // single-workgroup steps
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void lg_select(LgArgs a) {
+// Selection, pass 1: per-workgroup partial maxima over a slice of the columns
+// (max_Z w, max_Z u, best eligible (w, index)).
+constexpr int NSEL = 64;   // workgroups of the first selection pass
+
+__global__ __launch_bounds__(WG) void lg_sel_part(LgArgs a, double* pv, int* pi) {
+    const Prob& p = a.p;
+    __shared__ double sd[3][NW];
+    __shared__ int si[NW];
+    const int n = p.n, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int per = (n + NSEL - 1) / NSEL;
+    const int j0 = blockIdx.x * per, j1 = min(n, j0 + per);
+    double mwz = -INFINITY, mu = 0.0, bv = -INFINITY;
+    int bi = INT_MAX;
+    for (int j = j0 + threadIdx.x; j < j1; j += WG) {
+        if (p.pos[j] >= 0) continue;
+        const double wj = p.w[j];
+        const double u = sqrt(fmax(p.u2[j], 0.0));
+        mwz = fmax(mwz, wj);
+        mu = fmax(mu, u);
+        if (!p.excl[j] && u > DEP_TOL * sqrt(p.an2[j]) && better(wj, j, bv, bi)) {
+            bv = wj;
+            bi = j;
+        }
+    }
+    mwz = wave_max(mwz);
+    mu = wave_max(mu);
+    wave_argmax(bv, bi);
+    if (lane == 0) {
+        sd[0][wv] = mwz;
+        sd[1][wv] = mu;
+        sd[2][wv] = bv;
+        si[wv] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NW; ++w) {
+            mwz = fmax(mwz, sd[0][w]);
+            mu = fmax(mu, sd[1][w]);
+            if (better(sd[2][w], si[w], bv, bi)) {
+                bv = sd[2][w];
+                bi = si[w];
+            }
+        }
+        mwz = fmax(sd[0][0], mwz);
+        mu = fmax(sd[1][0], mu);
+        if (better(sd[2][0], si[0], bv, bi)) {
+            bv = sd[2][0];
+            bi = si[0];
+        }
+        pv[3 * blockIdx.x + 0] = mwz;
+        pv[3 * blockIdx.x + 1] = mu;
+        pv[3 * blockIdx.x + 2] = bv;
+        pi[blockIdx.x] = bi;
+    }
+}
+
+// Selection, pass 2 (one workgroup): termination test (a1) and Deviation
+// Maximization's candidate list (a2): the columns passing both thresholds are
+// collected in LDS and the first kmax - 1 in (w desc, index asc) order are
+// extracted.  More than CAND_CAP candidates falls back to passes over memory.
+constexpr int CAND_CAP = 2048;
+
+__global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, const int* pi) {
     __shared__ WgShared s;
+    __shared__ double cw[CAND_CAP];
+    __shared__ int ci[CAND_CAP];
+    __shared__ int ccount;
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
-    wg.select();
+    const Prob& p = a.p;
+    const DevParams& prm = a.prm;
+    double mwz = -INFINITY, mu = 0.0, bv = -INFINITY;
+    int bi = INT_MAX;
+    for (int g = threadIdx.x; g < NSEL; g += WG) {
+        mwz = fmax(mwz, pv[3 * g]);
+        mu = fmax(mu, pv[3 * g + 1]);
+        if (better(pv[3 * g + 2], pi[g], bv, bi)) {
+            bv = pv[3 * g + 2];
+            bi = pi[g];
+        }
+    }
+    mwz = wg.vmax(mwz);
+    mu = wg.vmax(mu);
+    wg.argmax(bv, bi);
+    const int cap = p.m - s.nP;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s.done = 0;
+        s.ncol = 1;
+        s.J[0] = bi;
+        s.nP0 = s.nP;
+        ccount = 0;
+        if (mwz == -INFINITY || mwz <= s.tol_w) {
+            s.done = 1;
+        } else if (bi == INT_MAX || bv <= s.tol_w) {
+            s.done = 1;
+            s.status = LHDM_STATUS_RANK;
+        } else if (s.outer >= prm.max_outer) {
+            s.done = 1;
+            s.status = LHDM_STATUS_MAXITER;
+        }
+    }
+    __syncthreads();
+    if (!(s.done || prm.lh || prm.kmax <= 1 || cap <= 1)) {
+        const double tw = prm.tau1 * bv, tu = prm.tau2 * mu;
+        for (int j = threadIdx.x; j < p.n; j += WG) {
+            if (p.pos[j] >= 0 || p.excl[j] || j == bi) continue;
+            const double wj = p.w[j];
+            if (!(wj >= tw)) continue;
+            const double u = sqrt(fmax(p.u2[j], 0.0));
+            if (!(u >= tu) || !(u > DEP_TOL * sqrt(p.an2[j]))) continue;
+            const int slotc = atomicAdd(&ccount, 1);
+            if (slotc < CAND_CAP) {
+                cw[slotc] = wj;
+                ci[slotc] = j;
+            }
+        }
+        __syncthreads();
+        const int cnt = ccount;
+        if (cnt > CAND_CAP) {
+            wg.select();   // rare: many candidates -> passes over memory
+        } else {
+            double pvv = bv;
+            int pii = bi;
+            for (int t = 1; t < prm.kmax; ++t) {
+                double cv = -INFINITY;
+                int cj = INT_MAX;
+                for (int e = threadIdx.x; e < cnt; e += WG) {
+                    const double wj = cw[e];
+                    const int j = ci[e];
+                    if (!(wj < pvv || (wj == pvv && j > pii))) continue;
+                    if (better(wj, j, cv, cj)) {
+                        cv = wj;
+                        cj = j;
+                    }
+                }
+                wg.argmax(cv, cj);
+                if (cj == INT_MAX) break;
+                if (threadIdx.x == 0) {
+                    s.J[t] = cj;
+                    s.ncol = t + 1;
+                }
+                pvv = cv;
+                pii = cj;
+            }
+        }
+    }
     if (threadIdx.x == 0) s.nP0 = s.nP;
     ctl_store(s, a.ctl);
 }
@@ -198,15 +350,73 @@ __global__ __launch_bounds__(WG) void lg_gather_cand(LgArgs a) {
     }
 }
 
-// Deviation maximization (or the single LH column), panel QR with bt carried
-// along, compact WY, new R columns and the feasibility loop on J.
-__global__ __launch_bounds__(WG) void lg_panel(LgArgs a) {
+// Partial Gram matrix of X[r0:m, 0:c] (column-major, ld ldx) over row blocks of
+// 256 rows, on the matrix cores; symmetric tiles ti <= tj only.  which = 0: the
+// projected candidates (G, c = ncol); which = 1: the reflectors (V, c = kr).
+constexpr int GRAM_ROWS = 256;
+
+__global__ __launch_bounds__(WG) void lg_gram_part(LgArgs a, int which, double* part) {
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int r0 = ctl->nP, m = p.m;
+    const int c = which ? ctl->kr : ctl->ncol;
+    const double* X = which ? p.V : p.G;
+    const int ldx = m;
+    const int rs = r0 + blockIdx.x * GRAM_ROWS;
+    if (rs >= m || c <= 0) return;
+    const int re = min(m, rs + GRAM_ROWS);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nt = (c + 15) / 16;
+    int tile = 0;
+    double* out = part + (size_t)blockIdx.x * 64 * 64;
+    for (int ti = 0; ti < nt; ++ti)
+        for (int tj = ti; tj < nt; ++tj, ++tile) {
+            if ((tile % NW) != wv) continue;
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            const int ca = ti * 16 + (lane & 15), cbb = tj * 16 + (lane & 15);
+            for (int r = rs; r < re; r += 4) {
+                const int row = r + (lane >> 4);
+                const double av = (row < re && ca < c) ? X[(size_t)ca * ldx + row] : 0.0;
+                const double bv = (row < re && cbb < c) ? X[(size_t)cbb * ldx + row] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[(ti * 16 + 4 * v + (lane >> 4)) * 64 + tj * 16 + (lane & 15)] = acc[v];
+        }
+}
+
+// Sum of the partial Grams in block order, mirrored into a symmetric matrix
+// (ld kq): T for the candidates, W for the reflectors.
+__global__ __launch_bounds__(WG) void lg_gram_reduce(LgArgs a, int which, const double* part) {
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int r0 = ctl->nP, m = p.m, kq = p.kq;
+    const int c = which ? ctl->kr : ctl->ncol;
+    const int nblk = (m - r0 + GRAM_ROWS - 1) / GRAM_ROWS;
+    double* dst = which ? p.W : p.T;
+    for (int e = threadIdx.x; e < c * c; e += WG) {
+        const int i = e / c, j = e % c;
+        if (i > j) continue;
+        const int ti = i / 16, tj = j / 16;
+        double sum = 0.0;
+        for (int blk = 0; blk < nblk; ++blk) {
+            const double* pp = part + (size_t)blk * 64 * 64;
+            sum += (ti <= tj) ? pp[i * 64 + j] : pp[j * 64 + i];
+        }
+        dst[(size_t)j * kq + i] = sum;
+        dst[(size_t)i * kq + j] = sum;
+    }
+}
+
+// Deviation maximization's greedy test (or the single LH column), panel QR with
+// bt carried along, explicit reflectors in both layouts.
+__global__ __launch_bounds__(WG) void lg_panel_a(LgArgs a) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
     const Prob& p = a.p;
     if (s.ncol > 1) {
-        wg.deviation_maximization();
+        wg.greedy_from_gram();
     } else {
         if (threadIdx.x == 0) s.k = 1;
         __syncthreads();
@@ -214,18 +424,24 @@ __global__ __launch_bounds__(WG) void lg_panel(LgArgs a) {
     if (threadIdx.x == 0) s.kr = s.k;
     __syncthreads();
     wg.panel_qr();
+    wg.explicit_v();
+    const int kr = s.kr, kq = p.kq;
+    for (int row = threadIdx.x; row < p.m; row += WG)
+        for (int t = 0; t < kq; ++t) p.Vt[(size_t)row * kq + t] = (t < kr) ? p.V[(size_t)t * p.m + row] : 0.0;
+    ctl_store(s, a.ctl);
+}
+
+// Compact-WY factor, new R columns, feasibility loop on J.
+__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a) {
+    __shared__ WgShared s;
+    ctl_load(s, a.ctl);
+    Wg wg(a.p, a.prm, s);
+    const Prob& p = a.p;
     if (s.kr > 1) {
-        wg.form_wy();
+        wg.form_t();
     } else {
-        for (int i = threadIdx.x; i < p.m; i += WG) p.V[i] = (i < s.nP) ? 0.0 : p.G[i];
         if (threadIdx.x == 0) p.T[0] = s.tau[0];
         __syncthreads();
-    }
-    // row-major copy of V for the WY update of Q
-    const int kr = s.kr, kq = p.kq;
-    for (size_t e = threadIdx.x; e < (size_t)p.m * kq; e += WG) {
-        const int row = (int)(e / kq), t = (int)(e % kq);
-        p.Vt[e] = (t < kr) ? p.V[(size_t)t * p.m + row] : 0.0;
     }
     wg.append_r();
     if (threadIdx.x == 0) s.j1 = s.J[0];
@@ -241,21 +457,28 @@ __global__ __launch_bounds__(WG) void lg_panel(LgArgs a) {
     ctl_store(s, a.ctl);
 }
 
-// Commit the accepted block: P grows by J, snapshot of the added columns of Q.
+// Commit, pass 1 (all workgroups): snapshot of the appended columns of Q and
+// the reset of the exclusions.
+__global__ __launch_bounds__(WG) void lg_commit_copy(LgArgs a) {
+    const Ctl* ctl = a.ctl;
+    const int k = ctl->k;
+    if (k == 0) return;
+    const Prob& p = a.p;
+    const int m = p.m, r0 = ctl->nP;
+    const size_t tot = (size_t)m * k;
+    for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < tot; e += (size_t)gridDim.x * WG)
+        p.Qadd[e] = p.Q[(size_t)r0 * m + e];
+    if (ctl->any_excl)
+        for (int j = blockIdx.x * WG + threadIdx.x; j < p.n; j += gridDim.x * WG) p.excl[j] = 0;
+}
+
+// Commit, pass 2: P grows by J.
 __global__ __launch_bounds__(WG) void lg_commit(LgArgs a) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
     if (s.k == 0) return;
     const Prob& p = a.p;
-    if (s.any_excl) {
-        for (int j = threadIdx.x; j < p.n; j += WG) p.excl[j] = 0;
-    }
-    const int m = p.m, r0 = s.nP, k = s.k;
-    for (size_t e = threadIdx.x; e < (size_t)m * k; e += WG) {
-        const int t = (int)(e / m), i = (int)(e % m);
-        p.Qadd[(size_t)t * m + i] = p.Q[(size_t)(r0 + t) * m + i];
-    }
-    __syncthreads();
+    const int r0 = s.nP, k = s.k;
     if (threadIdx.x == 0) {
         for (int t = 0; t < k; ++t) {
             p.P[r0 + t] = s.J[t];
@@ -676,7 +899,9 @@ __global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
 
 // --------------------------------------------------------------------------
 // R y = bt[0:nP]: workgroup g solves row block nb-1-g after the blocks below
-// it have published their part of y (device-scope flags with epochs).
+// it have published their part of y.  Each wave of the workgroup takes every
+// fourth dependency block on its own (no workgroup barrier in the loop); the R
+// entries of a dependency block are loaded before its flag is awaited.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
     const Ctl* ctl = a.ctl;
@@ -688,46 +913,51 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
     if (g >= nb) return;
     const int b = nb - 1 - g;
     const int r0 = b * TB, nr = min(nP, r0 + TB) - r0;
-    const int tid = threadIdx.x, row = tid & 63, grp = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     __shared__ double part[NW][TB];
     __shared__ double Rd[TB][TB + 1];
-    // diagonal block into LDS (R does not change during the solve)
     for (int e = tid; e < TB * TB; e += WG) {
         const int cc = e / TB, rr = e % TB;
         Rd[rr][cc] = (cc < nr && rr <= cc) ? p.R[(size_t)p.slot[r0 + cc] * p.kc + r0 + rr] : 0.0;
     }
     double acc = 0.0;
-    for (int cb = nb - 1; cb > b; --cb) {
-        if (tid == 0) spin_wait(&a.flags_t[cb], epoch, &a.ex->err);
-        __syncthreads();
-        const int c0 = cb * TB, c1 = min(nP, c0 + TB);
-        for (int cc = c0 + grp; cc < c1; cc += NW) {
-            const double yc = load_coherent(&p.ybuf[cc]);
-            if (row < nr) acc += p.R[(size_t)p.slot[cc] * p.kc + r0 + row] * yc;
-        }
+    const bool rowok = lane < nr;
+    for (int cb = nb - 1 - wv; cb > b; cb -= NW) {
+        const int c0 = cb * TB, nc = min(nP, c0 + TB) - c0;
+        double rv[TB];
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+            rv[j] = (j < nc && rowok) ? p.R[(size_t)p.slot[c0 + j] * p.kc + r0 + lane] : 0.0;
+        spin_wait(&a.flags_t[cb], epoch, &a.ex->err);
+        const double yv = (lane < nc) ? sys_ld(&p.ybuf[c0 + lane]) : 0.0;
+#pragma unroll
+        for (int j = 0; j < TB; ++j) acc += rv[j] * __shfl(yv, j, 64);
     }
-    part[grp][row] = acc;
+    part[wv][lane] = acc;
     __syncthreads();
-    if (grp != 0) return;
+    if (wv != 0) return;
     double v = 0.0;
-    if (row < nr) v = p.bt[r0 + row] - (((part[0][row] + part[1][row]) + part[2][row]) + part[3][row]);
+    if (rowok) v = p.bt[r0 + lane] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
     for (int j = nr - 1; j >= 0; --j) {
-        const double cand = v / Rd[row][row];
+        const double cand = v / Rd[lane][lane];
         const double yj = __shfl(cand, j, 64);
-        if (row == j) v = yj;
-        else if (row < j) v -= Rd[row][j] * yj;
+        if (lane == j) v = yj;
+        else if (lane < j) v -= Rd[lane][j] * yj;
     }
-    if (row < nr) p.ybuf[r0 + row] = v;
-    __threadfence();
-    if (row == 0) store_release(&a.flags_t[b], epoch);
+    if (rowok) sys_st(&p.ybuf[r0 + lane], v);
+    publish(&a.flags_t[b], epoch);
 }
 
 // --------------------------------------------------------------------------
 // Algorithm 5 on R.  Block b (one wave) owns new columns first + 64 b .. +64:
 // it applies, in order, the rotations published by every earlier block to its
 // columns, then generates its own column by column (bottom-up within a column)
-// and publishes them.
+// and publishes them.  When every column of a block carries one rotation (a
+// single removal in this stretch) the 65 rows a block touches are held in
+// registers; otherwise rotations are applied entry by entry in memory.
 // --------------------------------------------------------------------------
+constexpr int GROT_LDS = 512;   // rotations of one block staged in LDS per chunk
+
 __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     const LgExtra* ex = a.ex;
     const Prob& p = a.p;
@@ -738,59 +968,120 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     const int lane = threadIdx.x;
     const int idx = b * GB + lane;
     const bool valid = idx < nd;
-    __shared__ double rc[RQ], rs[RQ];
-    double* col = nullptr;
-    if (valid) col = p.R + (size_t)p.slot[a.ocol[idx]] * p.kc;
+    __shared__ double rc[GROT_LDS], rs[GROT_LDS];
+    double* col = p.R + (size_t)p.slot[a.ocol[valid ? idx : 0]] * p.kc;
     for (int bb = 0; bb < b; ++bb) {
-        if (lane == 0) spin_wait(&a.flags_g[bb], epoch, &a.ex->err);
-        __syncthreads();
-        const int e1 = min(nd, (bb + 1) * GB);
-        for (int e = bb * GB; e < e1; ++e) {
-            const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
-            for (int gg = 0; gg < l2; ++gg) {
-                const double cs = load_coherent(&a.rotbuf[2 * (off + gg)]);
-                const double sn = load_coherent(&a.rotbuf[2 * (off + gg) + 1]);
-                if (valid) {
-                    const int i = occ - gg;
-                    const double x0 = col[i - 1], x1 = col[i];
-                    col[i - 1] = cs * x0 + sn * x1;
-                    col[i] = -sn * x0 + cs * x1;
+        const int e0 = bb * GB, e1 = min(nd, (bb + 1) * GB);
+        spin_wait(&a.flags_g[bb], epoch, &a.ex->err);
+        const bool unit = a.lcnt[e0] == 1 && a.lcnt[e1 - 1] == 1 && (e1 - e0) == GB;
+        if (unit) {
+            // rotations e of this block act on rows (c_e, c_e + 1), c_e = first + e
+            const int off = a.roff[e0];
+            rc[lane] = sys_ld(&a.rotbuf[2 * (off + lane)]);
+            rs[lane] = sys_ld(&a.rotbuf[2 * (off + lane) + 1]);
+            __syncthreads();
+            if (valid) {
+                const int rbase = first + e0;
+                double x[GB + 1];
+#pragma unroll
+                for (int r = 0; r <= GB; ++r) x[r] = col[rbase + r];
+#pragma unroll
+                for (int e = 0; e < GB; ++e) {
+                    const double cs = rc[e], sn = rs[e];
+                    const double x0 = x[e], x1 = x[e + 1];
+                    x[e] = cs * x0 + sn * x1;
+                    x[e + 1] = -sn * x0 + cs * x1;
+                }
+#pragma unroll
+                for (int r = 0; r <= GB; ++r) col[rbase + r] = x[r];
+            }
+            __syncthreads();
+        } else {
+            for (int e = e0; e < e1; ++e) {
+                const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
+                for (int g0 = 0; g0 < l2; g0 += GROT_LDS) {
+                    const int cntr = min(GROT_LDS, l2 - g0);
+                    for (int u = lane; u < cntr; u += 64) {
+                        rc[u] = sys_ld(&a.rotbuf[2 * (off + g0 + u)]);
+                        rs[u] = sys_ld(&a.rotbuf[2 * (off + g0 + u) + 1]);
+                    }
+                    __syncthreads();
+                    if (valid)
+                        for (int u = 0; u < cntr; ++u) {
+                            const int i = occ - (g0 + u);
+                            const double x0 = col[i - 1], x1 = col[i];
+                            col[i - 1] = rc[u] * x0 + rs[u] * x1;
+                            col[i] = -rs[u] * x0 + rc[u] * x1;
+                        }
+                    __syncthreads();
                 }
             }
         }
     }
-    const int e1 = min(nd, (b + 1) * GB);
-    for (int e = b * GB; e < e1; ++e) {
-        const int t = e - b * GB;
-        const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
-        if (lane == t) {
-            for (int gg = 0; gg < l2; ++gg) {
-                const int i = occ - gg;
-                const double x0 = col[i - 1], x1 = col[i];
-                double cs, sn, rr;
-                givens(x0, x1, cs, sn, rr);
-                col[i - 1] = cs * x0 + sn * x1;
-                col[i] = 0.0;
-                rc[gg] = cs;
-                rs[gg] = sn;
-                a.rotbuf[2 * (off + gg)] = cs;
-                a.rotbuf[2 * (off + gg) + 1] = sn;
+    const int e0 = b * GB, e1 = min(nd, (b + 1) * GB);
+    const bool unit = a.lcnt[e0] == 1 && a.lcnt[e1 - 1] == 1 && (e1 - e0) == GB;
+    if (unit) {
+        // own block in registers: rotation t acts on rows (first + e0 + t, +1)
+        const int rbase = first + e0;
+        const int off = a.roff[e0];
+        double x[GB + 1];
+#pragma unroll
+        for (int r = 0; r <= GB; ++r) x[r] = col[rbase + r];
+#pragma unroll
+        for (int t = 0; t < GB; ++t) {
+            double cs = 1.0, sn = 0.0;
+            if (lane == t) {
+                double rr;
+                givens(x[t], x[t + 1], cs, sn, rr);
+                const double x0 = x[t], x1 = x[t + 1];
+                x[t] = cs * x0 + sn * x1;
+                x[t + 1] = 0.0;
+                sys_st(&a.rotbuf[2 * (off + t)], cs);
+                sys_st(&a.rotbuf[2 * (off + t) + 1], sn);
+            }
+            cs = __shfl(cs, t, 64);
+            sn = __shfl(sn, t, 64);
+            if (lane > t) {
+                const double x0 = x[t], x1 = x[t + 1];
+                x[t] = cs * x0 + sn * x1;
+                x[t + 1] = -sn * x0 + cs * x1;
             }
         }
-        __syncthreads();
-        if (valid && lane > t) {
-            for (int gg = 0; gg < l2; ++gg) {
-                const int i = occ - gg;
-                const double cs = rc[gg], sn = rs[gg];
-                const double x0 = col[i - 1], x1 = col[i];
-                col[i - 1] = cs * x0 + sn * x1;
-                col[i] = -sn * x0 + cs * x1;
+#pragma unroll
+        for (int r = 0; r <= GB; ++r) col[rbase + r] = x[r];
+    } else {
+        for (int e = e0; e < e1; ++e) {
+            const int t = e - e0;
+            const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
+            for (int g0 = 0; g0 < l2; g0 += GROT_LDS) {
+                const int cntr = min(GROT_LDS, l2 - g0);
+                if (lane == t) {
+                    for (int u = 0; u < cntr; ++u) {
+                        const int i = occ - (g0 + u);
+                        const double x0 = col[i - 1], x1 = col[i];
+                        double cs, sn, rr;
+                        givens(x0, x1, cs, sn, rr);
+                        col[i - 1] = cs * x0 + sn * x1;
+                        col[i] = 0.0;
+                        rc[u] = cs;
+                        rs[u] = sn;
+                        sys_st(&a.rotbuf[2 * (off + g0 + u)], cs);
+                        sys_st(&a.rotbuf[2 * (off + g0 + u) + 1], sn);
+                    }
+                }
+                __syncthreads();
+                if (valid && lane > t)
+                    for (int u = 0; u < cntr; ++u) {
+                        const int i = occ - (g0 + u);
+                        const double x0 = col[i - 1], x1 = col[i];
+                        col[i - 1] = rc[u] * x0 + rs[u] * x1;
+                        col[i] = -rs[u] * x0 + rc[u] * x1;
+                    }
+                __syncthreads();
             }
         }
-        __syncthreads();
     }
-    __threadfence();
-    if (lane == 0) store_release(&a.flags_g[b], epoch);
+    publish(&a.flags_g[b], epoch);
 }
 
 // The downdate's rotations applied to the columns of Q (one thread per row of Q)
@@ -828,7 +1119,8 @@ __global__ __launch_bounds__(WG) void lg_qrot(LgArgs a) {
 // host driver
 // --------------------------------------------------------------------------
 struct LargeLayout {
-    size_t slot, ybuf, Vt, Dt, rot, ocol, lcnt, roff, flt, flg, recomp, rpart, ctl, ex, misc, wfall, total;
+    size_t slot, ybuf, Vt, Dt, rot, ocol, lcnt, roff, flt, flg, recomp, rpart, gpart, selv, seli, ctl, ex, misc,
+        wfall, total;
 };
 
 static LargeLayout large_layout(int m, int n, int kmax) {
@@ -852,6 +1144,9 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.roff, sizeof(int) * kc);
     put(L.recomp, sizeof(int) * (size_t)n);
     put(L.rpart, sizeof(double) * (size_t)RES_CHUNKS * m);
+    put(L.gpart, sizeof(double) * (size_t)((m + 255) / 256) * 64 * 64);
+    put(L.selv, sizeof(double) * 3 * 64);
+    put(L.seli, sizeof(int) * 64);
     put(L.ctl, sizeof(Ctl));
     put(L.ex, sizeof(LgExtra));
     put(L.misc, 256);
@@ -915,6 +1210,9 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     a.flags_g = (int*)(base + L.flg);
     a.recomp = (int*)(base + L.recomp);
     a.rpart = (double*)(base + L.rpart);
+    a.gpart = (double*)(base + L.gpart);
+    a.selv = (double*)(base + L.selv);
+    a.seli = (int*)(base + L.seli);
     unsigned long long* anmax_bits = (unsigned long long*)(base + L.misc);
     int* bad = (int*)(base + L.misc + 8);
 
@@ -960,7 +1258,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     const int rgrid = (m + WG - 1) / WG;
     bool stop = mir->ctl.status != LHDM_STATUS_OK;
     while (!stop) {
-        hipLaunchKernelGGL(lg_select, dim3(1), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_sel_part, dim3(NSEL), dim3(WG), 0, st, a, a.selv, a.seli);
+        hipLaunchKernelGGL(lg_sel_main, dim3(1), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli);
         HIPCHK(hipGetLastError());
         if ((rc = read_ctl())) return rc;
         if (mir->ctl.done) break;
@@ -981,8 +1280,19 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             ca.nvec = mir->ctl.ncol;
             if ((rc = colmat_launch(st, ca))) return rc;
         }
-        hipLaunchKernelGGL(lg_panel, dim3(1), dim3(WG), 0, st, a);
+        const int gblk = (m + GRAM_ROWS - 1) / GRAM_ROWS;
+        if (mir->ctl.ncol > 1) {
+            hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 0, a.gpart);
+            hipLaunchKernelGGL(lg_gram_reduce, dim3(1), dim3(WG), 0, st, a, 0, (const double*)a.gpart);
+        }
+        hipLaunchKernelGGL(lg_panel_a, dim3(1), dim3(WG), 0, st, a);
+        if (mir->ctl.ncol > 1) {
+            hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 1, a.gpart);
+            hipLaunchKernelGGL(lg_gram_reduce, dim3(1), dim3(WG), 0, st, a, 1, (const double*)a.gpart);
+        }
+        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_qupdate, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, st, a);
         ++ep_t;
         hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t);

@@ -260,9 +260,8 @@ struct Wg {
         __syncthreads();
     }
 
-    // Cosines of the projected candidates (eq. of the cosine matrix) and the
-    // greedy acceptance of Algorithm 2.  Compacts G to the accepted columns.
-    __device__ void deviation_maximization() {
+    // Gram matrix of the projected candidates G[n_P:m, 0:ncol] into T (ld kq).
+    __device__ void candidate_gram() {
         const int m = p.m, c = s.ncol, r0 = s.nP, kq = p.kq;
         const int npair = c * (c + 1) / 2;
         for (int pr = wid; pr < npair; pr += NW) {
@@ -283,6 +282,13 @@ struct Wg {
             }
         }
         __syncthreads();
+    }
+
+    // Cosines of the projected candidates (eq. of the cosine matrix) from the
+    // Gram matrix in T, and the greedy acceptance of Algorithm 2.  Compacts G
+    // to the accepted columns.
+    __device__ void greedy_from_gram() {
+        const int m = p.m, c = s.ncol, kq = p.kq;
         if (tid == 0) {
             const int cap = p.m - s.nP;
             int acc[KM];
@@ -319,17 +325,24 @@ struct Wg {
         }
     }
 
+    __device__ void deviation_maximization() {
+        candidate_gram();
+        greedy_from_gram();
+    }
+
     // a3: Householder QR of the panel G[n_P:m, 0:k] with bt[n_P:m] carried as an
     // extra column (Algorithm 4); G keeps the reflectors below the diagonal,
-    // s.beta the new diagonal of R, s.tau the reflector scalars.
+    // s.beta the new diagonal of R, s.tau the reflector scalars.  Per column:
+    // one pass for all dot products with the reflector, one pass for the update
+    // that also accumulates the norm of the next column.
     __device__ void panel_qr() {
         const int m = p.m, k = s.kr, r0 = s.nP;
+        double part0 = 0.0;
+        for (int i = r0 + tid; i < m; i += WG) part0 += p.G[i] * p.G[i];
+        double nrm2 = sum(part0);
         for (int t = 0; t < k; ++t) {
             const int rt = r0 + t;
             double* g = p.G + (size_t)t * m;
-            double part = 0.0;
-            for (int i = rt + tid; i < m; i += WG) part += g[i] * g[i];
-            const double nrm2 = sum(part);
             const double x0 = g[rt];
             const double normx = sqrt(nrm2);
             double tau = 0.0, beta = x0, scal = 0.0;
@@ -346,35 +359,58 @@ struct Wg {
                 s.beta[t] = beta;
             }
             __syncthreads();
-            // apply H_t to panel columns t+1..k-1 and to bt
-            const int nrest = k - t;   // columns t+1..k-1 plus bt
-            for (int q = 0; q < nrest; ++q) {
-                const double* col = (q < nrest - 1) ? p.G + (size_t)(t + 1 + q) * m : p.bt;
-                double d = 0.0;
-                for (int i = rt + tid; i < m; i += WG) d += g[i] * col[i];
-                push(q, d);
+            // dot products of the reflector with columns t+1..k-1 and bt, 16 at a time
+            const int nrest = k - t;
+            for (int q0 = 0; q0 < nrest; q0 += 16) {
+                double pd[16];
+#pragma unroll
+                for (int qq = 0; qq < 16; ++qq) pd[qq] = 0.0;
+                for (int i = rt + tid; i < m; i += WG) {
+                    const double vi = g[i];
+#pragma unroll
+                    for (int qq = 0; qq < 16; ++qq) {
+                        const int q = q0 + qq;
+                        if (q < nrest) {
+                            const double* col = (q < nrest - 1) ? p.G + (size_t)(t + 1 + q) * m : p.bt;
+                            pd[qq] += vi * col[i];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int qq = 0; qq < 16; ++qq)
+                    if (q0 + qq < nrest) push(q0 + qq, pd[qq]);
             }
             finish(nrest);
-            for (int q = 0; q < nrest; ++q) {
-                double* col = (q < nrest - 1) ? p.G + (size_t)(t + 1 + q) * m : p.bt;
-                const double f = tau * s.vec[q];
-                for (int i = rt + tid; i < m; i += WG) col[i] -= f * g[i];
+            // update, and the squared norm of column t+1 from row rt+1
+            double nn = 0.0;
+            for (int i = rt + tid; i < m; i += WG) {
+                const double vi = g[i];
+                for (int q = 0; q < nrest; ++q) {
+                    double* col = (q < nrest - 1) ? p.G + (size_t)(t + 1 + q) * m : p.bt;
+                    const double nv = col[i] - (tau * s.vec[q]) * vi;
+                    col[i] = nv;
+                    if (q == 0 && i > rt && t + 1 < k) nn += nv * nv;
+                }
             }
-            __syncthreads();
+            if (t + 1 < k) nrm2 = sum(nn);
+            else __syncthreads();
         }
     }
 
-    // Explicit V (zeros above the unit diagonal, rows >= n_P) and the compact-WY
-    // factor T with H_0 H_1 ... H_{k-1} = I - V T V^T (forward, columnwise).
-    __device__ void form_wy() {
-        const int m = p.m, k = s.kr, r0 = s.nP, kq = p.kq;
+    // Explicit V (zeros above the unit diagonal, rows >= n_P).
+    __device__ void explicit_v() {
+        const int m = p.m, k = s.kr, r0 = s.nP;
         for (int t = 0; t < k; ++t) {
             const double* g = p.G + (size_t)t * m;
             double* v = p.V + (size_t)t * m;
             for (int i = tid; i < m; i += WG) v[i] = (i < r0 + t) ? 0.0 : g[i];
         }
         __syncthreads();
-        // V^T V strictly upper part into W (k x k scratch, column-major ld kq)
+    }
+
+    // V^T V, strictly upper part, into W (k x k, column-major ld kq).
+    __device__ void vtv() {
+        const int m = p.m, k = s.kr, r0 = s.nP, kq = p.kq;
         const int npair = k * (k - 1) / 2;
         for (int pr = wid; pr < npair; pr += NW) {
             int a = 1, rem = pr;
@@ -391,6 +427,12 @@ struct Wg {
             if (lane == 0) p.W[(size_t)a * kq + b] = acc;
         }
         __syncthreads();
+    }
+
+    // Compact-WY factor T with H_0 H_1 ... H_{k-1} = I - V T V^T (forward,
+    // columnwise) from s.tau and V^T V in W.
+    __device__ void form_t() {
+        const int k = s.kr, kq = p.kq;
         if (tid == 0) {
             double* T = p.T;
             for (int t = 0; t < k; ++t) {
@@ -406,6 +448,12 @@ struct Wg {
             }
         }
         __syncthreads();
+    }
+
+    __device__ void form_wy() {
+        explicit_v();
+        vtv();
+        form_t();
     }
 
     // New R columns: [Q_P^T a_J ; R_JJ].
@@ -616,28 +664,38 @@ struct Wg {
     }
 
     // Drop the removed positions from P; their R slots move behind the kept ones
-    // (slot stays a permutation, free slots at [n_P, kc)).
+    // (slot stays a permutation, free slots at [n_P, kc)).  Kept position c
+    // moves to c - #{removed < c}; the t-th removed slot goes to n_P - q + t.
     __device__ void compact() {
         const int q = s.q, nP = s.nP;
-        if (tid == 0) {
-            int w = 0, t = 0;
-            for (int c = 0; c < nP; ++c) {
-                const int j = p.P[c];
-                const int sl = p.slot[c];
-                if (t < q && p.rm[t] == c) {
-                    p.pos[j] = -1;
-                    p.rm[t] = sl;          // reuse rm to hold the freed slots
-                    ++t;
-                    continue;
-                }
-                p.P[w] = j;
-                p.slot[w] = sl;
-                p.pos[j] = w;
-                ++w;
-            }
-            for (int t2 = 0; t2 < q; ++t2) p.slot[w + t2] = p.rm[t2];
-            s.nP = w;
+        if (q == 0) return;
+        int* oldP = p.itmp;
+        int* oldS = p.itmp + p.kc;
+        for (int c = tid; c < nP; c += WG) {
+            oldP[c] = p.P[c];
+            oldS[c] = p.slot[c];
         }
+        __syncthreads();
+        for (int c = tid; c < nP; c += WG) {
+            int lo = 0, hi = q;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (p.rm[mid] < c) lo = mid + 1;
+                else hi = mid;
+            }
+            const int j = oldP[c];
+            if (lo < q && p.rm[lo] == c) {
+                p.pos[j] = -1;
+                p.slot[nP - q + lo] = oldS[c];
+            } else {
+                const int w = c - lo;
+                p.P[w] = j;
+                p.slot[w] = oldS[c];
+                p.pos[j] = w;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s.nP = nP - q;
         __syncthreads();
     }
 
