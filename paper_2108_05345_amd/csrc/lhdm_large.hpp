@@ -45,6 +45,7 @@ struct LgExtra {
     int kadd;         // added directions in the dual update
     int exact;        // 1: norms recomputed from the trailing columns of Q
     int pending;      // removals left over from a sweep capped at RQ positions
+    int bar;          // arrival counter of the multi-workgroup panel factorisation
     int seg_start[RQ + 1];
     int seg_off[RQ + 1];
 };
@@ -66,6 +67,7 @@ struct LgArgs {
     double* gpart;    // partial Gram matrices (ceil(m / 256) blocks of 64 x 64)
     double* selv;     // 3 * NSEL partial maxima of the selection
     int* seli;        // NSEL partial argmax indices
+    double* ppart;    // panel partials: PNW norms, PNW x (KM + 1) dots, one pivot
 };
 
 // --------------------------------------------------------------------------
@@ -408,50 +410,238 @@ __global__ __launch_bounds__(WG) void lg_gram_reduce(LgArgs a, int which, const 
     }
 }
 
-// Deviation maximization's greedy test (or the single LH column), panel QR with
-// bt carried along, explicit reflectors in both layouts.
-__global__ __launch_bounds__(WG) void lg_panel_a(LgArgs a) {
+// Deviation maximization's greedy test (or the single LH column); resets the
+// arrival counter of the panel factorisation.
+__global__ __launch_bounds__(WG) void lg_greedy(LgArgs a) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
-    const Prob& p = a.p;
     if (s.ncol > 1) {
         wg.greedy_from_gram();
     } else {
         if (threadIdx.x == 0) s.k = 1;
         __syncthreads();
     }
-    if (threadIdx.x == 0) s.kr = s.k;
-    __syncthreads();
-    wg.panel_qr();
-    wg.explicit_v();
-    const int kr = s.kr, kq = p.kq;
-    for (int row = threadIdx.x; row < p.m; row += WG)
-        for (int t = 0; t < kq; ++t) p.Vt[(size_t)row * kq + t] = (t < kr) ? p.V[(size_t)t * p.m + row] : 0.0;
+    if (threadIdx.x == 0) {
+        s.kr = s.k;
+        sys_sti(&a.ex->bar, 0);
+    }
     ctl_store(s, a.ctl);
 }
 
-// Compact-WY factor, new R columns, feasibility loop on J.
-__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a) {
+// Householder QR of the panel G[n_P:m, 0:kr] with bt[n_P:m] carried as column
+// kr (Algorithm 4), spread over the workgroups: each owns `rpw` consecutive
+// rows of the panel and keeps them in LDS; the column norm and the dot
+// products with the reflector are summed across workgroups (partials in a
+// fixed order, identical on every workgroup), with two counter barriers per
+// column.
+constexpr int PNW = 32;                  // largest number of workgroups of the panel factorisation
+constexpr int PANEL_LDS_MAX = 128 * 1024;   // dynamic LDS of one workgroup of the panel factorisation
+
+__device__ inline void panel_barrier(int* bar, int target, int* err) {
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's partials are stored
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        long long it = 0;
+        while (sys_ldi(bar) < target) {
+            if (++it > SPIN_LIMIT) {
+                atomicExch(err, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw) {
+    extern __shared__ double pan[];   // rpw x (kr + 1), row-major
+    __shared__ double sv[KM + 1];
+    __shared__ double sc[4];
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int r0 = ctl->nP, kr = ctl->kr, m = p.m;
+    const int npw = (m - r0 + rpw - 1) / rpw;
+    const int w = blockIdx.x;
+    if (w >= npw) return;
+    const int rs = r0 + w * rpw, re = min(m, rs + rpw), nr = re - rs;
+    const int ld = kr + 1;
+    const int tid = threadIdx.x;
+    double* NP = a.ppart;                    // [PNW]
+    double* DQ = a.ppart + PNW;              // [PNW][KM + 1]
+    double* X0 = a.ppart + PNW + PNW * (KM + 1);
+    for (int e = tid; e < nr * ld; e += WG) {
+        const int i = e / ld, q = e % ld;
+        pan[e] = (q < kr) ? p.G[(size_t)q * m + rs + i] : p.bt[rs + i];
+    }
+    __syncthreads();
+    int phase = 0;
+    // norm partial of column 0 and the pivot entry
+    if (tid == 0) {
+        double acc = 0.0;
+        for (int i = 0; i < nr; ++i) acc += pan[i * ld] * pan[i * ld];
+        sys_st(&NP[w], acc);
+        if (w == 0) sys_st(X0, pan[0]);
+    }
+    panel_barrier(&a.ex->bar, (++phase) * npw, &a.ex->err);
+    for (int t = 0; t < kr; ++t) {
+        const int rt = r0 + t;
+        if (tid == 0) {
+            double nrm2 = 0.0;
+            for (int u = 0; u < npw; ++u) nrm2 += sys_ld(&NP[u]);
+            const double x0 = sys_ld(X0);
+            const double normx = sqrt(nrm2);
+            double tau = 0.0, beta = x0, scal = 0.0;
+            if (normx > 0.0) {
+                beta = (x0 >= 0.0) ? -normx : normx;
+                tau = (beta - x0) / beta;
+                scal = 1.0 / (x0 - beta);
+            }
+            sc[0] = tau;
+            sc[1] = beta;
+            sc[2] = scal;
+            if (w == 0) {
+                a.ctl->tau[t] = tau;
+                a.ctl->beta[t] = beta;
+            }
+        }
+        __syncthreads();
+        const double tau = sc[0], scal = sc[2];
+        // local rows of this step: global rows >= rt
+        const int i0 = max(0, rt - rs);
+        for (int i = i0 + tid; i < nr; i += WG) {
+            if (rs + i == rt) pan[i * ld + t] = 1.0;
+            else pan[i * ld + t] *= scal;
+        }
+        __syncthreads();
+        // partial dots of the reflector with columns t+1 .. kr (bt is column kr)
+        for (int q = t + 1 + tid; q <= kr; q += WG) {
+            double acc = 0.0;
+            for (int i = i0; i < nr; ++i) acc += pan[i * ld + t] * pan[i * ld + q];
+            sys_st(&DQ[w * (KM + 1) + q], acc);
+        }
+        panel_barrier(&a.ex->bar, (++phase) * npw, &a.ex->err);
+        for (int q = t + 1 + tid; q <= kr; q += WG) {
+            double d = 0.0;
+            for (int u = 0; u < npw; ++u) d += sys_ld(&DQ[u * (KM + 1) + q]);
+            sv[q] = tau * d;
+        }
+        __syncthreads();
+        for (int i = i0 + tid; i < nr; i += WG) {
+            const double vi = pan[i * ld + t];
+            for (int q = t + 1; q <= kr; ++q) pan[i * ld + q] -= sv[q] * vi;
+        }
+        __syncthreads();
+        if (t + 1 < kr) {
+            if (tid == 0) {
+                const int j0 = max(0, rt + 1 - rs);
+                double acc = 0.0;
+                for (int i = j0; i < nr; ++i) acc += pan[i * ld + t + 1] * pan[i * ld + t + 1];
+                sys_st(&NP[w], acc);
+                if (rt + 1 >= rs && rt + 1 < re) sys_st(X0, pan[(rt + 1 - rs) * ld + t + 1]);
+            }
+            panel_barrier(&a.ex->bar, (++phase) * npw, &a.ex->err);
+        }
+    }
+    for (int e = tid; e < nr * ld; e += WG) {
+        const int i = e / ld, q = e % ld;
+        if (q < kr) p.G[(size_t)q * m + rs + i] = pan[e];
+        else p.bt[rs + i] = pan[e];
+    }
+}
+
+// Single-workgroup panel factorisation (used when a row chunk of the panel
+// would not fit in LDS).
+__global__ __launch_bounds__(WG) void lg_panel_1wg(LgArgs a) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
+    wg.panel_qr();
+    ctl_store(s, a.ctl);
+}
+
+// Explicit reflectors V (zeros above the unit diagonal) in both layouts.
+__global__ __launch_bounds__(WG) void lg_panel_v(LgArgs a) {
+    const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
-    if (s.kr > 1) {
-        wg.form_t();
-    } else {
-        if (threadIdx.x == 0) p.T[0] = s.tau[0];
+    const int r0 = ctl->nP, kr = ctl->kr, m = p.m, kq = p.kq;
+    for (int row = blockIdx.x * WG + threadIdx.x; row < m; row += gridDim.x * WG) {
+        for (int t = 0; t < kq; ++t) {
+            double v = 0.0;
+            if (t < kr && row >= r0 + t) v = p.G[(size_t)t * m + row];
+            if (t < kr) p.V[(size_t)t * m + row] = v;
+            p.Vt[(size_t)row * kq + t] = v;
+        }
+    }
+}
+
+// Compact-WY factor (from V^T V in W), new R columns, feasibility loop on J.
+// T and the new diagonal block of R are staged in LDS; the J-loop's triangular
+// solves run on one wave (one row per lane).
+__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a) {
+    __shared__ WgShared s;
+    __shared__ double Tl[KM][KM + 1];
+    __shared__ double Wl[KM][KM + 1];
+    ctl_load(s, a.ctl);
+    Wg wg(a.p, a.prm, s);
+    const Prob& p = a.p;
+    const int kr = s.kr, kq = p.kq, tid = threadIdx.x;
+    // T: column t = -tau_t T[0:t, 0:t] (V^T V)[0:t, t], diagonal tau
+    for (int e = tid; e < kr * kr; e += WG) {
+        const int i = e % kr, t = e / kr;
+        Wl[i][t] = (i < t) ? p.W[(size_t)t * kq + i] : 0.0;
+        Tl[i][t] = 0.0;
+    }
+    __syncthreads();
+    for (int t = 0; t < kr; ++t) {
+        if (tid < t) {
+            double acc = 0.0;
+            for (int l = tid; l < t; ++l) acc += Tl[tid][l] * Wl[l][t];
+            Tl[tid][t] = -s.tau[t] * acc;
+        }
+        if (tid == 0) Tl[t][t] = s.tau[t];
         __syncthreads();
     }
+    for (int e = tid; e < kr * kq; e += WG) {
+        const int i = e % kq, t = e / kq;
+        p.T[(size_t)t * kq + i] = (i < kr) ? Tl[i][t] : 0.0;
+    }
     wg.append_r();
-    if (threadIdx.x == 0) s.j1 = s.J[0];
+    // feasibility loop on J: longest prefix of J whose own LS components are positive
+    const int r0 = s.nP;
+    for (int e = tid; e < kr * kr; e += WG) {
+        const int i = e % kr, t = e / kr;
+        Wl[i][t] = (i <= t) ? p.R[(size_t)p.slot[r0 + t] * p.kc + r0 + i] : 0.0;
+    }
     __syncthreads();
-    wg.jloop();
-    if (threadIdx.x == 0) {
-        a.ex->restart = (s.k == 0);
-        if (s.k == 0) {
-            p.excl[s.j1] = 1;
-            s.any_excl = 1;
+    if (tid < 64) {
+        const int lane = tid;
+        int k = kr;
+        const double bl = (lane < kr) ? p.bt[r0 + lane] : 0.0;
+        while (k > 0) {
+            double v = (lane < k) ? bl : 0.0;
+            double mn = INFINITY;
+            for (int j = k - 1; j >= 0; --j) {
+                const double cand = v / Wl[lane < k ? lane : 0][lane < k ? lane : 0];
+                const double yj = __shfl(cand, j, 64);
+                mn = fmin(mn, yj);
+                if (lane == j) v = yj;
+                else if (lane < j) v -= Wl[lane][j] * yj;
+            }
+            if (mn > 0.0) break;
+            --k;
+        }
+        if (lane == 0) {
+            s.jdrops += kr - k;
+            s.k = k;
+            s.j1 = s.J[0];
+            a.ex->restart = (k == 0);
+            if (k == 0) {
+                p.excl[s.j1] = 1;
+                s.any_excl = 1;
+            }
         }
     }
     ctl_store(s, a.ctl);
@@ -623,6 +813,7 @@ struct ColmatArgs {
     int ldd;         // row stride of Dt (>= 16 NT)
     int nvec;        // vectors in this launch (<= 16 NT)
     int mode;
+    int al16;        // X and ldx allow 16-byte vector loads
     // MODE_PROJ: out[t * ldo + j]
     double* out;
     int ldo;
@@ -638,47 +829,74 @@ struct ColmatArgs {
 };
 
 template <int NT>
+__device__ __forceinline__ void colmat_step(const double (&av)[8], const double* __restrict__ Dt, int ldd,
+                                            int rowb, int lane, d4 (&acc)[NT]) {
+    double bv[NT][8];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) bv[t][s] = Dt[(size_t)(rowb + s) * ldd + t * 16 + (lane & 15)];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[t][s], acc[t], 0, 0, 0);
+}
+
+__device__ __forceinline__ void load8(const double* __restrict__ src, bool al16, double (&v)[8]) {
+    if (al16) {
+        const double2* s2 = reinterpret_cast<const double2*>(src);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const double2 x = s2[h];
+            v[2 * h] = x.x;
+            v[2 * h + 1] = x.y;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = src[s];
+    }
+}
+
+template <int NT>
 __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
     if (a.skip && *a.skip) return;
     __shared__ double part[NW][NT][4][64];
     __shared__ double Ct[16][16 * NT + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int j0 = blockIdx.x * 16;
-    const int col = j0 + (lane & 15);
     const int kk = lane >> 4;
-    const bool colok = col < a.ncols;
-    const double* xc = a.X + (size_t)(colok ? col : 0) * a.ldx;
+    // columns past the end repeat the last column (their results are dropped)
+    const int col = min(j0 + (lane & 15), a.ncols - 1);
+    const double* xc = a.X + (size_t)col * a.ldx;
+    const bool al16 = a.al16;
     d4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int r0 = wv * 32; r0 < a.m; r0 += 32 * NW) {
-        const int rb = r0 + 8 * kk;
-        double av[8];
-        if (colok && rb + 8 <= a.m) {
-            const double2* src = reinterpret_cast<const double2*>(xc + rb);
-            if ((((uintptr_t)(xc + rb)) & 15) == 0) {
+    const int nfull = a.m / 32;   // full 32-row steps; wave wv takes steps wv, wv + 4, ...
+    int st = wv;
+    double av[8], an[8];
+    if (st < nfull) load8(xc + st * 32 + 8 * kk, al16, av);
+    while (st < nfull) {
+        const int sn = st + NW;
+        if (sn < nfull) load8(xc + sn * 32 + 8 * kk, al16, an);
+        colmat_step<NT>(av, a.Dt, a.ldd, st * 32 + 8 * kk, lane, acc);
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    const double2 v = src[h];
-                    av[2 * h] = v.x;
-                    av[2 * h + 1] = v.y;
-                }
-            } else {
+        for (int q = 0; q < 8; ++q) av[q] = an[q];
+        st = sn;
+    }
+    if (wv == (nfull % NW) && nfull * 32 < a.m) {
+        // ragged tail: rows [32 nfull, m)
+        const int rb = nfull * 32 + 8 * kk;
+        double bv[8];
 #pragma unroll
-                for (int s = 0; s < 8; ++s) av[s] = xc[rb + s];
-            }
-        } else {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) av[s] = (colok && rb + s < a.m) ? xc[rb + s] : 0.0;
-        }
+        for (int q = 0; q < 8; ++q) av[q] = (rb + q < a.m) ? xc[rb + q] : 0.0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int row = rb + s;
-                const double bv = (row < a.m) ? a.Dt[(size_t)row * a.ldd + t * 16 + (lane & 15)] : 0.0;
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv, acc[t], 0, 0, 0);
-            }
+            for (int q = 0; q < 8; ++q)
+                bv[q] = (rb + q < a.m) ? a.Dt[(size_t)(rb + q) * a.ldd + t * 16 + (lane & 15)] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc[t], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -938,9 +1156,9 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
     if (wv != 0) return;
     double v = 0.0;
     if (rowok) v = p.bt[r0 + lane] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+    const double rinv = rowok ? 1.0 / Rd[lane][lane] : 0.0;
     for (int j = nr - 1; j >= 0; --j) {
-        const double cand = v / Rd[lane][lane];
-        const double yj = __shfl(cand, j, 64);
+        const double yj = __shfl(v * rinv, j, 64);
         if (lane == j) v = yj;
         else if (lane < j) v -= Rd[lane][j] * yj;
     }
@@ -1120,7 +1338,7 @@ __global__ __launch_bounds__(WG) void lg_qrot(LgArgs a) {
 // --------------------------------------------------------------------------
 struct LargeLayout {
     size_t slot, ybuf, Vt, Dt, rot, ocol, lcnt, roff, flt, flg, recomp, rpart, gpart, selv, seli, ctl, ex, misc,
-        wfall, total;
+        ppart, wfall, total;
 };
 
 static LargeLayout large_layout(int m, int n, int kmax) {
@@ -1147,6 +1365,7 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.gpart, sizeof(double) * (size_t)((m + 255) / 256) * 64 * 64);
     put(L.selv, sizeof(double) * 3 * 64);
     put(L.seli, sizeof(int) * 64);
+    put(L.ppart, sizeof(double) * (size_t)(PNW + PNW * (KM + 1) + 8));
     put(L.ctl, sizeof(Ctl));
     put(L.ex, sizeof(LgExtra));
     put(L.misc, 256);
@@ -1157,7 +1376,8 @@ static LargeLayout large_layout(int m, int n, int kmax) {
 
 static size_t large_workspace_bytes(int m, int n, int kmax) { return large_layout(m, n, kmax).total; }
 
-static int colmat_launch(hipStream_t st, const ColmatArgs& ca) {
+static int colmat_launch(hipStream_t st, ColmatArgs ca) {
+    ca.al16 = ((((uintptr_t)ca.X) & 15) == 0) && ((ca.ldx & 1) == 0);
     const int grid = (ca.ncols + 15) / 16;
     if (grid == 0 || ca.nvec <= 0) return 0;
     const int nt = (ca.nvec + 15) / 16;
@@ -1213,6 +1433,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     a.gpart = (double*)(base + L.gpart);
     a.selv = (double*)(base + L.selv);
     a.seli = (int*)(base + L.seli);
+    a.ppart = (double*)(base + L.ppart);
     unsigned long long* anmax_bits = (unsigned long long*)(base + L.misc);
     int* bad = (int*)(base + L.misc + 8);
 
@@ -1285,7 +1506,25 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 0, a.gpart);
             hipLaunchKernelGGL(lg_gram_reduce, dim3(1), dim3(WG), 0, st, a, 0, (const double*)a.gpart);
         }
-        hipLaunchKernelGGL(lg_panel_a, dim3(1), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_greedy, dim3(1), dim3(WG), 0, st, a);
+        {
+            const int mp = m - mir->ctl.nP;
+            int rpw = std::max(64, (mp + PNW - 1) / PNW);
+            rpw = ((rpw + 63) / 64) * 64;
+            const int npw = (mp + rpw - 1) / rpw;
+            const size_t lds = sizeof(double) * (size_t)rpw * (mir->ctl.ncol + 1);
+            static thread_local bool attr_set = false;
+            if (!attr_set) {
+                HIPCHK(hipFuncSetAttribute((const void*)lg_panel_mw, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           PANEL_LDS_MAX));
+                attr_set = true;
+            }
+            if (lds <= (size_t)PANEL_LDS_MAX)
+                hipLaunchKernelGGL(lg_panel_mw, dim3(npw), dim3(WG), lds, st, a, rpw);
+            else
+                hipLaunchKernelGGL(lg_panel_1wg, dim3(1), dim3(WG), 0, st, a);
+        }
+        hipLaunchKernelGGL(lg_panel_v, dim3(64), dim3(WG), 0, st, a);
         if (mir->ctl.ncol > 1) {
             hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 1, a.gpart);
             hipLaunchKernelGGL(lg_gram_reduce, dim3(1), dim3(WG), 0, st, a, 1, (const double*)a.gpart);

@@ -284,3 +284,17 @@ def test_deterministic(lhdm):
     r1 = lhdm.solve(A, b)
     r2 = lhdm.solve(A, b)
     assert torch.equal(r1.x, r2.x) and torch.equal(r1.passive, r2.passive)
+
+
+def test_device_engine_tall_panel_fallback(lhdm):
+    # m large enough that a row chunk of the panel factorisation exceeds LDS:
+    # the single-workgroup panel path; checked through KKT and the final LS subproblem
+    inst = make_small(8256, 8400, 200, 41, kind="uniform", noise_std=1e-2)
+    A, b = _dev(inst.A, inst.b)
+    r = lhdm.solve(A, b, kmax=64)
+    print(f"[tall] {r.info}", flush=True)
+    assert r.info["status"] == 0 and r.info["kkt_residual"] <= KKT
+    x = r.x.cpu().numpy()
+    P = _passive(r)
+    xs, *_ = np.linalg.lstsq(inst.A[:, P], inst.b, rcond=None)
+    assert np.abs(xs - x[P]).max() <= 1e-8 * np.abs(xs).max()
