@@ -26,12 +26,13 @@
 namespace lhdm {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64;
 
 constexpr int TB = 64;          // rows per block of the chained triangular solve
 constexpr int GB = 64;          // new columns per block of the chained downdate
 constexpr int RQ = 64;          // largest number of removals handled in one downdating sweep
 constexpr int RES_CHUNKS = 64;  // column chunks of the residual kernel
-constexpr long long SPIN_LIMIT = 1LL << 26;
+constexpr long long SPIN_LIMIT = 1LL << 21;   // bounded waits: ~2 s of polling, far beyond any chain
 
 struct LgExtra {
     int inner_done;   // set by lg_inner: no more inner iterations this outer step
@@ -45,7 +46,6 @@ struct LgExtra {
     int kadd;         // added directions in the dual update
     int exact;        // 1: norms recomputed from the trailing columns of Q
     int pending;      // removals left over from a sweep capped at RQ positions
-    int bar;          // arrival counter of the multi-workgroup panel factorisation
     int seg_start[RQ + 1];
     int seg_off[RQ + 1];
 };
@@ -60,14 +60,14 @@ struct LgArgs {
     int* ocol;        // kc: old logical column of each new column of the downdate
     int* lcnt;        // kc: rotations of each new column
     int* roff;        // kc: offset of its rotations
-    int* flags_t;     // kc/TB + 1 epochs of the triangular solve
-    int* flags_g;     // kc/GB + 1 epochs of the downdate
+    u64* yll;         // 2 * kc : y published by the chained triangular solve
+    u64* rotll;       // 4 * kc * RQ : rotations published by the chained downdate
     int* recomp;      // n: columns whose projected norm is recomputed exactly
     double* rpart;    // RES_CHUNKS * m residual partial sums
     double* gpart;    // partial Gram matrices (ceil(m / 256) blocks of 64 x 64)
     double* selv;     // 3 * NSEL partial maxima of the selection
     int* seli;        // NSEL partial argmax indices
-    double* ppart;    // panel partials: PNW norms, PNW x (KM + 1) dots, one pivot
+    u64* pll;         // 2 * (PNW + PNW x (KM + 1) + 1) : panel partials (norms, dots, pivot)
 };
 
 // --------------------------------------------------------------------------
@@ -88,36 +88,43 @@ __device__ inline void ctl_store(const WgShared& s, Ctl* g) {
     __syncthreads();
 }
 
-// Cross-workgroup hand-off in the chained kernels.  Data and flags move with
-// relaxed system-scope accesses (sc0 sc1: they bypass the non-coherent caches,
-// no whole-cache writeback or invalidate is issued); the producer waits for its
-// data stores to complete before it stores the flag.
-__device__ inline double sys_ld(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ inline void sys_st(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ inline int sys_ldi(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM); }
-__device__ inline void sys_sti(int* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM); }
-
-// Publish: all of this wave's earlier stores complete, then the flag.
-__device__ inline void publish(int* f, int epoch) {
-    __builtin_amdgcn_s_waitcnt(0);
-    sys_sti(f, epoch);
+// Low-latency hand-off: a double travels as two 8-byte words {32-bit half,
+// epoch}, each stored and loaded as one single-copy-atomic system-scope access.
+// A consumer polls the data itself until both halves carry the current epoch,
+// so no separate flag, store-completion wait or atomic counter is needed.
+// Epochs start at 1 and never repeat on a buffer (buffers are cleared when a
+// workspace is first used).
+__device__ inline void ll_put(u64* slot, double v, int epoch) {
+    const u64 bits = (u64)__double_as_longlong(v);
+    const u64 e = ((u64)(unsigned)epoch) << 32;
+    __hip_atomic_store(slot, e | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(slot + 1, e | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Wave-uniform wait until *f == epoch; gives up (and flags an error) after
-// SPIN_LIMIT polls so that every wave always exits.
-__device__ inline void spin_wait(const int* f, int epoch, int* err) {
+__device__ inline bool ll_try(const u64* slot, int epoch, double& v) {
+    const u64 w0 = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const u64 w1 = __hip_atomic_load(slot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const unsigned e = (unsigned)epoch;
+    if ((unsigned)(w0 >> 32) != e || (unsigned)(w1 >> 32) != e) return false;
+    v = __longlong_as_double((long long)((w1 << 32) | (w0 & 0xffffffffull)));
+    return true;
+}
+
+// Wave-uniform: every lane with `need` waits for its value (bounded wait).
+__device__ inline double ll_get(const u64* slot, bool need, int epoch, int* err) {
+    double v = 0.0;
+    bool ok = !need;
     long long it = 0;
-    while (sys_ldi(f) != epoch) {
+    while (true) {
+        if (!ok) ok = ll_try(slot, epoch, v);
+        if (__all(ok)) break;
         if (++it > SPIN_LIMIT) {
-            atomicExch(err, 1);
+            if ((threadIdx.x & 63) == 0) atomicExch(err, 1);
             break;
         }
         __builtin_amdgcn_s_sleep(1);
     }
+    return v;
 }
 
 // --------------------------------------------------------------------------
@@ -422,41 +429,33 @@ __global__ __launch_bounds__(WG) void lg_greedy(LgArgs a) {
         if (threadIdx.x == 0) s.k = 1;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        s.kr = s.k;
-        sys_sti(&a.ex->bar, 0);
-    }
+    if (threadIdx.x == 0) s.kr = s.k;
     ctl_store(s, a.ctl);
 }
 
 // Householder QR of the panel G[n_P:m, 0:kr] with bt[n_P:m] carried as column
 // kr (Algorithm 4), spread over the workgroups: each owns `rpw` consecutive
 // rows of the panel and keeps them in LDS; the column norm and the dot
-// products with the reflector are summed across workgroups (partials in a
-// fixed order, identical on every workgroup), with two counter barriers per
-// column.
+// products with the reflector are summed across workgroups from epoch-tagged
+// partials, in a fixed order that is identical on every workgroup.
 constexpr int PNW = 32;                  // largest number of workgroups of the panel factorisation
 constexpr int PANEL_LDS_MAX = 128 * 1024;   // dynamic LDS of one workgroup of the panel factorisation
 
-__device__ inline void panel_barrier(int* bar, int target, int* err) {
-    __builtin_amdgcn_s_waitcnt(0);   // this thread's partials are stored
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        long long it = 0;
-        while (sys_ldi(bar) < target) {
-            if (++it > SPIN_LIMIT) {
-                atomicExch(err, 1);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
+// Fixed-order sum of npw published partials at `slots` (stride `stride` words),
+// wave-uniform; every lane returns the same value.
+__device__ inline double ll_sum(const u64* slots, int stride, int npw, int epoch, int* err) {
+    const int lane = threadIdx.x & 63;
+    double tot = 0.0;
+    for (int u0 = 0; u0 < npw; u0 += 64) {
+        const int u = u0 + lane;
+        const double v = ll_get(slots + (size_t)stride * min(u, npw - 1), u < npw, epoch, err);
+        const int cnt = min(64, npw - u0);
+        for (int q = 0; q < cnt; ++q) tot += __shfl(v, q, 64);
     }
-    __syncthreads();
+    return tot;
 }
 
-__global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw) {
+__global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) {
     extern __shared__ double pan[];   // rpw x (kr + 1), row-major
     __shared__ double sv[KM + 1];
     __shared__ double sc[4];
@@ -468,49 +467,49 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw) {
     if (w >= npw) return;
     const int rs = r0 + w * rpw, re = min(m, rs + rpw), nr = re - rs;
     const int ld = kr + 1;
-    const int tid = threadIdx.x;
-    double* NP = a.ppart;                    // [PNW]
-    double* DQ = a.ppart + PNW;              // [PNW][KM + 1]
-    double* X0 = a.ppart + PNW + PNW * (KM + 1);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int* err = &a.ex->err;
+    u64* NPl = a.pll;                              // [PNW] x 2 words
+    u64* DQl = a.pll + 2 * PNW;                    // [PNW][KM + 1] x 2 words
+    u64* X0l = a.pll + 2 * (PNW + PNW * (KM + 1));  // 2 words
     for (int e = tid; e < nr * ld; e += WG) {
         const int i = e / ld, q = e % ld;
         pan[e] = (q < kr) ? p.G[(size_t)q * m + rs + i] : p.bt[rs + i];
     }
     __syncthreads();
-    int phase = 0;
-    // norm partial of column 0 and the pivot entry
+    // phase 0: norm partial of column 0 and the pivot entry
     if (tid == 0) {
         double acc = 0.0;
         for (int i = 0; i < nr; ++i) acc += pan[i * ld] * pan[i * ld];
-        sys_st(&NP[w], acc);
-        if (w == 0) sys_st(X0, pan[0]);
+        ll_put(&NPl[2 * w], acc, ebase);
+        if (w == 0) ll_put(X0l, pan[0], ebase);
     }
-    panel_barrier(&a.ex->bar, (++phase) * npw, &a.ex->err);
     for (int t = 0; t < kr; ++t) {
         const int rt = r0 + t;
-        if (tid == 0) {
-            double nrm2 = 0.0;
-            for (int u = 0; u < npw; ++u) nrm2 += sys_ld(&NP[u]);
-            const double x0 = sys_ld(X0);
-            const double normx = sqrt(nrm2);
-            double tau = 0.0, beta = x0, scal = 0.0;
-            if (normx > 0.0) {
-                beta = (x0 >= 0.0) ? -normx : normx;
-                tau = (beta - x0) / beta;
-                scal = 1.0 / (x0 - beta);
-            }
-            sc[0] = tau;
-            sc[1] = beta;
-            sc[2] = scal;
-            if (w == 0) {
-                a.ctl->tau[t] = tau;
-                a.ctl->beta[t] = beta;
+        const int en = ebase + 2 * t, ed = ebase + 2 * t + 1;
+        if (wv == 0) {
+            const double nrm2 = ll_sum(NPl, 2, npw, en, err);
+            const double x0 = ll_get(X0l, true, en, err);
+            if (lane == 0) {
+                const double normx = sqrt(nrm2);
+                double tau = 0.0, beta = x0, scal = 0.0;
+                if (normx > 0.0) {
+                    beta = (x0 >= 0.0) ? -normx : normx;
+                    tau = (beta - x0) / beta;
+                    scal = 1.0 / (x0 - beta);
+                }
+                sc[0] = tau;
+                sc[1] = beta;
+                sc[2] = scal;
+                if (w == 0) {
+                    a.ctl->tau[t] = tau;
+                    a.ctl->beta[t] = beta;
+                }
             }
         }
         __syncthreads();
         const double tau = sc[0], scal = sc[2];
-        // local rows of this step: global rows >= rt
-        const int i0 = max(0, rt - rs);
+        const int i0 = max(0, rt - rs);   // local rows with global index >= rt
         for (int i = i0 + tid; i < nr; i += WG) {
             if (rs + i == rt) pan[i * ld + t] = 1.0;
             else pan[i * ld + t] *= scal;
@@ -520,13 +519,15 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw) {
         for (int q = t + 1 + tid; q <= kr; q += WG) {
             double acc = 0.0;
             for (int i = i0; i < nr; ++i) acc += pan[i * ld + t] * pan[i * ld + q];
-            sys_st(&DQ[w * (KM + 1) + q], acc);
+            ll_put(&DQl[2 * (w * (KM + 1) + q)], acc, ed);
         }
-        panel_barrier(&a.ex->bar, (++phase) * npw, &a.ex->err);
-        for (int q = t + 1 + tid; q <= kr; q += WG) {
-            double d = 0.0;
-            for (int u = 0; u < npw; ++u) d += sys_ld(&DQ[u * (KM + 1) + q]);
-            sv[q] = tau * d;
+        // fixed-order sums across workgroups: one wave per group of columns
+        for (int q0 = t + 1; q0 <= kr; q0 += NW) {
+            const int q = q0 + wv;
+            if (q <= kr) {
+                const double d = ll_sum(DQl + 2 * q, 2 * (KM + 1), npw, ed, err);
+                if (lane == 0) sv[q] = tau * d;
+            }
         }
         __syncthreads();
         for (int i = i0 + tid; i < nr; i += WG) {
@@ -534,15 +535,12 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw) {
             for (int q = t + 1; q <= kr; ++q) pan[i * ld + q] -= sv[q] * vi;
         }
         __syncthreads();
-        if (t + 1 < kr) {
-            if (tid == 0) {
-                const int j0 = max(0, rt + 1 - rs);
-                double acc = 0.0;
-                for (int i = j0; i < nr; ++i) acc += pan[i * ld + t + 1] * pan[i * ld + t + 1];
-                sys_st(&NP[w], acc);
-                if (rt + 1 >= rs && rt + 1 < re) sys_st(X0, pan[(rt + 1 - rs) * ld + t + 1]);
-            }
-            panel_barrier(&a.ex->bar, (++phase) * npw, &a.ex->err);
+        if (t + 1 < kr && tid == 0) {
+            const int j0 = max(0, rt + 1 - rs);
+            double acc = 0.0;
+            for (int i = j0; i < nr; ++i) acc += pan[i * ld + t + 1] * pan[i * ld + t + 1];
+            ll_put(&NPl[2 * w], acc, ebase + 2 * (t + 1));
+            if (rt + 1 >= rs && rt + 1 < re) ll_put(X0l, pan[(rt + 1 - rs) * ld + t + 1], ebase + 2 * (t + 1));
         }
     }
     for (int e = tid; e < nr * ld; e += WG) {
@@ -1117,9 +1115,10 @@ __global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
 
 // --------------------------------------------------------------------------
 // R y = bt[0:nP]: workgroup g solves row block nb-1-g after the blocks below
-// it have published their part of y.  Each wave of the workgroup takes every
-// fourth dependency block on its own (no workgroup barrier in the loop); the R
-// entries of a dependency block are loaded before its flag is awaited.
+// it have published their part of y (epoch-tagged).  Each wave of the
+// workgroup takes every fourth dependency block on its own (no workgroup
+// barrier in the loop); the R entries of a dependency block are loaded before
+// its part of y is awaited.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
     const Ctl* ctl = a.ctl;
@@ -1146,8 +1145,7 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
 #pragma unroll
         for (int j = 0; j < TB; ++j)
             rv[j] = (j < nc && rowok) ? p.R[(size_t)p.slot[c0 + j] * p.kc + r0 + lane] : 0.0;
-        spin_wait(&a.flags_t[cb], epoch, &a.ex->err);
-        const double yv = (lane < nc) ? sys_ld(&p.ybuf[c0 + lane]) : 0.0;
+        const double yv = ll_get(&a.yll[2 * (c0 + min(lane, nc - 1))], lane < nc, epoch, &a.ex->err);
 #pragma unroll
         for (int j = 0; j < TB; ++j) acc += rv[j] * __shfl(yv, j, 64);
     }
@@ -1162,8 +1160,10 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
         if (lane == j) v = yj;
         else if (lane < j) v -= Rd[lane][j] * yj;
     }
-    if (rowok) sys_st(&p.ybuf[r0 + lane], v);
-    publish(&a.flags_t[b], epoch);
+    if (rowok) {
+        ll_put(&a.yll[2 * (r0 + lane)], v, epoch);
+        p.ybuf[r0 + lane] = v;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -1190,13 +1190,12 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     double* col = p.R + (size_t)p.slot[a.ocol[valid ? idx : 0]] * p.kc;
     for (int bb = 0; bb < b; ++bb) {
         const int e0 = bb * GB, e1 = min(nd, (bb + 1) * GB);
-        spin_wait(&a.flags_g[bb], epoch, &a.ex->err);
         const bool unit = a.lcnt[e0] == 1 && a.lcnt[e1 - 1] == 1 && (e1 - e0) == GB;
         if (unit) {
             // rotations e of this block act on rows (c_e, c_e + 1), c_e = first + e
             const int off = a.roff[e0];
-            rc[lane] = sys_ld(&a.rotbuf[2 * (off + lane)]);
-            rs[lane] = sys_ld(&a.rotbuf[2 * (off + lane) + 1]);
+            rc[lane] = ll_get(&a.rotll[4 * (off + lane)], true, epoch, &a.ex->err);
+            rs[lane] = ll_get(&a.rotll[4 * (off + lane) + 2], true, epoch, &a.ex->err);
             __syncthreads();
             if (valid) {
                 const int rbase = first + e0;
@@ -1219,9 +1218,15 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                 const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
                 for (int g0 = 0; g0 < l2; g0 += GROT_LDS) {
                     const int cntr = min(GROT_LDS, l2 - g0);
-                    for (int u = lane; u < cntr; u += 64) {
-                        rc[u] = sys_ld(&a.rotbuf[2 * (off + g0 + u)]);
-                        rs[u] = sys_ld(&a.rotbuf[2 * (off + g0 + u) + 1]);
+                    for (int u0 = 0; u0 < cntr; u0 += 64) {
+                        const int u = u0 + lane;
+                        const int uu = min(u, cntr - 1);
+                        const double cv = ll_get(&a.rotll[4 * (off + g0 + uu)], u < cntr, epoch, &a.ex->err);
+                        const double sv2 = ll_get(&a.rotll[4 * (off + g0 + uu) + 2], u < cntr, epoch, &a.ex->err);
+                        if (u < cntr) {
+                            rc[u] = cv;
+                            rs[u] = sv2;
+                        }
                     }
                     __syncthreads();
                     if (valid)
@@ -1254,8 +1259,10 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                 const double x0 = x[t], x1 = x[t + 1];
                 x[t] = cs * x0 + sn * x1;
                 x[t + 1] = 0.0;
-                sys_st(&a.rotbuf[2 * (off + t)], cs);
-                sys_st(&a.rotbuf[2 * (off + t) + 1], sn);
+                ll_put(&a.rotll[4 * (off + t)], cs, epoch);
+                ll_put(&a.rotll[4 * (off + t) + 2], sn, epoch);
+                a.rotbuf[2 * (off + t)] = cs;
+                a.rotbuf[2 * (off + t) + 1] = sn;
             }
             cs = __shfl(cs, t, 64);
             sn = __shfl(sn, t, 64);
@@ -1283,8 +1290,10 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                         col[i] = 0.0;
                         rc[u] = cs;
                         rs[u] = sn;
-                        sys_st(&a.rotbuf[2 * (off + g0 + u)], cs);
-                        sys_st(&a.rotbuf[2 * (off + g0 + u) + 1], sn);
+                        ll_put(&a.rotll[4 * (off + g0 + u)], cs, epoch);
+                        ll_put(&a.rotll[4 * (off + g0 + u) + 2], sn, epoch);
+                        a.rotbuf[2 * (off + g0 + u)] = cs;
+                        a.rotbuf[2 * (off + g0 + u) + 1] = sn;
                     }
                 }
                 __syncthreads();
@@ -1299,7 +1308,6 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
             }
         }
     }
-    publish(&a.flags_g[b], epoch);
 }
 
 // The downdate's rotations applied to the columns of Q (one thread per row of Q)
@@ -1350,8 +1358,10 @@ static LargeLayout large_layout(int m, int n, int kmax) {
         off = o;
         o += pad256(bytes);
     };
-    put(L.flt, sizeof(int) * (kc / TB + 2));   // flag buffers first: fixed offsets for a given kc
-    put(L.flg, sizeof(int) * (kc / GB + 2));
+    // hand-off buffers first: fixed offsets for a given kc
+    put(L.flt, sizeof(u64) * 2 * kc);
+    put(L.flg, sizeof(u64) * 4 * kc * RQ);
+    put(L.ppart, sizeof(u64) * 2 * (PNW + PNW * (KM + 1) + 1));
     put(L.slot, slot_bytes(m, n, kmax));
     put(L.ybuf, sizeof(double) * kc);
     put(L.Vt, sizeof(double) * (size_t)m * kq);
@@ -1365,7 +1375,6 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.gpart, sizeof(double) * (size_t)((m + 255) / 256) * 64 * 64);
     put(L.selv, sizeof(double) * 3 * 64);
     put(L.seli, sizeof(int) * 64);
-    put(L.ppart, sizeof(double) * (size_t)(PNW + PNW * (KM + 1) + 8));
     put(L.ctl, sizeof(Ctl));
     put(L.ex, sizeof(LgExtra));
     put(L.misc, 256);
@@ -1426,27 +1435,29 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     a.ocol = (int*)(base + L.ocol);
     a.lcnt = (int*)(base + L.lcnt);
     a.roff = (int*)(base + L.roff);
-    a.flags_t = (int*)(base + L.flt);
-    a.flags_g = (int*)(base + L.flg);
+    a.yll = (u64*)(base + L.flt);
+    a.rotll = (u64*)(base + L.flg);
     a.recomp = (int*)(base + L.recomp);
     a.rpart = (double*)(base + L.rpart);
     a.gpart = (double*)(base + L.gpart);
     a.selv = (double*)(base + L.selv);
     a.seli = (int*)(base + L.seli);
-    a.ppart = (double*)(base + L.ppart);
+    a.pll = (u64*)(base + L.ppart);
     unsigned long long* anmax_bits = (unsigned long long*)(base + L.misc);
     int* bad = (int*)(base + L.misc + 8);
 
     // The chained kernels wait for flag == epoch.  Epochs only grow while the
     // same flag buffers (same workspace, same kc) are reused; anything else
     // clears the flags and restarts the epochs.
+    // The hand-off buffers are matched by epoch.  Epochs only grow while the same
+    // buffers (same workspace, same kc) are reused; anything else clears them and
+    // restarts the epochs.
     static thread_local void* last_ws = nullptr;
     static thread_local int last_kc = -1;
-    static thread_local int ep_t = 0, ep_g = 0;
-    if (last_ws != ws || last_kc != p.kc || ep_t > (1 << 30) || ep_g > (1 << 30)) {
-        HIPCHK(hipMemsetAsync(base + L.flt, 0, pad256(sizeof(int) * (p.kc / TB + 2)), st));
-        HIPCHK(hipMemsetAsync(base + L.flg, 0, pad256(sizeof(int) * (p.kc / GB + 2)), st));
-        ep_t = ep_g = 0;
+    static thread_local int ep_t = 0, ep_g = 0, ep_p = 0;
+    if (last_ws != ws || last_kc != p.kc || ep_t > (1 << 30) || ep_g > (1 << 30) || ep_p > (1 << 22)) {
+        HIPCHK(hipMemsetAsync(base + L.flt, 0, L.slot - L.flt, st));
+        ep_t = ep_g = ep_p = 0;
         last_ws = ws;
         last_kc = p.kc;
     }
@@ -1519,8 +1530,9 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
                                            PANEL_LDS_MAX));
                 attr_set = true;
             }
+            ++ep_p;
             if (lds <= (size_t)PANEL_LDS_MAX)
-                hipLaunchKernelGGL(lg_panel_mw, dim3(npw), dim3(WG), lds, st, a, rpw);
+                hipLaunchKernelGGL(lg_panel_mw, dim3(npw), dim3(WG), lds, st, a, rpw, ep_p * 256);
             else
                 hipLaunchKernelGGL(lg_panel_1wg, dim3(1), dim3(WG), 0, st, a);
         }
