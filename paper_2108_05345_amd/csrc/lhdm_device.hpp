@@ -167,6 +167,15 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
     i = __shfl(i, 0, 64);
 }
 
+// Value of lane `l` (wave-uniform, normally a compile-time constant) of a
+// double, through the scalar unit rather than the LDS crossbar.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Rotation G = [[c, s], [-s, c]] with G [a, b]^T = [r, 0]^T (Algorithm 5's givens).
 __device__ __forceinline__ void givens(double a, double b, double& c, double& s, double& r) {
     if (b == 0.0) {
@@ -178,6 +187,23 @@ __device__ __forceinline__ void givens(double a, double b, double& c, double& s,
     r = hypot(a, b);
     c = a / r;
     s = b / r;
+}
+
+// The same rotation with one reciprocal square root instead of a scaled
+// hypot and two divisions (a few ulp from the correctly rounded c, s, r), for
+// the latency-bound chain of the downdate; inputs whose squares could leave
+// the normal range take the scaled path.
+__device__ __forceinline__ void givens_fast(double a, double b, double& c, double& s, double& r) {
+    const double mx = fmax(fabs(a), fabs(b));
+    if (b != 0.0 && mx > 0x1p-480 && mx < 0x1p480) {
+        const double q = fma(a, a, b * b);
+        const double y = rsqrt(q);
+        c = a * y;
+        s = b * y;
+        r = q * y;
+        return;
+    }
+    givens(a, b, c, s, r);
 }
 
 }  // namespace lhdm

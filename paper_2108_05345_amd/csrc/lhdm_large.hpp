@@ -46,6 +46,9 @@ struct LgExtra {
     int kadd;         // added directions in the dual update
     int exact;        // 1: norms recomputed from the trailing columns of Q
     int pending;      // removals left over from a sweep capped at RQ positions
+    int gident;       // 1: every candidate of the outer step was accepted
+    int ccount;       // candidates collected by the selection (may exceed CAND_CAP)
+    int gmap[KM];     // candidate panel column of accepted column q
     int seg_start[RQ + 1];
     int seg_off[RQ + 1];
 };
@@ -67,7 +70,9 @@ struct LgArgs {
     double* gpart;    // partial Gram matrices (ceil(m / 256) blocks of 64 x 64)
     double* selv;     // 3 * NSEL partial maxima of the selection
     int* seli;        // NSEL partial argmax indices
-    u64* pll;         // 2 * (PNW + PNW x (KM + 1) + 1) : panel partials (norms, dots, pivot)
+    double* candw;    // CAND_CAP: collected candidates' dual values
+    int* candi;       // CAND_CAP: and column indices
+    u64* pll;         // 2 * (2 PNW + 2) x (KM + 1) : panel partials (dots, pivot row)
 };
 
 // --------------------------------------------------------------------------
@@ -111,6 +116,10 @@ __device__ inline bool ll_try(const u64* slot, int epoch, double& v) {
 }
 
 // Wave-uniform: every lane with `need` waits for its value (bounded wait).
+// A wave whose value is not yet on the critical path (URGENT false) polls
+// eight times less often, which keeps the many consumers of one published
+// block from crowding out the one that is waiting for it next.
+template <bool URGENT = true>
 __device__ inline double ll_get(const u64* slot, bool need, int epoch, int* err) {
     double v = 0.0;
     bool ok = !need;
@@ -122,9 +131,34 @@ __device__ inline double ll_get(const u64* slot, bool need, int epoch, int* err)
             if ((threadIdx.x & 63) == 0) atomicExch(err, 1);
             break;
         }
-        __builtin_amdgcn_s_sleep(1);
+        if (URGENT) __builtin_amdgcn_s_sleep(1);
+        else __builtin_amdgcn_s_sleep(8);
     }
     return v;
+}
+
+__device__ inline double ll_get_u(const u64* slot, bool need, int epoch, int* err, bool urgent) {
+    return urgent ? ll_get<true>(slot, need, epoch, err) : ll_get<false>(slot, need, epoch, err);
+}
+
+// Wave-uniform: one lane polls a single word (the last one a producer writes)
+// until it carries `epoch`, at a low rate (bounded wait).  Consumers that are
+// not on the critical path wait here before reading the whole block, so that
+// the uncached polling traffic of many waiting waves stays small.
+__device__ inline void ll_wait_word(const u64* word, int epoch, int* err) {
+    long long it = 0;
+    while (true) {
+        bool ok = true;
+        if ((threadIdx.x & 63) == 0)
+            ok = (unsigned)(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >> 32) ==
+                 (unsigned)epoch;
+        if (__all(ok)) break;
+        if (++it > SPIN_LIMIT) {
+            if ((threadIdx.x & 63) == 0) atomicExch(err, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -208,6 +242,7 @@ __global__ __launch_bounds__(WG) void lg_sel_part(LgArgs a, double* pv, int* pi)
     const int n = p.n, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int per = (n + NSEL - 1) / NSEL;
     const int j0 = blockIdx.x * per, j1 = min(n, j0 + per);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ex->ccount = 0;
     double mwz = -INFINITY, mu = 0.0, bv = -INFINITY;
     int bi = INT_MAX;
     for (int j = j0 + threadIdx.x; j < j1; j += WG) {
@@ -253,17 +288,66 @@ __global__ __launch_bounds__(WG) void lg_sel_part(LgArgs a, double* pv, int* pi)
     }
 }
 
-// Selection, pass 2 (one workgroup): termination test (a1) and Deviation
-// Maximization's candidate list (a2): the columns passing both thresholds are
-// collected in LDS and the first kmax - 1 in (w desc, index asc) order are
-// extracted.  More than CAND_CAP candidates falls back to passes over memory.
+// Selection, pass 2 (NSEL workgroups): Deviation Maximization's candidate
+// filter (a2).  Every workgroup reduces the partial maxima of pass 1 (the same
+// exact maxima everywhere), then appends the columns of its range passing
+// w_j >= tau1 max w and u_j >= tau2 max u to a global list (order immaterial:
+// pass 3 ranks them).
 constexpr int CAND_CAP = 2048;
 
+__global__ __launch_bounds__(WG) void lg_sel_cand(LgArgs a, const double* pv, const int* pi) {
+    const Prob& p = a.p;
+    const DevParams& prm = a.prm;
+    __shared__ double red[2];
+    __shared__ int redi;
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid < 64) {
+        double mu = 0.0, bv = -INFINITY;
+        int bi = INT_MAX;
+        for (int g = lane; g < NSEL; g += 64) {
+            mu = fmax(mu, pv[3 * g + 1]);
+            if (better(pv[3 * g + 2], pi[g], bv, bi)) {
+                bv = pv[3 * g + 2];
+                bi = pi[g];
+            }
+        }
+        mu = wave_max(mu);
+        wave_argmax(bv, bi);
+        if (lane == 0) {
+            red[0] = mu;
+            red[1] = bv;
+            redi = bi;
+        }
+    }
+    __syncthreads();
+    const double mu = red[0], bv = red[1];
+    const int bi = redi;
+    if (bi == INT_MAX || p.m - a.ctl->nP <= 1) return;
+    const double tw = prm.tau1 * bv, tu = prm.tau2 * mu;
+    const int per = (p.n + NSEL - 1) / NSEL;
+    const int j0 = blockIdx.x * per, j1 = min(p.n, j0 + per);
+    for (int j = j0 + tid; j < j1; j += WG) {
+        const int ps = p.pos[j], ex = p.excl[j];
+        const double wj = p.w[j], u2 = p.u2[j], an2 = p.an2[j];
+        if (ps >= 0 || ex || j == bi || !(wj >= tw)) continue;
+        const double u = sqrt(fmax(u2, 0.0));
+        if (!(u >= tu) || !(u > DEP_TOL * sqrt(an2))) continue;
+        const int slot = atomicAdd(&a.ex->ccount, 1);
+        if (slot < CAND_CAP) {
+            a.candw[slot] = wj;
+            a.candi[slot] = j;
+        }
+    }
+}
+
+// Selection, pass 3 (one workgroup): termination test (a1) and the first
+// kmax - 1 collected candidates in (w desc, index asc) order, each placed by
+// its rank among the collected ones.  More than CAND_CAP candidates falls back
+// to passes over memory.
 __global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, const int* pi) {
     __shared__ WgShared s;
     __shared__ double cw[CAND_CAP];
     __shared__ int ci[CAND_CAP];
-    __shared__ int ccount;
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
     const Prob& p = a.p;
@@ -288,7 +372,6 @@ __global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, co
         s.ncol = 1;
         s.J[0] = bi;
         s.nP0 = s.nP;
-        ccount = 0;
         if (mwz == -INFINITY || mwz <= s.tol_w) {
             s.done = 1;
         } else if (bi == INT_MAX || bv <= s.tol_w) {
@@ -301,47 +384,23 @@ __global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, co
     }
     __syncthreads();
     if (!(s.done || prm.lh || prm.kmax <= 1 || cap <= 1)) {
-        const double tw = prm.tau1 * bv, tu = prm.tau2 * mu;
-        for (int j = threadIdx.x; j < p.n; j += WG) {
-            if (p.pos[j] >= 0 || p.excl[j] || j == bi) continue;
-            const double wj = p.w[j];
-            if (!(wj >= tw)) continue;
-            const double u = sqrt(fmax(p.u2[j], 0.0));
-            if (!(u >= tu) || !(u > DEP_TOL * sqrt(p.an2[j]))) continue;
-            const int slotc = atomicAdd(&ccount, 1);
-            if (slotc < CAND_CAP) {
-                cw[slotc] = wj;
-                ci[slotc] = j;
-            }
-        }
-        __syncthreads();
-        const int cnt = ccount;
+        const int cnt = a.ex->ccount;
         if (cnt > CAND_CAP) {
             wg.select();   // rare: many candidates -> passes over memory
         } else {
-            double pvv = bv;
-            int pii = bi;
-            for (int t = 1; t < prm.kmax; ++t) {
-                double cv = -INFINITY;
-                int cj = INT_MAX;
-                for (int e = threadIdx.x; e < cnt; e += WG) {
-                    const double wj = cw[e];
-                    const int j = ci[e];
-                    if (!(wj < pvv || (wj == pvv && j > pii))) continue;
-                    if (better(wj, j, cv, cj)) {
-                        cv = wj;
-                        cj = j;
-                    }
-                }
-                wg.argmax(cv, cj);
-                if (cj == INT_MAX) break;
-                if (threadIdx.x == 0) {
-                    s.J[t] = cj;
-                    s.ncol = t + 1;
-                }
-                pvv = cv;
-                pii = cj;
+            for (int e = threadIdx.x; e < cnt; e += WG) {
+                cw[e] = a.candw[e];
+                ci[e] = a.candi[e];
             }
+            __syncthreads();
+            for (int e = threadIdx.x; e < cnt; e += WG) {
+                const double we = cw[e];
+                const int je = ci[e];
+                int r = 0;
+                for (int f = 0; f < cnt; ++f) r += better(cw[f], ci[f], we, je) ? 1 : 0;
+                if (r < prm.kmax - 1) s.J[1 + r] = je;
+            }
+            if (threadIdx.x == 0) s.ncol = 1 + min(cnt, prm.kmax - 1);
         }
     }
     if (threadIdx.x == 0) s.nP0 = s.nP;
@@ -417,132 +476,222 @@ __global__ __launch_bounds__(WG) void lg_gram_reduce(LgArgs a, int which, const 
     }
 }
 
-// Deviation maximization's greedy test (or the single LH column); resets the
-// arrival counter of the panel factorisation.
+// Deviation maximization's greedy test (Algorithm 2) on the candidates' Gram
+// matrix, or the single column of Lawson-Hanson.  The pairwise cosines are
+// evaluated in parallel into bit masks (bit a of bad[t]: |cos(a, t)| >= delta);
+// the greedy scan in candidate order is then one mask test per candidate.
+// Accepted candidates' panel columns go to gmap; the panel factorisation
+// reads the candidate panel through it.
 __global__ __launch_bounds__(WG) void lg_greedy(LgArgs a) {
     __shared__ WgShared s;
+    __shared__ double Tl[KM][KM + 1];
+    __shared__ double sq[KM];
+    __shared__ unsigned long long bad[KM];
+    __shared__ int gm[KM];
     ctl_load(s, a.ctl);
-    Wg wg(a.p, a.prm, s);
-    if (s.ncol > 1) {
-        wg.greedy_from_gram();
-    } else {
-        if (threadIdx.x == 0) s.k = 1;
+    const Prob& p = a.p;
+    LgExtra* ex = a.ex;
+    const int c = s.ncol, kq = p.kq, tid = threadIdx.x;
+    if (c > 1) {
+        for (int e = tid; e < c * c; e += WG) {
+            const int ra = e / c, t = e % c;
+            Tl[ra][t] = p.T[(size_t)ra * kq + t];
+        }
         __syncthreads();
+        if (tid < c) sq[tid] = sqrt(Tl[tid][tid]);
+        __syncthreads();
+        if (tid < c) {
+            const int t = tid;
+            const double nt = sq[t];
+            unsigned long long msk = 0;
+            for (int ra = 0; ra < t; ++ra) {
+                const double th = Tl[ra][t] / (nt * sq[ra]);
+                if (!(fabs(th) < a.prm.delta)) msk |= 1ull << ra;
+            }
+            bad[t] = msk;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const int cap = p.m - s.nP;
+            unsigned long long acc = 1ull;
+            int na = 1;
+            gm[0] = 0;
+            for (int t = 1; t < c; ++t) {
+                if (na >= cap) break;
+                if ((bad[t] & acc) == 0ull) {
+                    acc |= 1ull << t;
+                    gm[na++] = t;
+                }
+            }
+            for (int q = 0; q < na; ++q) s.J[q] = s.J[gm[q]];
+            s.k = na;
+            ex->gident = (na == c);
+        }
+    } else {
+        if (tid == 0) {
+            s.k = 1;
+            gm[0] = 0;
+            ex->gident = 1;
+        }
     }
-    if (threadIdx.x == 0) s.kr = s.k;
+    __syncthreads();
+    if (tid < s.k) ex->gmap[tid] = gm[tid];
+    if (tid == 0) s.kr = s.k;
     ctl_store(s, a.ctl);
+}
+
+// G[row, q] = G[row, gmap[q]] for q < kr on the rows this thread owns; the
+// whole row is read before any of it is written.
+__device__ inline void compact_panel_row(const Prob& p, const int* gmap, int kr, int row) {
+    double v[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) v[q] = (q < kr) ? p.G[(size_t)gmap[q] * p.m + row] : 0.0;
+#pragma unroll
+    for (int q = 0; q < KM; ++q)
+        if (q < kr) p.G[(size_t)q * p.m + row] = v[q];
 }
 
 // Householder QR of the panel G[n_P:m, 0:kr] with bt[n_P:m] carried as column
 // kr (Algorithm 4), spread over the workgroups: each owns `rpw` consecutive
-// rows of the panel and keeps them in LDS; the column norm and the dot
-// products with the reflector are summed across workgroups from epoch-tagged
-// partials, in a fixed order that is identical on every workgroup.
+// rows of the panel and keeps them in LDS.  One cross-workgroup exchange per
+// column: every workgroup publishes the dots of its part of column t with
+// columns t..kr (the first is the squared norm), the owner of the pivot row
+// publishes that row, and every workgroup sums the partials in one fixed
+// order (so all of them derive bitwise the same reflector).  With x the
+// column below the diagonal, x0 its pivot entry and beta the new diagonal,
+// the scaled reflector v (v0 = 1) satisfies v^T a_q = (x^T a_q - beta a_q0) /
+// (x0 - beta), which is what lets the norm and the dots travel together.
 constexpr int PNW = 32;                  // largest number of workgroups of the panel factorisation
 constexpr int PANEL_LDS_MAX = 128 * 1024;   // dynamic LDS of one workgroup of the panel factorisation
-
-// Fixed-order sum of npw published partials at `slots` (stride `stride` words),
-// wave-uniform; every lane returns the same value.
-__device__ inline double ll_sum(const u64* slots, int stride, int npw, int epoch, int* err) {
-    const int lane = threadIdx.x & 63;
-    double tot = 0.0;
-    for (int u0 = 0; u0 < npw; u0 += 64) {
-        const int u = u0 + lane;
-        const double v = ll_get(slots + (size_t)stride * min(u, npw - 1), u < npw, epoch, err);
-        const int cnt = min(64, npw - u0);
-        for (int q = 0; q < cnt; ++q) tot += __shfl(v, q, 64);
-    }
-    return tot;
-}
+constexpr int PSLOT = KM + 1;            // published values per workgroup and column
+constexpr int PGATHER = ((PNW + 1) * PSLOT + WG - 1) / WG;   // gathered values per thread
 
 __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) {
     extern __shared__ double pan[];   // rpw x (kr + 1), row-major
-    __shared__ double sv[KM + 1];
-    __shared__ double sc[4];
+    __shared__ double red[NW][PSLOT];
+    __shared__ double gat[(PNW + 1) * PSLOT];   // partials of every workgroup, then the pivot row
+    __shared__ double dsum[PSLOT];
     const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
     const int r0 = ctl->nP, kr = ctl->kr, m = p.m;
     const int npw = (m - r0 + rpw - 1) / rpw;
     const int w = blockIdx.x;
-    if (w >= npw) return;
+    const int* gmap = a.ex->gmap;
+    if (w >= npw) {
+        // workgroups past the panel: accepted candidates' rows above the panel
+        const int row = (w - npw) * WG + threadIdx.x;
+        if (!a.ex->gident && row < r0) compact_panel_row(p, gmap, kr, row);
+        return;
+    }
     const int rs = r0 + w * rpw, re = min(m, rs + rpw), nr = re - rs;
     const int ld = kr + 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int* err = &a.ex->err;
-    u64* NPl = a.pll;                              // [PNW] x 2 words
-    u64* DQl = a.pll + 2 * PNW;                    // [PNW][KM + 1] x 2 words
-    u64* X0l = a.pll + 2 * (PNW + PNW * (KM + 1));  // 2 words
+    u64* DQl = a.pll;                          // [2][PNW][PSLOT] x 2 words, by column parity
+    u64* PVl = a.pll + 2 * (2 * PNW * PSLOT);  // [2][PSLOT] x 2 words
     for (int e = tid; e < nr * ld; e += WG) {
         const int i = e / ld, q = e % ld;
-        pan[e] = (q < kr) ? p.G[(size_t)q * m + rs + i] : p.bt[rs + i];
+        pan[e] = (q < kr) ? p.G[(size_t)gmap[q] * m + rs + i] : p.bt[rs + i];
     }
     __syncthreads();
-    // phase 0: norm partial of column 0 and the pivot entry
-    if (tid == 0) {
-        double acc = 0.0;
-        for (int i = 0; i < nr; ++i) acc += pan[i * ld] * pan[i * ld];
-        ll_put(&NPl[2 * w], acc, ebase);
-        if (w == 0) ll_put(X0l, pan[0], ebase);
-    }
     for (int t = 0; t < kr; ++t) {
-        const int rt = r0 + t;
-        const int en = ebase + 2 * t, ed = ebase + 2 * t + 1;
-        if (wv == 0) {
-            const double nrm2 = ll_sum(NPl, 2, npw, en, err);
-            const double x0 = ll_get(X0l, true, en, err);
-            if (lane == 0) {
-                const double normx = sqrt(nrm2);
-                double tau = 0.0, beta = x0, scal = 0.0;
-                if (normx > 0.0) {
-                    beta = (x0 >= 0.0) ? -normx : normx;
-                    tau = (beta - x0) / beta;
-                    scal = 1.0 / (x0 - beta);
-                }
-                sc[0] = tau;
-                sc[1] = beta;
-                sc[2] = scal;
-                if (w == 0) {
-                    a.ctl->tau[t] = tau;
-                    a.ctl->beta[t] = beta;
-                }
-            }
-        }
-        __syncthreads();
-        const double tau = sc[0], scal = sc[2];
+        const int rt = r0 + t, ep = ebase + t, par = t & 1;
         const int i0 = max(0, rt - rs);   // local rows with global index >= rt
-        for (int i = i0 + tid; i < nr; i += WG) {
-            if (rs + i == rt) pan[i * ld + t] = 1.0;
-            else pan[i * ld + t] *= scal;
-        }
-        __syncthreads();
-        // partial dots of the reflector with columns t+1 .. kr (bt is column kr)
-        for (int q = t + 1 + tid; q <= kr; q += WG) {
-            double acc = 0.0;
-            for (int i = i0; i < nr; ++i) acc += pan[i * ld + t] * pan[i * ld + q];
-            ll_put(&DQl[2 * (w * (KM + 1) + q)], acc, ed);
-        }
-        // fixed-order sums across workgroups: one wave per group of columns
-        for (int q0 = t + 1; q0 <= kr; q0 += NW) {
-            const int q = q0 + wv;
-            if (q <= kr) {
-                const double d = ll_sum(DQl + 2 * q, 2 * (KM + 1), npw, ed, err);
-                if (lane == 0) sv[q] = tau * d;
+        const int nq = kr + 1 - t;        // columns t .. kr
+        const bool owner = rt >= rs && rt < re;
+        // local dots of column t with columns t .. kr: lanes take columns,
+        // waves take every fourth row
+        for (int c0 = 0; c0 < nq; c0 += 64) {
+            const int c = c0 + lane;
+            double acc0 = 0.0, acc1 = 0.0;
+            if (c < nq) {
+                int i = i0 + wv;
+                for (; i + NW < nr; i += 2 * NW) {
+                    acc0 += pan[i * ld + t] * pan[i * ld + t + c];
+                    acc1 += pan[(i + NW) * ld + t] * pan[(i + NW) * ld + t + c];
+                }
+                if (i < nr) acc0 += pan[i * ld + t] * pan[i * ld + t + c];
+                red[wv][c] = acc0 + acc1;
             }
         }
         __syncthreads();
-        for (int i = i0 + tid; i < nr; i += WG) {
-            const double vi = pan[i * ld + t];
-            for (int q = t + 1; q <= kr; ++q) pan[i * ld + q] -= sv[q] * vi;
+        for (int c = tid; c < nq; c += WG) {
+            const double d = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+            ll_put(&DQl[2 * ((par * PNW + w) * PSLOT + c)], d, ep);
+            if (owner) ll_put(&PVl[2 * (par * PSLOT + c)], pan[(rt - rs) * ld + t + c], ep);
+        }
+        // gather: value e = u * nq + c is workgroup u's dot with column t + c
+        // (u < npw) or the pivot row entry (u == npw)
+        {
+            const int tot = (npw + 1) * nq;
+            double val[PGATHER];
+            bool ok[PGATHER];
+#pragma unroll
+            for (int k = 0; k < PGATHER; ++k) {
+                val[k] = 0.0;
+                ok[k] = tid + k * WG >= tot;
+            }
+            long long it = 0;
+            while (true) {
+                bool all = true;
+#pragma unroll
+                for (int k = 0; k < PGATHER; ++k) {
+                    if (!ok[k]) {
+                        const int e = tid + k * WG, u = e / nq, c = e % nq;
+                        const u64* slot = (u < npw) ? &DQl[2 * ((par * PNW + u) * PSLOT + c)]
+                                                    : &PVl[2 * (par * PSLOT + c)];
+                        ok[k] = ll_try(slot, ep, val[k]);
+                    }
+                    all = all && ok[k];
+                }
+                if (__all(all)) break;
+                if (++it > SPIN_LIMIT) {
+                    if (lane == 0) atomicExch(err, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+#pragma unroll
+            for (int k = 0; k < PGATHER; ++k) {
+                const int e = tid + k * WG;
+                if (e < tot) gat[(e / nq) * PSLOT + e % nq] = val[k];
+            }
         }
         __syncthreads();
-        if (t + 1 < kr && tid == 0) {
-            const int j0 = max(0, rt + 1 - rs);
-            double acc = 0.0;
-            for (int i = j0; i < nr; ++i) acc += pan[i * ld + t + 1] * pan[i * ld + t + 1];
-            ll_put(&NPl[2 * w], acc, ebase + 2 * (t + 1));
-            if (rt + 1 >= rs && rt + 1 < re) ll_put(X0l, pan[(rt + 1 - rs) * ld + t + 1], ebase + 2 * (t + 1));
+        if (tid < nq) {
+            double d = 0.0;
+            for (int u = 0; u < npw; ++u) d += gat[u * PSLOT + tid];
+            dsum[tid] = d;
         }
+        __syncthreads();
+        const double x0 = gat[npw * PSLOT];
+        const double normx = sqrt(dsum[0]);
+        double tau = 0.0, beta = x0, scal = 0.0;
+        if (normx > 0.0) {
+            beta = (x0 >= 0.0) ? -normx : normx;
+            tau = (beta - x0) / beta;
+            scal = 1.0 / (x0 - beta);
+        }
+        if (w == 0 && tid == 0) {
+            a.ctl->tau[t] = tau;
+            a.ctl->beta[t] = beta;
+        }
+        // apply the reflector to columns t+1 .. kr of the local rows
+        for (int c0 = 1; c0 < nq; c0 += 64) {
+            const int c = c0 + lane;
+            if (c < nq) {
+                const double sq = tau * (scal * (dsum[c] - beta * gat[npw * PSLOT + c]));
+                for (int i = i0 + wv; i < nr; i += NW) {
+                    const double vi = (rs + i == rt) ? 1.0 : pan[i * ld + t] * scal;
+                    pan[i * ld + t + c] -= sq * vi;
+                }
+            }
+        }
+        __syncthreads();
+        // store the scaled reflector in column t (read by no later step)
+        for (int i = i0 + tid; i < nr; i += WG) pan[i * ld + t] = (rs + i == rt) ? 1.0 : pan[i * ld + t] * scal;
     }
+    __syncthreads();
     for (int e = tid; e < nr * ld; e += WG) {
         const int i = e / ld, q = e % ld;
         if (q < kr) p.G[(size_t)q * m + rs + i] = pan[e];
@@ -555,6 +704,9 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
 __global__ __launch_bounds__(WG) void lg_panel_1wg(LgArgs a) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
+    if (!a.ex->gident)
+        for (int row = threadIdx.x; row < a.p.m; row += WG) compact_panel_row(a.p, a.ex->gmap, s.kr, row);
+    __syncthreads();
     Wg wg(a.p, a.prm, s);
     wg.panel_qr();
     ctl_store(s, a.ctl);
@@ -1060,20 +1212,28 @@ __global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
     const int i0 = blockIdx.x * 16;
     const int ntile = (kr + 15) / 16;
     const int myrow = i0 + (lane & 15);
+    // pass 1: W = Q[rows, r0:m] V, U1 column quads per wave in flight
+    constexpr int U1 = 8;
     d4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int l0 = r0 + 4 * wv; l0 < m; l0 += 4 * NW) {
-        const int l = l0 + (lane >> 4);
-        const double av = (myrow < m && l < m) ? p.Q[(size_t)l * m + myrow] : 0.0;   // A[M=row][K=l]
+    for (int l0 = r0 + 4 * wv; l0 < m; l0 += 4 * NW * U1) {
+        double av[U1], bv[U1][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (t < ntile) {
+        for (int u = 0; u < U1; ++u) {
+            const int l = l0 + 4 * NW * u + (lane >> 4);
+            av[u] = (myrow < m && l < m) ? p.Q[(size_t)l * m + myrow] : 0.0;   // A[M=row][K=l]
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
                 const int sc = t * 16 + (lane & 15);
-                const double bv = (l < m && sc < kr) ? p.Vt[(size_t)l * kq + sc] : 0.0;   // B[K=l][N=s]
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                bv[u][t] = (t < ntile && l < m && sc < kr) ? p.Vt[(size_t)l * kq + sc] : 0.0;   // B[K=l][N=s]
             }
         }
+#pragma unroll
+        for (int u = 0; u < U1; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][t], acc[t], 0, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -1095,20 +1255,43 @@ __global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
         W2[rr][sc] = sum;
     }
     __syncthreads();
-    for (int c0 = r0 + 16 * wv; c0 < m; c0 += 16 * NW) {
-        d4 o = d4{0.0, 0.0, 0.0, 0.0};
-        const int cc = c0 + (lane & 15);
-        for (int s0 = 0; s0 < kr; s0 += 4) {
-            const int sc = s0 + (lane >> 4);
-            const double av = (sc < kr && cc < m) ? p.V[(size_t)sc * m + cc] : 0.0;   // A[M=col][K=s]
-            const double bv = (sc < kr) ? W2[lane & 15][sc] : 0.0;                    // B[K=s][N=row]
-            o = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, o, 0, 0, 0);
-        }
-        const int rr = i0 + (lane & 15);
+    // pass 2: Q[rows, r0:m] -= W2 V^T, two 16-column tiles per wave in flight
+    constexpr int U2 = 2;
+    const int rr = i0 + (lane & 15);
+    for (int c0 = r0 + 16 * wv; c0 < m; c0 += 16 * NW * U2) {
+        double qv[U2][4], va[U2][KM / 4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int c2 = c0 + 4 * v + (lane >> 4);
-            if (rr < m && c2 < m) p.Q[(size_t)c2 * m + rr] -= o[v];
+        for (int u = 0; u < U2; ++u) {
+            const int cb = c0 + 16 * NW * u;
+            const int cc = cb + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c2 = cb + 4 * v + (lane >> 4);
+                qv[u][v] = (rr < m && c2 < m) ? p.Q[(size_t)c2 * m + rr] : 0.0;
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < KM / 4; ++s4) {
+                const int sc = 4 * s4 + (lane >> 4);
+                va[u][s4] = (4 * s4 < kr && sc < kr && cc < m) ? p.V[(size_t)sc * m + cc] : 0.0;   // A[M=col][K=s]
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+            const int cb = c0 + 16 * NW * u;
+            d4 o = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < KM / 4; ++s4) {
+                if (4 * s4 < kr) {
+                    const int sc = 4 * s4 + (lane >> 4);
+                    const double bw = (sc < kr) ? W2[lane & 15][sc] : 0.0;   // B[K=s][N=row]
+                    o = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u][s4], bw, o, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c2 = cb + 4 * v + (lane >> 4);
+                if (rr < m && c2 < m) p.Q[(size_t)c2 * m + rr] = qv[u][v] - o[v];
+            }
         }
     }
 }
@@ -1132,33 +1315,65 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
     const int r0 = b * TB, nr = min(nP, r0 + TB) - r0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     __shared__ double part[NW][TB];
+    __shared__ double ys[NW][TB];
     __shared__ double Rd[TB][TB + 1];
-    for (int e = tid; e < TB * TB; e += WG) {
-        const int cc = e / TB, rr = e % TB;
-        Rd[rr][cc] = (cc < nr && rr <= cc) ? p.R[(size_t)p.slot[r0 + cc] * p.kc + r0 + rr] : 0.0;
+    {
+        // diagonal block: four threads per column, one slot lookup each
+        const int cc = tid >> 2, rq = (tid & 3) * (TB / 4);
+        const double* col = (cc < nr) ? p.R + (size_t)p.slot[r0 + cc] * p.kc + r0 : nullptr;
+#pragma unroll
+        for (int u = 0; u < TB / 4; ++u) {
+            const int rr = rq + u;
+            Rd[rr][cc] = (col && rr <= cc) ? col[rr] : 0.0;
+        }
+    }
+    const bool rowok = lane < nr;
+    const double btv = rowok ? p.bt[r0 + lane] : 0.0;
+    __syncthreads();
+    // the wave that receives the last dependency (block b + 1) finishes the
+    // block; it holds row `lane` of the diagonal block, scaled by the inverse
+    // diagonal entry and restricted to the strictly upper part, in registers
+    const int fw = (b == nb - 1) ? 0 : ((nb - 2 - b) & (NW - 1));
+    double rrow[TB];
+    double rinv = 0.0;
+    if (wv == fw) {
+        rinv = rowok ? 1.0 / Rd[lane][lane] : 0.0;
+#pragma unroll
+        for (int j = 0; j < TB; ++j) rrow[j] = (j > lane) ? Rd[lane][j] * rinv : 0.0;
     }
     double acc = 0.0;
-    const bool rowok = lane < nr;
     for (int cb = nb - 1 - wv; cb > b; cb -= NW) {
         const int c0 = cb * TB, nc = min(nP, c0 + TB) - c0;
         double rv[TB];
 #pragma unroll
         for (int j = 0; j < TB; ++j)
             rv[j] = (j < nc && rowok) ? p.R[(size_t)p.slot[c0 + j] * p.kc + r0 + lane] : 0.0;
-        const double yv = ll_get(&a.yll[2 * (c0 + min(lane, nc - 1))], lane < nc, epoch, &a.ex->err);
+        if (cb != b + 1) ll_wait_word(&a.yll[2 * (c0 + nc - 1) + 1], epoch, &a.ex->err);
+        const double yv = ll_get<true>(&a.yll[2 * (c0 + min(lane, nc - 1))], lane < nc, epoch, &a.ex->err);
+        ys[wv][lane] = (lane < nc) ? yv : 0.0;
+        __builtin_amdgcn_wave_barrier();
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-        for (int j = 0; j < TB; ++j) acc += rv[j] * __shfl(yv, j, 64);
+        for (int j = 0; j < TB; j += 4) {
+            a0 += rv[j] * ys[wv][j];
+            a1 += rv[j + 1] * ys[wv][j + 1];
+            a2 += rv[j + 2] * ys[wv][j + 2];
+            a3 += rv[j + 3] * ys[wv][j + 3];
+        }
+        acc += (a0 + a1) + (a2 + a3);
+        __builtin_amdgcn_wave_barrier();
     }
     part[wv][lane] = acc;
     __syncthreads();
-    if (wv != 0) return;
+    if (wv != fw) return;
+    // column-oriented back substitution on the row-scaled block: entry j is
+    // final when step j reads it, and is broadcast through the scalar unit
     double v = 0.0;
-    if (rowok) v = p.bt[r0 + lane] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
-    const double rinv = rowok ? 1.0 / Rd[lane][lane] : 0.0;
-    for (int j = nr - 1; j >= 0; --j) {
-        const double yj = __shfl(v * rinv, j, 64);
-        if (lane == j) v = yj;
-        else if (lane < j) v -= Rd[lane][j] * yj;
+    if (rowok) v = (btv - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane])) * rinv;
+#pragma unroll
+    for (int j = TB - 1; j >= 0; --j) {
+        const double yj = readlane_d(v, j);
+        v = fma(-rrow[j], yj, v);
     }
     if (rowok) {
         ll_put(&a.yll[2 * (r0 + lane)], v, epoch);
@@ -1194,8 +1409,9 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
         if (unit) {
             // rotations e of this block act on rows (c_e, c_e + 1), c_e = first + e
             const int off = a.roff[e0];
-            rc[lane] = ll_get(&a.rotll[4 * (off + lane)], true, epoch, &a.ex->err);
-            rs[lane] = ll_get(&a.rotll[4 * (off + lane) + 2], true, epoch, &a.ex->err);
+            if (bb != b - 1) ll_wait_word(&a.rotll[4 * (off + GB - 1) + 3], epoch, &a.ex->err);
+            rc[lane] = ll_get<true>(&a.rotll[4 * (off + lane)], true, epoch, &a.ex->err);
+            rs[lane] = ll_get<true>(&a.rotll[4 * (off + lane) + 2], true, epoch, &a.ex->err);
             __syncthreads();
             if (valid) {
                 const int rbase = first + e0;
@@ -1221,8 +1437,10 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                     for (int u0 = 0; u0 < cntr; u0 += 64) {
                         const int u = u0 + lane;
                         const int uu = min(u, cntr - 1);
-                        const double cv = ll_get(&a.rotll[4 * (off + g0 + uu)], u < cntr, epoch, &a.ex->err);
-                        const double sv2 = ll_get(&a.rotll[4 * (off + g0 + uu) + 2], u < cntr, epoch, &a.ex->err);
+                        const double cv = ll_get_u(&a.rotll[4 * (off + g0 + uu)], u < cntr, epoch, &a.ex->err,
+                                                   bb == b - 1);
+                        const double sv2 = ll_get_u(&a.rotll[4 * (off + g0 + uu) + 2], u < cntr, epoch,
+                                                    &a.ex->err, bb == b - 1);
                         if (u < cntr) {
                             rc[u] = cv;
                             rs[u] = sv2;
@@ -1255,7 +1473,7 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
             double cs = 1.0, sn = 0.0;
             if (lane == t) {
                 double rr;
-                givens(x[t], x[t + 1], cs, sn, rr);
+                givens_fast(x[t], x[t + 1], cs, sn, rr);
                 const double x0 = x[t], x1 = x[t + 1];
                 x[t] = cs * x0 + sn * x1;
                 x[t + 1] = 0.0;
@@ -1264,8 +1482,8 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                 a.rotbuf[2 * (off + t)] = cs;
                 a.rotbuf[2 * (off + t) + 1] = sn;
             }
-            cs = __shfl(cs, t, 64);
-            sn = __shfl(sn, t, 64);
+            cs = readlane_d(cs, t);
+            sn = readlane_d(sn, t);
             if (lane > t) {
                 const double x0 = x[t], x1 = x[t + 1];
                 x[t] = cs * x0 + sn * x1;
@@ -1285,7 +1503,7 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                         const int i = occ - (g0 + u);
                         const double x0 = col[i - 1], x1 = col[i];
                         double cs, sn, rr;
-                        givens(x0, x1, cs, sn, rr);
+                        givens_fast(x0, x1, cs, sn, rr);
                         col[i - 1] = cs * x0 + sn * x1;
                         col[i] = 0.0;
                         rc[u] = cs;
@@ -1310,42 +1528,100 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     }
 }
 
-// The downdate's rotations applied to the columns of Q (one thread per row of Q)
-// and to bt (one extra thread).
-__global__ __launch_bounds__(WG) void lg_qrot(LgArgs a) {
+// The downdate's rotations applied to the columns of Q and to bt (bt is
+// handled as one more row of Q).  One lane per row; the new columns are taken
+// in chunks of QC.  The rows a chunk's rotations touch, [first + e0, top of its
+// last column], sit in an LDS ring; the rows the next chunk adds are loaded
+// into registers while the current chunk is rotated, and rows no later
+// rotation touches are written back as soon as a chunk ends.  When every new
+// column of a chunk carries one rotation the running row stays in a register.
+constexpr int QC = 64;        // new columns per chunk
+constexpr int QW = 128;       // ring rows: a chunk touches at most QC + RQ rows
+constexpr int QPF = 64;       // rows prefetched into registers per chunk
+
+__global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
+    __shared__ double win[QW][64];
     const LgExtra* ex = a.ex;
     const Prob& p = a.p;
-    const int m = p.m, nd = ex->ndown;
-    const int row = blockIdx.x * WG + threadIdx.x;
-    if (row > m) return;
-    double* base;
-    size_t stride;
-    if (row < m) {
-        base = p.Q + row;
-        stride = (size_t)m;
-    } else {
-        base = p.bt;
-        stride = 1;
-    }
-    for (int e = 0; e < nd; ++e) {
-        const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
-        for (int gg = 0; gg < l2; ++gg) {
-            const int i = occ - gg;
-            const double cs = a.rotbuf[2 * (off + gg)], sn = a.rotbuf[2 * (off + gg) + 1];
-            double* pa = base + (size_t)(i - 1) * stride;
-            double* pb = base + (size_t)i * stride;
-            const double x0 = *pa, x1 = *pb;
-            *pa = cs * x0 + sn * x1;
-            *pb = -sn * x0 + cs * x1;
+    const int m = p.m, nd = ex->ndown, first = ex->first;
+    if (nd <= 0) return;
+    const int lane = threadIdx.x;
+    const int row = blockIdx.x * 64 + lane;
+    const bool valid = row <= m;
+    double* base = (row < m) ? p.Q + row : p.bt;
+    const size_t stride = (row < m) ? (size_t)m : 1;
+    const int* lcnt = a.lcnt;
+    const double* rot = a.rotbuf;
+    const int nch = (nd + QC - 1) / QC;
+    double pf[QPF];
+    int pf_lo = first;
+    int pf_n = min(QPF, first + min(nd, QC) - 1 + lcnt[min(nd, QC) - 1] - first + 1);
+#pragma unroll
+    for (int u = 0; u < QPF; ++u) pf[u] = (u < pf_n && valid) ? base[(size_t)(pf_lo + u) * stride] : 0.0;
+    int have = first - 1;   // rows first + e0 .. have are in the ring
+    for (int ch = 0; ch < nch; ++ch) {
+        const int e0 = ch * QC, e1 = min(nd, e0 + QC);
+        const int need_hi = first + e1 - 1 + lcnt[e1 - 1];
+#pragma unroll
+        for (int u = 0; u < QPF; ++u)
+            if (u < pf_n) win[(pf_lo + u) % QW][lane] = pf[u];
+        have = max(have, pf_lo + pf_n - 1);
+        for (int r = have + 1; r <= need_hi; ++r) win[r % QW][lane] = valid ? base[(size_t)r * stride] : 0.0;
+        have = max(have, need_hi);
+        pf_n = 0;
+        if (ch + 1 < nch) {
+            const int en = min(nd, e1 + QC) - 1;
+            pf_lo = have + 1;
+            pf_n = min(QPF, first + en + lcnt[en] - have);
+#pragma unroll
+            for (int u = 0; u < QPF; ++u)
+                pf[u] = (u < pf_n && valid) ? base[(size_t)(pf_lo + u) * stride] : 0.0;
+        }
+        if (lcnt[e0] == 1 && lcnt[e1 - 1] == 1) {
+            // column e rotates rows (first + e, first + e + 1) with rotation roff[e]
+            const int off = a.roff[e0];
+            double x = win[(first + e0) % QW][lane];
+            double ys[QC];
+#pragma unroll
+            for (int u = 0; u < QC; ++u) ys[u] = (e0 + u < e1) ? win[(first + e0 + u + 1) % QW][lane] : 0.0;
+#pragma unroll
+            for (int u = 0; u < QC; ++u) {
+                if (e0 + u < e1) {
+                    const double cs = rot[2 * (off + u)], sn = rot[2 * (off + u) + 1];
+                    const double y = ys[u];
+                    if (valid) base[(size_t)(first + e0 + u) * stride] = cs * x + sn * y;
+                    x = -sn * x + cs * y;
+                }
+            }
+            win[(first + e1) % QW][lane] = x;
+        } else {
+            for (int e = e0; e < e1; ++e) {
+                // bottom-up: rotation gg acts on rows (op - gg - 1, op - gg)
+                const int L = lcnt[e], off = a.roff[e], op = a.ocol[e];
+                double r = win[op % QW][lane];
+                for (int gg = 0; gg < L; ++gg) {
+                    const int i = op - gg;
+                    const double cs = rot[2 * (off + gg)], sn = rot[2 * (off + gg) + 1];
+                    const double v0 = win[(i - 1) % QW][lane];
+                    win[i % QW][lane] = -sn * v0 + cs * r;
+                    r = cs * v0 + sn * r;
+                }
+                win[(op - L) % QW][lane] = r;
+            }
+            if (valid)
+                for (int rr = first + e0; rr < first + e1; ++rr) base[(size_t)rr * stride] = win[rr % QW][lane];
         }
     }
+    if (valid)
+        for (int rr = first + nd; rr <= have; ++rr) base[(size_t)rr * stride] = win[rr % QW][lane];
 }
 
 // --------------------------------------------------------------------------
 // host driver
 // --------------------------------------------------------------------------
 struct LargeLayout {
-    size_t slot, ybuf, Vt, Dt, rot, ocol, lcnt, roff, flt, flg, recomp, rpart, gpart, selv, seli, ctl, ex, misc,
+    size_t slot, ybuf, Vt, Dt, rot, ocol, lcnt, roff, flt, flg, recomp, rpart, gpart, selv, seli, candw, candi, ctl,
+        ex, misc,
         ppart, wfall, total;
 };
 
@@ -1361,7 +1637,7 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     // hand-off buffers first: fixed offsets for a given kc
     put(L.flt, sizeof(u64) * 2 * kc);
     put(L.flg, sizeof(u64) * 4 * kc * RQ);
-    put(L.ppart, sizeof(u64) * 2 * (PNW + PNW * (KM + 1) + 1));
+    put(L.ppart, sizeof(u64) * 2 * (2 * PNW + 2) * PSLOT);
     put(L.slot, slot_bytes(m, n, kmax));
     put(L.ybuf, sizeof(double) * kc);
     put(L.Vt, sizeof(double) * (size_t)m * kq);
@@ -1375,6 +1651,8 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.gpart, sizeof(double) * (size_t)((m + 255) / 256) * 64 * 64);
     put(L.selv, sizeof(double) * 3 * 64);
     put(L.seli, sizeof(int) * 64);
+    put(L.candw, sizeof(double) * CAND_CAP);
+    put(L.candi, sizeof(int) * CAND_CAP);
     put(L.ctl, sizeof(Ctl));
     put(L.ex, sizeof(LgExtra));
     put(L.misc, 256);
@@ -1442,6 +1720,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     a.gpart = (double*)(base + L.gpart);
     a.selv = (double*)(base + L.selv);
     a.seli = (int*)(base + L.seli);
+    a.candw = (double*)(base + L.candw);
+    a.candi = (int*)(base + L.candi);
     a.pll = (u64*)(base + L.ppart);
     unsigned long long* anmax_bits = (unsigned long long*)(base + L.misc);
     int* bad = (int*)(base + L.misc + 8);
@@ -1491,6 +1771,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     bool stop = mir->ctl.status != LHDM_STATUS_OK;
     while (!stop) {
         hipLaunchKernelGGL(lg_sel_part, dim3(NSEL), dim3(WG), 0, st, a, a.selv, a.seli);
+        if (!prm.lh && prm.kmax > 1)
+            hipLaunchKernelGGL(lg_sel_cand, dim3(NSEL), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli);
         hipLaunchKernelGGL(lg_sel_main, dim3(1), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli);
         HIPCHK(hipGetLastError());
         if ((rc = read_ctl())) return rc;
@@ -1532,7 +1814,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             ++ep_p;
             if (lds <= (size_t)PANEL_LDS_MAX)
-                hipLaunchKernelGGL(lg_panel_mw, dim3(npw), dim3(WG), lds, st, a, rpw, ep_p * 256);
+                hipLaunchKernelGGL(lg_panel_mw, dim3(npw + (mir->ctl.nP + WG - 1) / WG), dim3(WG), lds, st, a, rpw,
+                                   ep_p * 256);
             else
                 hipLaunchKernelGGL(lg_panel_1wg, dim3(1), dim3(WG), 0, st, a);
         }
@@ -1563,7 +1846,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             ++ep_g;
             hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ep_g);
-            hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + WG - 1) / WG), dim3(WG), 0, st, a);
+            hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64), 0, st, a);
             hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a);
             ++ep_t;
             hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t);
