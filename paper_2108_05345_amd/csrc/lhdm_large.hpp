@@ -725,6 +725,14 @@ __global__ __launch_bounds__(WG) void lg_panel_v(LgArgs a) {
             p.Vt[(size_t)row * kq + t] = v;
         }
     }
+    // the new columns of R: rows above the panel from the projection, the
+    // panel's pivot rows, and the new diagonal
+    const int nrow = r0 + kr;
+    for (int e = blockIdx.x * WG + threadIdx.x; e < kr * nrow; e += gridDim.x * WG) {
+        const int t = e / nrow, i = e % nrow;
+        if (i <= r0 + t)
+            p.R[(size_t)p.slot[r0 + t] * p.kc + i] = (i < r0 + t) ? p.G[(size_t)t * m + i] : ctl->beta[t];
+    }
 }
 
 // Compact-WY factor (from V^T V in W), new R columns, feasibility loop on J.
@@ -758,7 +766,6 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a) {
         const int i = e % kq, t = e / kq;
         p.T[(size_t)t * kq + i] = (i < kr) ? Tl[i][t] : 0.0;
     }
-    wg.append_r();
     // feasibility loop on J: longest prefix of J whose own LS components are positive
     const int r0 = s.nP;
     for (int e = tid; e < kr * kr; e += WG) {
@@ -767,18 +774,27 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a) {
     }
     __syncthreads();
     if (tid < 64) {
+        // one wave: row `lane` of R22 scaled by its inverse diagonal entry,
+        // strictly upper part, in registers; back substitution with scalar-unit
+        // broadcasts, repeated for shorter prefixes while a component is <= 0
         const int lane = tid;
+        const bool lk = lane < kr;
+        const double rinv = lk ? 1.0 / Wl[lane][lane] : 0.0;
+        double rrow[KM];
+#pragma unroll
+        for (int j = 0; j < KM; ++j) rrow[j] = (lk && j > lane && j < kr) ? Wl[lane][j] * rinv : 0.0;
+        const double bl = lk ? p.bt[r0 + lane] * rinv : 0.0;
         int k = kr;
-        const double bl = (lane < kr) ? p.bt[r0 + lane] : 0.0;
         while (k > 0) {
             double v = (lane < k) ? bl : 0.0;
             double mn = INFINITY;
-            for (int j = k - 1; j >= 0; --j) {
-                const double cand = v / Wl[lane < k ? lane : 0][lane < k ? lane : 0];
-                const double yj = __shfl(cand, j, 64);
-                mn = fmin(mn, yj);
-                if (lane == j) v = yj;
-                else if (lane < j) v -= Wl[lane][j] * yj;
+#pragma unroll
+            for (int j = KM - 1; j >= 0; --j) {
+                if (j < k) {
+                    const double yj = readlane_d(v, j);
+                    mn = fmin(mn, yj);
+                    v = fma(-rrow[j], yj, v);
+                }
             }
             if (mn > 0.0) break;
             --k;
@@ -1344,10 +1360,15 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
     double acc = 0.0;
     for (int cb = nb - 1 - wv; cb > b; cb -= NW) {
         const int c0 = cb * TB, nc = min(nP, c0 + TB) - c0;
+        // the block's slot indices in one vector load, each broadcast from its
+        // lane, so the 64 column loads wait on a single round trip
+        const int slv = p.slot[c0 + min(lane, nc - 1)];
         double rv[TB];
 #pragma unroll
-        for (int j = 0; j < TB; ++j)
-            rv[j] = (j < nc && rowok) ? p.R[(size_t)p.slot[c0 + j] * p.kc + r0 + lane] : 0.0;
+        for (int j = 0; j < TB; ++j) {
+            const int sj = __builtin_amdgcn_readlane(slv, j);
+            rv[j] = (j < nc && rowok) ? p.R[(size_t)sj * p.kc + r0 + lane] : 0.0;
+        }
         if (cb != b + 1) ll_wait_word(&a.yll[2 * (c0 + nc - 1) + 1], epoch, &a.ex->err);
         const double yv = ll_get<true>(&a.yll[2 * (c0 + min(lane, nc - 1))], lane < nc, epoch, &a.ex->err);
         ys[wv][lane] = (lane < nc) ? yv : 0.0;
@@ -1553,11 +1574,20 @@ __global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
     const int* lcnt = a.lcnt;
     const double* rot = a.rotbuf;
     const int nch = (nd + QC - 1) / QC;
+    const int totrot = ex->totrot;
     double pf[QPF];
     int pf_lo = first;
     int pf_n = min(QPF, first + min(nd, QC) - 1 + lcnt[min(nd, QC) - 1] - first + 1);
 #pragma unroll
     for (int u = 0; u < QPF; ++u) pf[u] = (u < pf_n && valid) ? base[(size_t)(pf_lo + u) * stride] : 0.0;
+    // rotations of a chunk whose columns carry one rotation each: lane u holds
+    // the rotation of column e0 + u (loaded one chunk ahead)
+    double rc_pf, rs_pf;
+    {
+        const int ro = a.roff[0] + lane;
+        rc_pf = (lane < min(nd, QC) && ro < totrot) ? rot[2 * ro] : 1.0;
+        rs_pf = (lane < min(nd, QC) && ro < totrot) ? rot[2 * ro + 1] : 0.0;
+    }
     int have = first - 1;   // rows first + e0 .. have are in the ring
     for (int ch = 0; ch < nch; ++ch) {
         const int e0 = ch * QC, e1 = min(nd, e0 + QC);
@@ -1568,6 +1598,7 @@ __global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
         have = max(have, pf_lo + pf_n - 1);
         for (int r = have + 1; r <= need_hi; ++r) win[r % QW][lane] = valid ? base[(size_t)r * stride] : 0.0;
         have = max(have, need_hi);
+        const double rc_cur = rc_pf, rs_cur = rs_pf;
         pf_n = 0;
         if (ch + 1 < nch) {
             const int en = min(nd, e1 + QC) - 1;
@@ -1576,10 +1607,12 @@ __global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
 #pragma unroll
             for (int u = 0; u < QPF; ++u)
                 pf[u] = (u < pf_n && valid) ? base[(size_t)(pf_lo + u) * stride] : 0.0;
+            const int ro = a.roff[e1] + lane;
+            rc_pf = (e1 + lane <= en && ro < totrot) ? rot[2 * ro] : 1.0;
+            rs_pf = (e1 + lane <= en && ro < totrot) ? rot[2 * ro + 1] : 0.0;
         }
         if (lcnt[e0] == 1 && lcnt[e1 - 1] == 1) {
             // column e rotates rows (first + e, first + e + 1) with rotation roff[e]
-            const int off = a.roff[e0];
             double x = win[(first + e0) % QW][lane];
             double ys[QC];
 #pragma unroll
@@ -1587,7 +1620,7 @@ __global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
 #pragma unroll
             for (int u = 0; u < QC; ++u) {
                 if (e0 + u < e1) {
-                    const double cs = rot[2 * (off + u)], sn = rot[2 * (off + u) + 1];
+                    const double cs = readlane_d(rc_cur, u), sn = readlane_d(rs_cur, u);
                     const double y = ys[u];
                     if (valid) base[(size_t)(first + e0 + u) * stride] = cs * x + sn * y;
                     x = -sn * x + cs * y;
