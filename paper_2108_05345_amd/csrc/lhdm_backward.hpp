@@ -41,7 +41,7 @@ struct BwdShared {
 __global__ __launch_bounds__(WG) void backward_kernel(const BwdIn* __restrict__ ins, char* wsbase) {
     __shared__ BwdShared s;
     const BwdIn in = ins[blockIdx.x];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = wave_index();
     const int m = in.m, n = in.n;
     const int kc = m < n ? m : n;
     double* F = (double*)(wsbase + in.ws_off);        // m x kc: A_P, then its QR

@@ -167,6 +167,19 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
     i = __shfl(i, 0, 64);
 }
 
+// Index of this thread's wave in the workgroup, as a scalar: the compiler then
+// treats conditions on it as uniform (scalar branches, no exec masking).
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Orders this wave's LDS accesses at a point where its lanes exchange data
+// through LDS (emits no instruction: the LDS operations of one wave complete
+// in order; this only keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Value of lane `l` (wave-uniform, normally a compile-time constant) of a
 // double, through the scalar unit rather than the LDS crossbar.
 __device__ __forceinline__ double readlane_d(double v, int l) {

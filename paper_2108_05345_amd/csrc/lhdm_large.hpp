@@ -17,6 +17,7 @@
 #pragma once
 
 #include <climits>
+#include <type_traits>
 #include <vector>
 
 #include "lhdm_device.hpp"
@@ -168,7 +169,7 @@ __device__ inline void ll_wait_word(const u64* word, int epoch, int* err) {
 __global__ __launch_bounds__(WG) void lg_init_cols(LgArgs a, unsigned long long* anmax_bits, int* bad) {
     const Prob& p = a.p;
     const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * NW + (threadIdx.x >> 6);
+    const int j = blockIdx.x * NW + wave_index();
     if (j >= p.n) return;
     const double* col = p.A + (size_t)j * p.lda;
     double ab = 0.0, aa = 0.0;
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(WG) void lg_sel_part(LgArgs a, double* pv, int* pi)
     const Prob& p = a.p;
     __shared__ double sd[3][NW];
     __shared__ int si[NW];
-    const int n = p.n, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = p.n, lane = threadIdx.x & 63, wv = wave_index();
     const int per = (n + NSEL - 1) / NSEL;
     const int j0 = blockIdx.x * per, j1 = min(n, j0 + per);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ex->ccount = 0;
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(WG) void lg_gram_part(LgArgs a, int which, double* 
     const int rs = r0 + blockIdx.x * GRAM_ROWS;
     if (rs >= m || c <= 0) return;
     const int re = min(m, rs + GRAM_ROWS);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_index();
     const int nt = (c + 15) / 16;
     int tile = 0;
     double* out = part + (size_t)blockIdx.x * 64 * 64;
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
     }
     const int rs = r0 + w * rpw, re = min(m, rs + rpw), nr = re - rs;
     const int ld = kr + 1;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_index();
     int* err = &a.ex->err;
     u64* DQl = a.pll;                          // [2][PNW][PSLOT] x 2 words, by column parity
     u64* PVl = a.pll + 2 * (2 * PNW * PSLOT);  // [2][PSLOT] x 2 words
@@ -601,17 +602,24 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
         const bool owner = rt >= rs && rt < re;
         // local dots of column t with columns t .. kr: lanes take columns,
         // waves take every fourth row
+        // (eight rows' loads issued before their products)
         for (int c0 = 0; c0 < nq; c0 += 64) {
             const int c = c0 + lane;
-            double acc0 = 0.0, acc1 = 0.0;
             if (c < nq) {
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
                 int i = i0 + wv;
-                for (; i + NW < nr; i += 2 * NW) {
-                    acc0 += pan[i * ld + t] * pan[i * ld + t + c];
-                    acc1 += pan[(i + NW) * ld + t] * pan[(i + NW) * ld + t + c];
+                for (; i + 7 * NW < nr; i += 8 * NW) {
+                    double xt[8], xq[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        xt[u] = pan[(i + u * NW) * ld + t];
+                        xq[u] = pan[(i + u * NW) * ld + t + c];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[u & 3] += xt[u] * xq[u];
                 }
-                if (i < nr) acc0 += pan[i * ld + t] * pan[i * ld + t + c];
-                red[wv][c] = acc0 + acc1;
+                for (; i < nr; i += NW) acc[0] += pan[i * ld + t] * pan[i * ld + t + c];
+                red[wv][c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
             }
         }
         __syncthreads();
@@ -681,7 +689,22 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
             const int c = c0 + lane;
             if (c < nq) {
                 const double sq = tau * (scal * (dsum[c] - beta * gat[npw * PSLOT + c]));
-                for (int i = i0 + wv; i < nr; i += NW) {
+                int i = i0 + wv;
+                for (; i + 7 * NW < nr; i += 8 * NW) {
+                    double xt[8], xq[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        xt[u] = pan[(i + u * NW) * ld + t];
+                        xq[u] = pan[(i + u * NW) * ld + t + c];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int gi = i + u * NW;
+                        const double vi = (rs + gi == rt) ? 1.0 : xt[u] * scal;
+                        pan[gi * ld + t + c] = xq[u] - sq * vi;
+                    }
+                }
+                for (; i < nr; i += NW) {
                     const double vi = (rs + i == rt) ? 1.0 : pan[i * ld + t] * scal;
                     pan[i * ld + t + c] -= sq * vi;
                 }
@@ -1028,7 +1051,7 @@ __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
     if (a.skip && *a.skip) return;
     __shared__ double part[NW][NT][4][64];
     __shared__ double Ct[16][16 * NT + 1];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_index();
     const int j0 = blockIdx.x * 16;
     const int kk = lane >> 4;
     // columns past the end repeat the last column (their results are dropped)
@@ -1117,6 +1140,116 @@ __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
 
 // Vectors of the dual update, row-major m x 64: vector gv of the whole set is
 // r (gv = 0), an added column of Q (1..kadd) or a dropped/trailing column of Q.
+// Dual pass in one launch when the block holds 18 .. 1 + 16 NT vectors:
+// w = A^T r (vector 0) on the vector units and the dot products of every
+// column of A with vectors 1 .. 16 NT on FP64 MFMA 16x16x4, followed by the
+// projected-norm update.  A workgroup owns 64 columns of A (four 16-column
+// tiles); its waves take interleaved pairs of 8-row steps, so at any time the
+// workgroup reads one contiguous block of rows of its 64 columns and the
+// vector block is read once per workgroup.  Lane (c = l % 16, g = l / 16)
+// reads 16 bytes of its column per step (64 contiguous bytes per column per
+// load instruction).  The waves meet once, to add their partial results.
+template <int NT>
+__global__ __launch_bounds__(WG) void lg_dual2(ColmatArgs a) {
+    if (a.skip && *a.skip) return;
+    constexpr int PF = 2;   // 8-row steps per wave and trip
+    __shared__ double Cs[NW][4][NT][4][64];   // per wave, column tile, vector tile, register, lane
+    __shared__ double Rs[NW][4][64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_index(), g = lane >> 4, cl = lane & 15;
+    const int j0 = blockIdx.x * 64;
+    const double* __restrict__ Dt = a.Dt;
+    const int m = a.m, ldd = a.ldd;
+    const double* xc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xc[c] = a.X + (size_t)min(j0 + 16 * c + cl, a.ncols - 1) * a.ldx;
+    d4 acc[4][NT];
+    double rd[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[c][t] = d4{0.0, 0.0, 0.0, 0.0};
+    auto trip = [&](int s0, auto guard) {
+        constexpr bool G = decltype(guard)::value;
+        double2 v[PF][4];
+        double rv[PF][2], bv[PF][2][NT];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int row = (s0 + u) * 8 + 2 * g;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (!G) {
+                    v[u][c] = *reinterpret_cast<const double2*>(xc[c] + row);
+                } else {
+                    v[u][c].x = (row < m) ? xc[c][row] : 0.0;
+                    v[u][c].y = (row + 1 < m) ? xc[c][row + 1] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bool ok = !G || row + h < m;
+                const double* drow = Dt + (size_t)(ok ? row + h : 0) * ldd;
+                rv[u][h] = ok ? drow[0] : 0.0;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) bv[u][h][t] = ok ? drow[1 + 16 * t + cl] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                rd[c] = fma(v[u][c].x, rv[u][0], rd[c]);
+                rd[c] = fma(v[u][c].y, rv[u][1], rd[c]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][c].x, bv[u][0][t], acc[c][t], 0, 0, 0);
+                    acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][c].y, bv[u][1][t], acc[c][t], 0, 0, 0);
+                }
+            }
+    };
+    // full trips unguarded (16-byte loads need an aligned A, checked by the
+    // host), then the ragged rows with bounds checks
+    const int nst = (m + 7) / 8, nfull = m / 8;
+    int s0 = wv * PF;
+    for (; s0 + PF <= nfull; s0 += NW * PF) trip(s0, std::false_type{});
+    for (; s0 < nst; s0 += NW * PF) trip(s0, std::true_type{});
+    // partial results of the four waves: lane l, register v of a tile holds
+    // column 4 v + l / 16, vector l % 16
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double r = rd[c];
+        r += __shfl_xor(r, 16, 64);
+        r += __shfl_xor(r, 32, 64);
+        Rs[wv][c][lane] = r;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Cs[wv][c][t][v][lane] = acc[c][t][v];
+    }
+    __syncthreads();
+    if (tid >= 64) return;
+    // thread tid: column j0 + tid, i.e. tile tid / 16, column 4 v + l / 16 = tid % 16
+    const int c = tid >> 4, jc = tid & 15, v = jc >> 2;
+    const int j = j0 + tid;
+    if (j >= a.ncols) return;
+    const double rsum = ((Rs[0][c][jc] + Rs[1][c][jc]) + Rs[2][c][jc]) + Rs[3][c][jc];
+    const Prob& p = a.p;
+    p.w[j] = rsum;
+    double u2 = a.exact ? 0.0 : p.u2[j];
+    for (int q = 0; q + 1 < a.nvec; ++q) {
+        // vector 1 + q: tile q / 16, lane (jc % 4) * 16 + q % 16, register v
+        const int t = q >> 4, l = (jc & 3) * 16 + (q & 15);
+        const double d = ((Cs[0][c][t][v][l] + Cs[1][c][t][v][l]) + Cs[2][c][t][v][l]) + Cs[3][c][t][v][l];
+        if (!a.exact && q + 1 <= a.kadd) u2 -= d * d;
+        else u2 += d * d;
+    }
+    u2 = fmax(u2, 0.0);
+    if (!a.exact && p.pos[j] < 0 && u2 < RECOMP_FRAC * p.an2[j]) {
+        const int slotn = atomicAdd(a.nrecomp, 1);
+        a.recomp[slotn] = j;
+    }
+    p.u2[j] = u2;
+}
+
 __global__ __launch_bounds__(WG) void lg_gather_dual(LgArgs a, int v0) {
     const LgExtra* ex = a.ex;
     if (a.ex->restart) return;
@@ -1165,7 +1298,7 @@ __global__ __launch_bounds__(WG) void lg_recompute(LgArgs a) {
     const Prob& p = a.p;
     const int lane = threadIdx.x & 63;
     const int nP = a.ctl->nP;
-    for (int e = blockIdx.x * NW + (threadIdx.x >> 6); e < cnt; e += gridDim.x * NW) {
+    for (int e = blockIdx.x * NW + wave_index(); e < cnt; e += gridDim.x * NW) {
         const int j = a.recomp[e];
         const double* col = p.A + (size_t)j * p.lda;
         double u2 = 0.0;
@@ -1224,7 +1357,7 @@ __global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
     __shared__ double part[NW][4][4][64];
     __shared__ double Wt[16][KM + 1];
     __shared__ double W2[16][KM + 1];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_index();
     const int i0 = blockIdx.x * 16;
     const int ntile = (kr + 15) / 16;
     const int myrow = i0 + (lane & 15);
@@ -1329,7 +1462,7 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
     if (g >= nb) return;
     const int b = nb - 1 - g;
     const int r0 = b * TB, nr = min(nP, r0 + TB) - r0;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_index();
     __shared__ double part[NW][TB];
     __shared__ double ys[NW][TB];
     __shared__ double Rd[TB][TB + 1];
@@ -1372,7 +1505,7 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
         if (cb != b + 1) ll_wait_word(&a.yll[2 * (c0 + nc - 1) + 1], epoch, &a.ex->err);
         const double yv = ll_get<true>(&a.yll[2 * (c0 + min(lane, nc - 1))], lane < nc, epoch, &a.ex->err);
         ys[wv][lane] = (lane < nc) ? yv : 0.0;
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
         for (int j = 0; j < TB; j += 4) {
@@ -1382,7 +1515,7 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
             a3 += rv[j + 3] * ys[wv][j + 3];
         }
         acc += (a0 + a1) + (a2 + a3);
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();
     }
     part[wv][lane] = acc;
     __syncthreads();
@@ -1406,11 +1539,32 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
 // Algorithm 5 on R.  Block b (one wave) owns new columns first + 64 b .. +64:
 // it applies, in order, the rotations published by every earlier block to its
 // columns, then generates its own column by column (bottom-up within a column)
-// and publishes them.  When every column of a block carries one rotation (a
-// single removal in this stretch) the 65 rows a block touches are held in
-// registers; otherwise rotations are applied entry by entry in memory.
+// and publishes them.  A block whose columns carry one rotation each (a single
+// removal in this stretch) keeps the 65 rows it touches in registers; any
+// other block keeps the at most 64 + RQ rows it touches in an LDS window.
+// Block metadata (rotation counts, offsets, old columns) is read one column
+// per lane and broadcast by readlane, so no scalar load sits on the chain.
 // --------------------------------------------------------------------------
-constexpr int GROT_LDS = 512;   // rotations of one block staged in LDS per chunk
+constexpr int GW = GB + RQ;   // rows of a block's LDS window
+
+// Rotation zeroing b in (a, b) on every lane without branching; the scaled
+// path is taken (uniformly) only when the lane that matters needs it.
+__device__ __forceinline__ void givens_lane(double a, double b, int t, double& c, double& s) {
+    const double mx = fmax(fabs(a), fabs(b));
+    const double q = fma(a, a, b * b);
+    const double y = rsqrt(q);
+    c = a * y;
+    s = b * y;
+    if (b == 0.0) {
+        c = 1.0;
+        s = 0.0;
+    }
+    const bool bad = (b != 0.0) && !(mx > 0x1p-480 && mx < 0x1p480);
+    if (__builtin_amdgcn_readlane((int)bad, t)) {
+        double r;
+        givens(a, b, c, s, r);
+    }
+}
 
 __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     const LgExtra* ex = a.ex;
@@ -1422,129 +1576,136 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     const int lane = threadIdx.x;
     const int idx = b * GB + lane;
     const bool valid = idx < nd;
-    __shared__ double rc[GROT_LDS], rs[GROT_LDS];
+    int* err = &a.ex->err;
+    __shared__ double win[GW][64];
+    __shared__ double rcl[RQ], rsl[RQ];
     double* col = p.R + (size_t)p.slot[a.ocol[valid ? idx : 0]] * p.kc;
-    for (int bb = 0; bb < b; ++bb) {
-        const int e0 = bb * GB, e1 = min(nd, (bb + 1) * GB);
-        const bool unit = a.lcnt[e0] == 1 && a.lcnt[e1 - 1] == 1 && (e1 - e0) == GB;
+    for (int bb = 0; bb <= b; ++bb) {
+        const bool own = bb == b;
+        const int e0 = bb * GB, e1 = min(nd, e0 + GB), ne = e1 - e0;
+        const int ml = e0 + min(lane, ne - 1);
+        const int lc_l = a.lcnt[ml], ro_l = a.roff[ml], oc_l = a.ocol[ml];
+        const int lc_last = __builtin_amdgcn_readlane(lc_l, ne - 1);
+        const bool unit = __builtin_amdgcn_readlane(lc_l, 0) == 1 && lc_last == 1 && ne == GB;
+        const int off = __builtin_amdgcn_readlane(ro_l, 0);
+        const int rlo = first + e0;
         if (unit) {
-            // rotations e of this block act on rows (c_e, c_e + 1), c_e = first + e
-            const int off = a.roff[e0];
-            if (bb != b - 1) ll_wait_word(&a.rotll[4 * (off + GB - 1) + 3], epoch, &a.ex->err);
-            rc[lane] = ll_get<true>(&a.rotll[4 * (off + lane)], true, epoch, &a.ex->err);
-            rs[lane] = ll_get<true>(&a.rotll[4 * (off + lane) + 2], true, epoch, &a.ex->err);
-            __syncthreads();
-            if (valid) {
-                const int rbase = first + e0;
-                double x[GB + 1];
+            // rotation e of this block acts on rows (rlo + e, rlo + e + 1)
+            double x[GB + 1];
 #pragma unroll
-                for (int r = 0; r <= GB; ++r) x[r] = col[rbase + r];
+            for (int r = 0; r <= GB; ++r) x[r] = valid ? col[rlo + r] : 0.0;
+            if (!own) {
+                if (bb != b - 1) ll_wait_word(&a.rotll[4 * (off + GB - 1) + 3], epoch, err);
+                const double rcv = ll_get<true>(&a.rotll[4 * (off + lane)], true, epoch, err);
+                const double rsv = ll_get<true>(&a.rotll[4 * (off + lane) + 2], true, epoch, err);
 #pragma unroll
                 for (int e = 0; e < GB; ++e) {
-                    const double cs = rc[e], sn = rs[e];
+                    const double cs = readlane_d(rcv, e), sn = readlane_d(rsv, e);
                     const double x0 = x[e], x1 = x[e + 1];
                     x[e] = cs * x0 + sn * x1;
                     x[e + 1] = -sn * x0 + cs * x1;
                 }
+            } else {
+                // every lane evaluates a rotation from its own entries; lane t's is used
+                double mc = 1.0, ms = 0.0;
 #pragma unroll
-                for (int r = 0; r <= GB; ++r) col[rbase + r] = x[r];
+                for (int t = 0; t < GB; ++t) {
+                    double cs, sn;
+                    givens_lane(x[t], x[t + 1], t, cs, sn);
+                    cs = readlane_d(cs, t);
+                    sn = readlane_d(sn, t);
+                    if (lane == t) {
+                        mc = cs;
+                        ms = sn;
+                    }
+                    if (lane >= t) {
+                        const double x0 = x[t], x1 = x[t + 1];
+                        x[t] = cs * x0 + sn * x1;
+                        x[t + 1] = (lane == t) ? 0.0 : -sn * x0 + cs * x1;
+                    }
+                }
+                ll_put(&a.rotll[4 * (off + lane)], mc, epoch);
+                ll_put(&a.rotll[4 * (off + lane) + 2], ms, epoch);
+                a.rotbuf[2 * (off + lane)] = mc;
+                a.rotbuf[2 * (off + lane) + 1] = ms;
             }
-            __syncthreads();
+            if (valid) {
+#pragma unroll
+                for (int r = 0; r <= GB; ++r) col[rlo + r] = x[r];
+            }
         } else {
-            for (int e = e0; e < e1; ++e) {
-                const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
-                for (int g0 = 0; g0 < l2; g0 += GROT_LDS) {
-                    const int cntr = min(GROT_LDS, l2 - g0);
-                    for (int u0 = 0; u0 < cntr; u0 += 64) {
-                        const int u = u0 + lane;
-                        const int uu = min(u, cntr - 1);
-                        const double cv = ll_get_u(&a.rotll[4 * (off + g0 + uu)], u < cntr, epoch, &a.ex->err,
-                                                   bb == b - 1);
-                        const double sv2 = ll_get_u(&a.rotll[4 * (off + g0 + uu) + 2], u < cntr, epoch,
-                                                    &a.ex->err, bb == b - 1);
-                        if (u < cntr) {
-                            rc[u] = cv;
-                            rs[u] = sv2;
+            // rows rlo .. rhi of this lane's column in the LDS window
+            const int rhi = rlo + ne - 1 + lc_last;
+            for (int r = rlo; r <= rhi; ++r) win[r - rlo][lane] = valid ? col[r] : 0.0;
+            wave_lds_sync();
+            if (!own) {
+                const int kend = __builtin_amdgcn_readlane(ro_l, ne - 1) + lc_last;   // rotations [off, kend)
+                if (bb != b - 1 && kend > off) ll_wait_word(&a.rotll[4 * (kend - 1) + 3], epoch, err);
+                int kc0 = INT_MIN / 2;
+                double rcv = 1.0, rsv = 0.0;
+                for (int e = 0; e < ne; ++e) {
+                    const int L = __builtin_amdgcn_readlane(lc_l, e), op = __builtin_amdgcn_readlane(oc_l, e);
+                    const int ko = __builtin_amdgcn_readlane(ro_l, e);
+                    if (L == 0) continue;
+                    double run = win[op - rlo][lane];
+                    for (int gg = 0; gg < L; ++gg) {
+                        const int k = ko + gg;
+                        if (k >= kc0 + 64) {
+                            kc0 = k;
+                            const int kk = min(k + lane, kend - 1);
+                            rcv = ll_get<true>(&a.rotll[4 * kk], k + lane < kend, epoch, err);
+                            rsv = ll_get<true>(&a.rotll[4 * kk + 2], k + lane < kend, epoch, err);
                         }
+                        const double cs = readlane_d(rcv, k - kc0), sn = readlane_d(rsv, k - kc0);
+                        const int i = op - gg;
+                        const double v0 = win[i - 1 - rlo][lane];
+                        win[i - rlo][lane] = -sn * v0 + cs * run;
+                        run = cs * v0 + sn * run;
                     }
-                    __syncthreads();
-                    if (valid)
-                        for (int u = 0; u < cntr; ++u) {
-                            const int i = occ - (g0 + u);
-                            const double x0 = col[i - 1], x1 = col[i];
-                            col[i - 1] = rc[u] * x0 + rs[u] * x1;
-                            col[i] = -rs[u] * x0 + rc[u] * x1;
+                    win[op - L - rlo][lane] = run;
+                }
+            } else {
+                for (int e = 0; e < ne; ++e) {
+                    const int L = __builtin_amdgcn_readlane(lc_l, e), op = __builtin_amdgcn_readlane(oc_l, e);
+                    const int ko = __builtin_amdgcn_readlane(ro_l, e);
+                    if (L == 0) continue;
+                    if (lane == e) {
+                        // bottom-up: zero rows op, op - 1, ..., op - L + 1 of this column
+                        double run = win[op - rlo][lane];
+                        for (int gg = 0; gg < L; ++gg) {
+                            const int i = op - gg;
+                            const double v0 = win[i - 1 - rlo][lane];
+                            double cs, sn, rr;
+                            givens_fast(v0, run, cs, sn, rr);
+                            win[i - rlo][lane] = 0.0;
+                            run = cs * v0 + sn * run;
+                            rcl[gg] = cs;
+                            rsl[gg] = sn;
+                            ll_put(&a.rotll[4 * (ko + gg)], cs, epoch);
+                            ll_put(&a.rotll[4 * (ko + gg) + 2], sn, epoch);
+                            a.rotbuf[2 * (ko + gg)] = cs;
+                            a.rotbuf[2 * (ko + gg) + 1] = sn;
                         }
-                    __syncthreads();
+                        win[op - L - rlo][lane] = run;
+                    }
+                    wave_lds_sync();
+                    if (lane > e && valid) {
+                        double run = win[op - rlo][lane];
+                        for (int gg = 0; gg < L; ++gg) {
+                            const double cs = rcl[gg], sn = rsl[gg];
+                            const int i = op - gg;
+                            const double v0 = win[i - 1 - rlo][lane];
+                            win[i - rlo][lane] = -sn * v0 + cs * run;
+                            run = cs * v0 + sn * run;
+                        }
+                        win[op - L - rlo][lane] = run;
+                    }
+                    wave_lds_sync();
                 }
             }
-        }
-    }
-    const int e0 = b * GB, e1 = min(nd, (b + 1) * GB);
-    const bool unit = a.lcnt[e0] == 1 && a.lcnt[e1 - 1] == 1 && (e1 - e0) == GB;
-    if (unit) {
-        // own block in registers: rotation t acts on rows (first + e0 + t, +1)
-        const int rbase = first + e0;
-        const int off = a.roff[e0];
-        double x[GB + 1];
-#pragma unroll
-        for (int r = 0; r <= GB; ++r) x[r] = col[rbase + r];
-#pragma unroll
-        for (int t = 0; t < GB; ++t) {
-            double cs = 1.0, sn = 0.0;
-            if (lane == t) {
-                double rr;
-                givens_fast(x[t], x[t + 1], cs, sn, rr);
-                const double x0 = x[t], x1 = x[t + 1];
-                x[t] = cs * x0 + sn * x1;
-                x[t + 1] = 0.0;
-                ll_put(&a.rotll[4 * (off + t)], cs, epoch);
-                ll_put(&a.rotll[4 * (off + t) + 2], sn, epoch);
-                a.rotbuf[2 * (off + t)] = cs;
-                a.rotbuf[2 * (off + t) + 1] = sn;
-            }
-            cs = readlane_d(cs, t);
-            sn = readlane_d(sn, t);
-            if (lane > t) {
-                const double x0 = x[t], x1 = x[t + 1];
-                x[t] = cs * x0 + sn * x1;
-                x[t + 1] = -sn * x0 + cs * x1;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r <= GB; ++r) col[rbase + r] = x[r];
-    } else {
-        for (int e = e0; e < e1; ++e) {
-            const int t = e - e0;
-            const int l2 = a.lcnt[e], off = a.roff[e], occ = a.ocol[e];
-            for (int g0 = 0; g0 < l2; g0 += GROT_LDS) {
-                const int cntr = min(GROT_LDS, l2 - g0);
-                if (lane == t) {
-                    for (int u = 0; u < cntr; ++u) {
-                        const int i = occ - (g0 + u);
-                        const double x0 = col[i - 1], x1 = col[i];
-                        double cs, sn, rr;
-                        givens_fast(x0, x1, cs, sn, rr);
-                        col[i - 1] = cs * x0 + sn * x1;
-                        col[i] = 0.0;
-                        rc[u] = cs;
-                        rs[u] = sn;
-                        ll_put(&a.rotll[4 * (off + g0 + u)], cs, epoch);
-                        ll_put(&a.rotll[4 * (off + g0 + u) + 2], sn, epoch);
-                        a.rotbuf[2 * (off + g0 + u)] = cs;
-                        a.rotbuf[2 * (off + g0 + u) + 1] = sn;
-                    }
-                }
-                __syncthreads();
-                if (valid && lane > t)
-                    for (int u = 0; u < cntr; ++u) {
-                        const int i = occ - (g0 + u);
-                        const double x0 = col[i - 1], x1 = col[i];
-                        col[i - 1] = rc[u] * x0 + rs[u] * x1;
-                        col[i] = -rs[u] * x0 + rc[u] * x1;
-                    }
-                __syncthreads();
-            }
+            wave_lds_sync();
+            if (valid)
+                for (int r = rlo; r <= rhi; ++r) col[r] = win[r - rlo][lane];
         }
     }
 }
@@ -1898,6 +2059,35 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         hipLaunchKernelGGL(lg_dual_plan, dim3(1), dim3(64), 0, st, a);
         for (int v0 = 0; v0 < nvec; v0 += 64) {
             hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, st, a, v0);
+            const bool al16 = ((((uintptr_t)A) & 15) == 0) && ((lda & 1) == 0);
+            if (al16 && nvec >= 18 && nvec <= 49) {
+                // the whole block in one pass
+                ColmatArgs ca{};
+                ca.X = A;
+                ca.ldx = lda;
+                ca.m = m;
+                ca.ncols = n;
+                ca.Dt = a.Dt;
+                ca.ldd = 64;
+                ca.mode = MODE_DUAL;
+                ca.nvec = nvec;
+                ca.v0 = 0;
+                ca.vtot = nvec;
+                ca.kadd = kadd;
+                ca.exact = exact;
+                ca.p = p;
+                ca.recomp = a.recomp;
+                ca.nrecomp = &a.ex->nrecomp;
+                ca.al16 = ((((uintptr_t)A) & 15) == 0) && ((lda & 1) == 0);
+                const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
+                const int ev = kprof_begin(st);
+                const dim3 g((n + 63) / 64);
+                if (nvec <= 33) hipLaunchKernelGGL(lg_dual2<2>, g, dim3(WG), 0, st, ca);
+                else hipLaunchKernelGGL(lg_dual2<3>, g, dim3(WG), 0, st, ca);
+                HIPCHK(hipGetLastError());
+                kprof_end(st, ev, bytes);
+                break;
+            }
             ColmatArgs ca{};
             ca.X = A;
             ca.ldx = lda;

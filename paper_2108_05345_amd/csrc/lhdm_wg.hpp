@@ -41,7 +41,7 @@ struct Wg {
     double* yv;   // least-squares solution by position: LDS (workgroup engine) or global
 
     __device__ Wg(Prob& p_, const DevParams& prm_, WgShared& s_)
-        : p(p_), prm(prm_), s(s_), tid(threadIdx.x), lane(threadIdx.x & 63), wid(threadIdx.x >> 6),
+        : p(p_), prm(prm_), s(s_), tid(threadIdx.x), lane(threadIdx.x & 63), wid(wave_index()),
           yv(p_.ybuf ? p_.ybuf : s_.y) {}
 
     // ---------------- workgroup reductions ----------------
