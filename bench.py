@@ -9,7 +9,8 @@ delta sweep); plain LH on the same instance gives the speedup.  One step = one
 complete solve (every step of the method, initialisation to KKT).
 
 Prints one JSON line.  Extra objects: ``roofline`` for the dominant kernel (the
-dual GEMV fused with the projected-norm update, timed live with HIP events),
+dual pass, w = A^T r fused with the projected-norm update, timed live with HIP
+events on the solve's stream),
 ``cpu_baseline`` (the CPU oracle on a bounded sample of the same solve) and
 ``lh`` (the plain Lawson-Hanson timing).
 """
@@ -156,7 +157,7 @@ def main():
         traffic = measured_traffic()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "lg_colmat_dot (dual w = A^T r fused with the projected-norm update)",
+                "kernel": "dual pass: lg_dual2 / lg_colmat_dot (w = A^T r fused with the projected-norm update)",
                 "launches": int(kl.value), "avg_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": bytes_per}
 
