@@ -1579,7 +1579,8 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     int* err = &a.ex->err;
     __shared__ double win[GW][64];
     __shared__ double rcl[RQ], rsl[RQ];
-    double* col = p.R + (size_t)p.slot[a.ocol[valid ? idx : 0]] * p.kc;
+    // lanes past the last new column read the last one's storage (never written)
+    double* col = p.R + (size_t)p.slot[a.ocol[valid ? idx : nd - 1]] * p.kc;
     for (int bb = 0; bb <= b; ++bb) {
         const bool own = bb == b;
         const int e0 = bb * GB, e1 = min(nd, e0 + GB), ne = e1 - e0;
@@ -1593,7 +1594,7 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
             // rotation e of this block acts on rows (rlo + e, rlo + e + 1)
             double x[GB + 1];
 #pragma unroll
-            for (int r = 0; r <= GB; ++r) x[r] = valid ? col[rlo + r] : 0.0;
+            for (int r = 0; r <= GB; ++r) x[r] = col[rlo + r];
             if (!own) {
                 if (bb != b - 1) ll_wait_word(&a.rotll[4 * (off + GB - 1) + 3], epoch, err);
                 const double rcv = ll_get<true>(&a.rotll[4 * (off + lane)], true, epoch, err);
@@ -1636,7 +1637,15 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
         } else {
             // rows rlo .. rhi of this lane's column in the LDS window
             const int rhi = rlo + ne - 1 + lc_last;
-            for (int r = rlo; r <= rhi; ++r) win[r - rlo][lane] = valid ? col[r] : 0.0;
+            for (int r0 = rlo; r0 <= rhi; r0 += 8) {
+                // eight loads in flight before their LDS writes
+                double tmp[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) tmp[u] = (r0 + u <= rhi) ? col[r0 + u] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (r0 + u <= rhi) win[r0 + u - rlo][lane] = tmp[u];
+            }
             wave_lds_sync();
             if (!own) {
                 const int kend = __builtin_amdgcn_readlane(ro_l, ne - 1) + lc_last;   // rotations [off, kend)
@@ -1757,7 +1766,14 @@ __global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
         for (int u = 0; u < QPF; ++u)
             if (u < pf_n) win[(pf_lo + u) % QW][lane] = pf[u];
         have = max(have, pf_lo + pf_n - 1);
-        for (int r = have + 1; r <= need_hi; ++r) win[r % QW][lane] = valid ? base[(size_t)r * stride] : 0.0;
+        for (int r0 = have + 1; r0 <= need_hi; r0 += 8) {
+            double tmp[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tmp[u] = (valid && r0 + u <= need_hi) ? base[(size_t)(r0 + u) * stride] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (r0 + u <= need_hi) win[(r0 + u) % QW][lane] = tmp[u];
+        }
         have = max(have, need_hi);
         const double rc_cur = rc_pf, rs_cur = rs_pf;
         pf_n = 0;
@@ -1871,9 +1887,16 @@ static int colmat_launch(hipStream_t st, ColmatArgs ca) {
 }
 
 // Host copy of the control words read at each decision point.
+// Host copy of the control block and the leading int fields of LgExtra, laid
+// out as in the workspace (LgExtra starts at the next 256-byte boundary after
+// Ctl) so that one transfer brings both.
+constexpr size_t CTL_SPAN = (sizeof(Ctl) + 255) / 256 * 256;
 struct Mirror {
-    Ctl ctl;
-    int ex_head[16];   // the leading int fields of LgExtra
+    union {
+        Ctl ctl;
+        char raw[CTL_SPAN];
+    };
+    int ex_head[16];
 };
 
 static int large_solve(hipStream_t st, int m, int n, const double* A, long long lda, const double* b,
@@ -1902,6 +1925,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     a.prm = prm;
     a.ctl = (Ctl*)(base + L.ctl);
     a.ex = (LgExtra*)(base + L.ex);
+    if (L.ex - L.ctl != CTL_SPAN) return LHDM_EINVAL;   // Mirror assumes this spacing
     a.Dt = (double*)(base + L.Dt);
     a.rotbuf = (double*)(base + L.rot);
     a.ocol = (int*)(base + L.ocol);
@@ -1939,8 +1963,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     if (!mir) HIPCHK(hipHostMalloc((void**)&mir, sizeof(Mirror), hipHostMallocDefault));
 
     auto read_ctl = [&]() -> int {
-        HIPCHK(hipMemcpyAsync(&mir->ctl, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(mir->ex_head, a.ex, sizeof(mir->ex_head), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(mir, a.ctl, sizeof(Mirror), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         kprof_drain();
         const LgExtra* hx = reinterpret_cast<const LgExtra*>(mir->ex_head);
