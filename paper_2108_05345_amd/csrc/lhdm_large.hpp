@@ -6,7 +6,7 @@
 //                       FP64 matrix cores (v_mfma_f64_16x16x4f64).  Used for the
 //                       dual w = A^T r fused with the update of the projected
 //                       column norms, and for the candidate projection Q^T A_J.
-//   * lg_qupdate     -- Q[:, n_P:m] <- Q[:, n_P:m] (I - V T V^T) (compact WY).
+//   * lg_qup1/2      -- Q[:, n_P:m] <- Q[:, n_P:m] (I - V T V^T) (compact WY).
 //   * lg_trsv        -- R y = (Q^T b)[:n_P], row blocks chained by device flags.
 //   * lg_givens      -- Algorithm 5 on R: column blocks chained by device flags.
 //   * lg_qrot        -- the same rotations applied to the columns of Q.
@@ -74,6 +74,7 @@ struct LgArgs {
     double* candw;    // CAND_CAP: collected candidates' dual values
     int* candi;       // CAND_CAP: and column indices
     u64* pll;         // 2 * (2 PNW + 2) x (KM + 1) : panel partials (dots, pivot row)
+    double* wpart;    // ceil(m / QCB) x kq x m : pass-1 partial products of the Q update
 };
 
 // --------------------------------------------------------------------------
@@ -1349,52 +1350,106 @@ __global__ __launch_bounds__(WG) void lg_residual_sum(LgArgs a) {
 // the columns of Q_t), W2 = W T.  Pass 2: Q_t -= W2 V^T, computed transposed
 // so that each store covers 16 consecutive rows of a column of Q.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
+// Q[:, n_P:m] <- Q[:, n_P:m] (I - V T V^T) in two passes over the trailing
+// columns.  Pass 1: W = Q_t V on FP64 MFMA, tile by tile.  Pass 2 (16 rows
+// of Q per workgroup): W = the sum of the tiles' partial products, W2 = W T,
+// then Q_t -= W2 V^T, four 16-column tiles in flight per wave.
+constexpr int QRB = 128;  // rows per tile of pass 1
+constexpr int QCB = 256;  // trailing columns per tile of pass 1
+constexpr int QU1 = 16;   // 4-column steps in flight per wave (pass 1)
+constexpr int QU2 = 4;    // 16-column tiles in flight per wave (pass 2)
+
+// Pass 1 on a tile of QRB rows x QCB trailing columns: wave w owns rows
+// 32 w .. 32 w + 31 of the tile (two 16-row MFMA tiles) and all its columns, so
+// together the waves read 1 KB of every column of the tile.  The tile's
+// product with V (QRB x kr) goes to its slot of wpart; pass 2 adds the slots.
+__global__ __launch_bounds__(WG) void lg_qup1(LgArgs a) {
     const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
     const int kr = ctl->kr, r0 = ctl->nP0, m = p.m, kq = p.kq;
     if (kr == 0) return;
-    __shared__ double part[NW][4][4][64];
+    const int cb = blockIdx.y;
+    const int c0 = r0 + cb * QCB, c1 = min(m, c0 + QCB);
+    if (c0 >= m) return;
+    const int lane = threadIdx.x & 63, wv = wave_index();
+    const int ntile = (kr + 15) / 16;
+    const int rbase = blockIdx.x * QRB + 32 * wv;
+    int rows[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) rows[h] = min(rbase + 16 * h + (lane & 15), m - 1);
+    d4 acc[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[h][t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = c0; l0 < c1; l0 += 4 * QU1) {
+        double av[QU1][2], bv[QU1][2];
+#pragma unroll
+        for (int u = 0; u < QU1; ++u) {
+            const int l = l0 + 4 * u + (lane >> 4);
+            const bool ok = l < c1;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) av[u][h] = ok ? p.Q[(size_t)l * m + rows[h]] : 0.0;   // A[M=row][K=l]
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int sc = t * 16 + (lane & 15);
+                bv[u][t] = (ok && sc < kr) ? p.Vt[(size_t)l * kq + sc] : 0.0;   // B[K=l][N=s]
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < QU1; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    if (t < ntile) acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][h], bv[u][t], acc[h][t], 0, 0, 0);
+        if (ntile > 2) {
+            // panels wider than 32 columns: the remaining tiles, loads reissued
+#pragma unroll
+            for (int u = 0; u < QU1; ++u) {
+                const int l = l0 + 4 * u + (lane >> 4);
+#pragma unroll
+                for (int t = 2; t < 4; ++t) {
+                    const int sc = t * 16 + (lane & 15);
+                    const double b = (l < c1 && sc < kr) ? p.Vt[(size_t)l * kq + sc] : 0.0;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        if (t < ntile) acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][h], b, acc[h][t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // lane l, register v of a tile: row 4 v + l / 16 of the 16-row tile, vector l % 16
+    double* wp = a.wpart + (size_t)cb * kq * m;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (t < ntile)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rbase + 16 * h + 4 * v + (lane >> 4), sc = t * 16 + (lane & 15);
+                    if (row < m && sc < kr) wp[(size_t)sc * m + row] = acc[h][t][v];
+                }
+}
+
+template <int NS4>   // 4-wide steps over the panel columns: 8 (kr <= 32) or 16 (kr <= 64)
+__global__ __launch_bounds__(WG) void lg_qup2(LgArgs a) {
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int kr = ctl->kr, r0 = ctl->nP0, m = p.m, kq = p.kq;
+    if (kr == 0) return;
     __shared__ double Wt[16][KM + 1];
     __shared__ double W2[16][KM + 1];
     const int lane = threadIdx.x & 63, wv = wave_index();
     const int i0 = blockIdx.x * 16;
-    const int ntile = (kr + 15) / 16;
-    const int myrow = i0 + (lane & 15);
-    // pass 1: W = Q[rows, r0:m] V, U1 column quads per wave in flight
-    constexpr int U1 = 8;
-    d4 acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int l0 = r0 + 4 * wv; l0 < m; l0 += 4 * NW * U1) {
-        double av[U1], bv[U1][4];
-#pragma unroll
-        for (int u = 0; u < U1; ++u) {
-            const int l = l0 + 4 * NW * u + (lane >> 4);
-            av[u] = (myrow < m && l < m) ? p.Q[(size_t)l * m + myrow] : 0.0;   // A[M=row][K=l]
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int sc = t * 16 + (lane & 15);
-                bv[u][t] = (t < ntile && l < m && sc < kr) ? p.Vt[(size_t)l * kq + sc] : 0.0;   // B[K=l][N=s]
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U1; ++u)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][t], acc[t], 0, 0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) part[wv][t][v][lane] = acc[t][v];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < ntile * 256; idx += WG) {
-        const int t = idx / 256, v = (idx / 64) % 4, l = idx % 64;
-        double sum = part[0][t][v][l];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) sum += part[w][t][v][l];
-        Wt[4 * v + (l >> 4)][t * 16 + (l & 15)] = sum;   // row 4v + l/16, reflector t*16 + l%16
+    const int ncb = (m - r0 + QCB - 1) / QCB;   // column tiles of pass 1
+    for (int e = threadIdx.x; e < 16 * kr; e += WG) {
+        const int rr = e % 16, sc = e / 16;
+        double w = 0.0;
+        if (i0 + rr < m)
+            for (int cb = 0; cb < ncb; ++cb) w += a.wpart[((size_t)cb * kq + sc) * m + i0 + rr];
+        Wt[rr][sc] = w;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 16 * kr; e += WG) {
@@ -1404,13 +1459,11 @@ __global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
         W2[rr][sc] = sum;
     }
     __syncthreads();
-    // pass 2: Q[rows, r0:m] -= W2 V^T, two 16-column tiles per wave in flight
-    constexpr int U2 = 2;
     const int rr = i0 + (lane & 15);
-    for (int c0 = r0 + 16 * wv; c0 < m; c0 += 16 * NW * U2) {
-        double qv[U2][4], va[U2][KM / 4];
+    for (int c0 = r0 + 16 * wv; c0 < m; c0 += 16 * NW * QU2) {
+        double qv[QU2][4], va[QU2][NS4];
 #pragma unroll
-        for (int u = 0; u < U2; ++u) {
+        for (int u = 0; u < QU2; ++u) {
             const int cb = c0 + 16 * NW * u;
             const int cc = cb + (lane & 15);
 #pragma unroll
@@ -1419,17 +1472,17 @@ __global__ __launch_bounds__(WG) void lg_qupdate(LgArgs a) {
                 qv[u][v] = (rr < m && c2 < m) ? p.Q[(size_t)c2 * m + rr] : 0.0;
             }
 #pragma unroll
-            for (int s4 = 0; s4 < KM / 4; ++s4) {
+            for (int s4 = 0; s4 < NS4; ++s4) {
                 const int sc = 4 * s4 + (lane >> 4);
                 va[u][s4] = (4 * s4 < kr && sc < kr && cc < m) ? p.V[(size_t)sc * m + cc] : 0.0;   // A[M=col][K=s]
             }
         }
 #pragma unroll
-        for (int u = 0; u < U2; ++u) {
+        for (int u = 0; u < QU2; ++u) {
             const int cb = c0 + 16 * NW * u;
             d4 o = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int s4 = 0; s4 < KM / 4; ++s4) {
+            for (int s4 = 0; s4 < NS4; ++s4) {
                 if (4 * s4 < kr) {
                     const int sc = 4 * s4 + (lane >> 4);
                     const double bw = (sc < kr) ? W2[lane & 15][sc] : 0.0;   // B[K=s][N=row]
@@ -1832,7 +1885,7 @@ __global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
 struct LargeLayout {
     size_t slot, ybuf, Vt, Dt, rot, ocol, lcnt, roff, flt, flg, recomp, rpart, gpart, selv, seli, candw, candi, ctl,
         ex, misc,
-        ppart, wfall, total;
+        ppart, wfall, wpart, total;
 };
 
 static LargeLayout large_layout(int m, int n, int kmax) {
@@ -1867,6 +1920,7 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.ex, sizeof(LgExtra));
     put(L.misc, 256);
     put(L.wfall, sizeof(double) * (size_t)n);
+    put(L.wpart, sizeof(double) * (size_t)((m + QCB - 1) / QCB) * kq * m);
     L.total = o;
     return L;
 }
@@ -1935,6 +1989,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     a.rotll = (u64*)(base + L.flg);
     a.recomp = (int*)(base + L.recomp);
     a.rpart = (double*)(base + L.rpart);
+    a.wpart = (double*)(base + L.wpart);
     a.gpart = (double*)(base + L.gpart);
     a.selv = (double*)(base + L.selv);
     a.seli = (int*)(base + L.seli);
@@ -2042,7 +2097,9 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             hipLaunchKernelGGL(lg_gram_reduce, dim3(1), dim3(WG), 0, st, a, 1, (const double*)a.gpart);
         }
         hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, st, a);
-        hipLaunchKernelGGL(lg_qupdate, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, st, a);
+        if (mir->ctl.ncol <= 32) hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+        else hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, st, a);
         ++ep_t;
