@@ -390,17 +390,49 @@ __global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, co
         if (cnt > CAND_CAP) {
             wg.select();   // rare: many candidates -> passes over memory
         } else {
-            for (int e = threadIdx.x; e < cnt; e += WG) {
-                cw[e] = a.candw[e];
-                ci[e] = a.candi[e];
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < cnt; e += WG) {
-                const double we = cw[e];
-                const int je = ci[e];
-                int r = 0;
-                for (int f = 0; f < cnt; ++f) r += better(cw[f], ci[f], we, je) ? 1 : 0;
-                if (r < prm.kmax - 1) s.J[1 + r] = je;
+            if (cnt <= 256) {
+                for (int e = threadIdx.x; e < cnt; e += WG) {
+                    cw[e] = a.candw[e];
+                    ci[e] = a.candi[e];
+                }
+                __syncthreads();
+                for (int e = threadIdx.x; e < cnt; e += WG) {
+                    const double we = cw[e];
+                    const int je = ci[e];
+                    int r = 0;
+                    for (int f = 0; f < cnt; ++f) r += better(cw[f], ci[f], we, je) ? 1 : 0;
+                    if (r < prm.kmax - 1) s.J[1 + r] = je;
+                }
+            } else {
+                // bitonic sort of the padded list, best first
+                int nn = 512;
+                while (nn < cnt) nn <<= 1;
+                for (int e = threadIdx.x; e < nn; e += WG) {
+                    cw[e] = (e < cnt) ? a.candw[e] : -INFINITY;
+                    ci[e] = (e < cnt) ? a.candi[e] : INT_MAX;
+                }
+                __syncthreads();
+                for (int k = 2; k <= nn; k <<= 1) {
+                    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                        for (int e = threadIdx.x; e < nn; e += WG) {
+                            const int l = e ^ jj;
+                            if (l > e) {
+                                const bool first_better = better(cw[e], ci[e], cw[l], ci[l]);
+                                const bool want_first = (e & k) == 0;   // this run sorts best first
+                                if (first_better != want_first) {
+                                    const double tw = cw[e];
+                                    const int ti = ci[e];
+                                    cw[e] = cw[l];
+                                    ci[e] = ci[l];
+                                    cw[l] = tw;
+                                    ci[l] = ti;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+                for (int r = threadIdx.x; r < min(cnt, prm.kmax - 1); r += WG) s.J[1 + r] = ci[r];
             }
             if (threadIdx.x == 0) s.ncol = 1 + min(cnt, prm.kmax - 1);
         }
