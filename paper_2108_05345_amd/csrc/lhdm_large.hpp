@@ -1805,36 +1805,68 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
 }
 
 // The downdate's rotations applied to the columns of Q and to bt (bt is
-// handled as one more row of Q).  One lane per row; the new columns are taken
-// in chunks of QC.  The rows a chunk's rotations touch, [first + e0, top of its
-// last column], sit in an LDS ring; the rows the next chunk adds are loaded
-// into registers while the current chunk is rotated, and rows no later
-// rotation touches are written back as soon as a chunk ends.  When every new
-// column of a chunk carries one rotation the running row stays in a register.
+// handled as one more row of Q).  One lane per row; a workgroup holds 64 rows
+// and 1 + QNL waves.  The loader waves stream the rows' entries in the touched
+// columns of Q (blocks of QLB columns, loader l takes blocks l, l + QNL, ...)
+// into an LDS ring of QW columns; the rotating wave takes the new columns in
+// chunks of QC, waits until the loaders have delivered every column its chunk
+// touches, rotates in the ring (the running entry of a stretch of single
+// rotations stays in a register) and writes back the columns no later
+// rotation touches.  Ring columns are reused only below the lowest column the
+// rotating wave still needs; every wait is bounded.
 constexpr int QC = 64;        // new columns per chunk
-constexpr int QW = 128;       // ring rows: a chunk touches at most QC + RQ rows
-constexpr int QPF = 64;       // rows prefetched into registers per chunk
+constexpr int QW = 256;       // ring columns (a chunk touches at most QC + RQ)
+constexpr int QNL = 3;        // loader waves
+constexpr int QLB = 64;       // columns per loader block
 
-__global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
+__global__ __launch_bounds__(64 * (1 + QNL)) void lg_qrot(LgArgs a) {
     __shared__ double win[QW][64];
+    __shared__ int lprog[QNL];   // blocks completed by each loader
+    __shared__ int consumed;     // lowest column the rotating wave still needs
     const LgExtra* ex = a.ex;
     const Prob& p = a.p;
     const int m = p.m, nd = ex->ndown, first = ex->first;
     if (nd <= 0) return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = wave_index();
     const int row = blockIdx.x * 64 + lane;
     const bool valid = row <= m;
     double* base = (row < m) ? p.Q + row : p.bt;
     const size_t stride = (row < m) ? (size_t)m : 1;
     const int* lcnt = a.lcnt;
     const double* rot = a.rotbuf;
+    int* err = &a.ex->err;
+    const int rend = first + nd - 1 + lcnt[nd - 1];   // highest column touched
+    if (threadIdx.x < QNL) lprog[threadIdx.x] = 0;
+    if (threadIdx.x == 0) consumed = first;
+    __syncthreads();
+    if (wv > 0) {
+        // loader wave l = wv - 1
+        const int l = wv - 1;
+        int done = 0;
+        for (int k = l; first + k * QLB <= rend; k += QNL) {
+            const int cb = first + k * QLB;
+            long long it = 0;
+            while (cb + QLB - 1 - __hip_atomic_load(&consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= QW) {
+                if (++it > SPIN_LIMIT) {
+                    if (lane == 0) atomicExch(err, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            double v[QLB];
+#pragma unroll
+            for (int u = 0; u < QLB; ++u) v[u] = (valid && cb + u <= rend) ? base[(size_t)(cb + u) * stride] : 0.0;
+#pragma unroll
+            for (int u = 0; u < QLB; ++u)
+                if (cb + u <= rend) win[(cb + u) % QW][lane] = v[u];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            ++done;
+            if (lane == 0) __hip_atomic_store(&lprog[l], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        return;
+    }
     const int nch = (nd + QC - 1) / QC;
     const int totrot = ex->totrot;
-    double pf[QPF];
-    int pf_lo = first;
-    int pf_n = min(QPF, first + min(nd, QC) - 1 + lcnt[min(nd, QC) - 1] - first + 1);
-#pragma unroll
-    for (int u = 0; u < QPF; ++u) pf[u] = (u < pf_n && valid) ? base[(size_t)(pf_lo + u) * stride] : 0.0;
     // rotations of a chunk whose columns carry one rotation each: lane u holds
     // the rotation of column e0 + u (loaded one chunk ahead)
     double rc_pf, rs_pf;
@@ -1843,47 +1875,47 @@ __global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
         rc_pf = (lane < min(nd, QC) && ro < totrot) ? rot[2 * ro] : 1.0;
         rs_pf = (lane < min(nd, QC) && ro < totrot) ? rot[2 * ro + 1] : 0.0;
     }
-    int have = first - 1;   // rows first + e0 .. have are in the ring
     for (int ch = 0; ch < nch; ++ch) {
         const int e0 = ch * QC, e1 = min(nd, e0 + QC);
         const int need_hi = first + e1 - 1 + lcnt[e1 - 1];
-#pragma unroll
-        for (int u = 0; u < QPF; ++u)
-            if (u < pf_n) win[(pf_lo + u) % QW][lane] = pf[u];
-        have = max(have, pf_lo + pf_n - 1);
-        for (int r0 = have + 1; r0 <= need_hi; r0 += 8) {
-            double tmp[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) tmp[u] = (valid && r0 + u <= need_hi) ? base[(size_t)(r0 + u) * stride] : 0.0;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (r0 + u <= need_hi) win[(r0 + u) % QW][lane] = tmp[u];
-        }
-        have = max(have, need_hi);
         const double rc_cur = rc_pf, rs_cur = rs_pf;
-        pf_n = 0;
         if (ch + 1 < nch) {
             const int en = min(nd, e1 + QC) - 1;
-            pf_lo = have + 1;
-            pf_n = min(QPF, first + en + lcnt[en] - have);
-#pragma unroll
-            for (int u = 0; u < QPF; ++u)
-                pf[u] = (u < pf_n && valid) ? base[(size_t)(pf_lo + u) * stride] : 0.0;
             const int ro = a.roff[e1] + lane;
             rc_pf = (e1 + lane <= en && ro < totrot) ? rot[2 * ro] : 1.0;
             rs_pf = (e1 + lane <= en && ro < totrot) ? rot[2 * ro + 1] : 0.0;
         }
+        // wait until every block up to the one holding column need_hi is in the ring
+        {
+            const int kmax = (need_hi - first) / QLB;
+            long long it = 0;
+            while (true) {
+                bool ok = true;
+#pragma unroll
+                for (int l = 0; l < QNL; ++l) {
+                    if (kmax >= l) {
+                        const int need_blocks = (kmax - l) / QNL + 1;
+                        ok = ok && __hip_atomic_load(&lprog[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >=
+                                       need_blocks;
+                    }
+                }
+                if (ok) break;
+                if (++it > SPIN_LIMIT) {
+                    if (lane == 0) atomicExch(err, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        }
         if (lcnt[e0] == 1 && lcnt[e1 - 1] == 1) {
             // column e rotates rows (first + e, first + e + 1) with rotation roff[e]
             double x = win[(first + e0) % QW][lane];
-            double ys[QC];
-#pragma unroll
-            for (int u = 0; u < QC; ++u) ys[u] = (e0 + u < e1) ? win[(first + e0 + u + 1) % QW][lane] : 0.0;
 #pragma unroll
             for (int u = 0; u < QC; ++u) {
                 if (e0 + u < e1) {
                     const double cs = readlane_d(rc_cur, u), sn = readlane_d(rs_cur, u);
-                    const double y = ys[u];
+                    const double y = win[(first + e0 + u + 1) % QW][lane];
                     if (valid) base[(size_t)(first + e0 + u) * stride] = cs * x + sn * y;
                     x = -sn * x + cs * y;
                 }
@@ -1906,9 +1938,12 @@ __global__ __launch_bounds__(64) void lg_qrot(LgArgs a) {
             if (valid)
                 for (int rr = first + e0; rr < first + e1; ++rr) base[(size_t)rr * stride] = win[rr % QW][lane];
         }
+        // columns below first + e1 are final: their ring slots may be reused
+        wave_lds_sync();
+        if (lane == 0) __hip_atomic_store(&consumed, first + e1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     if (valid)
-        for (int rr = first + nd; rr <= have; ++rr) base[(size_t)rr * stride] = win[rr % QW][lane];
+        for (int rr = first + nd; rr <= rend; ++rr) base[(size_t)rr * stride] = win[rr % QW][lane];
 }
 
 // --------------------------------------------------------------------------
@@ -2152,7 +2187,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             ++ep_g;
             hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ep_g);
-            hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64), 0, st, a);
+            hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a);
             hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a);
             ++ep_t;
             hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t);
