@@ -1182,12 +1182,12 @@ __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
 // vector block is read once per workgroup.  Lane (c = l % 16, g = l / 16)
 // reads 16 bytes of its column per step (64 contiguous bytes per column per
 // load instruction).  The waves meet once, to add their partial results.
-template <int NT>
-__global__ __launch_bounds__(WG) void lg_dual2(ColmatArgs a) {
+template <int NT, int NWV, int PF>   // PF: 8-row steps per wave and trip
+__global__ __launch_bounds__(64 * NWV) void lg_dual2(ColmatArgs a) {
+    static_assert(NWV == 4 || NWV == 8, "four or eight waves");
     if (a.skip && *a.skip) return;
-    constexpr int PF = 2;   // 8-row steps per wave and trip
-    __shared__ double Cs[NW][4][NT][4][64];   // per wave, column tile, vector tile, register, lane
-    __shared__ double Rs[NW][4][64];
+    __shared__ double Cs[4][4][NT][4][64];   // per wave, column tile, vector tile, register, lane
+    __shared__ double Rs[4][4][64];
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_index(), g = lane >> 4, cl = lane & 15;
     const int j0 = blockIdx.x * 64;
     const double* __restrict__ Dt = a.Dt;
@@ -1201,62 +1201,120 @@ __global__ __launch_bounds__(WG) void lg_dual2(ColmatArgs a) {
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[c][t] = d4{0.0, 0.0, 0.0, 0.0};
-    auto trip = [&](int s0, auto guard) {
-        constexpr bool G = decltype(guard)::value;
+    struct Buf {
         double2 v[PF][4];
         double rv[PF][2], bv[PF][2][NT];
+    };
+    auto ld = [&](int s0, Buf& B, auto guard) {
+        constexpr bool G = decltype(guard)::value;
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int row = (s0 + u) * 8 + 2 * g;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 if (!G) {
-                    v[u][c] = *reinterpret_cast<const double2*>(xc[c] + row);
+                    B.v[u][c] = *reinterpret_cast<const double2*>(xc[c] + row);
                 } else {
-                    v[u][c].x = (row < m) ? xc[c][row] : 0.0;
-                    v[u][c].y = (row + 1 < m) ? xc[c][row + 1] : 0.0;
+                    B.v[u][c].x = (row < m) ? xc[c][row] : 0.0;
+                    B.v[u][c].y = (row + 1 < m) ? xc[c][row + 1] : 0.0;
                 }
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const bool ok = !G || row + h < m;
                 const double* drow = Dt + (size_t)(ok ? row + h : 0) * ldd;
-                rv[u][h] = ok ? drow[0] : 0.0;
+                B.rv[u][h] = ok ? drow[0] : 0.0;
 #pragma unroll
-                for (int t = 0; t < NT; ++t) bv[u][h][t] = ok ? drow[1 + 16 * t + cl] : 0.0;
+                for (int t = 0; t < NT; ++t) B.bv[u][h][t] = ok ? drow[1 + 16 * t + cl] : 0.0;
             }
         }
+    };
+    auto mm = [&](const Buf& B) {
 #pragma unroll
         for (int u = 0; u < PF; ++u)
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                rd[c] = fma(v[u][c].x, rv[u][0], rd[c]);
-                rd[c] = fma(v[u][c].y, rv[u][1], rd[c]);
+                rd[c] = fma(B.v[u][c].x, B.rv[u][0], rd[c]);
+                rd[c] = fma(B.v[u][c].y, B.rv[u][1], rd[c]);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][c].x, bv[u][0][t], acc[c][t], 0, 0, 0);
-                    acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][c].y, bv[u][1][t], acc[c][t], 0, 0, 0);
+                    acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(B.v[u][c].x, B.bv[u][0][t], acc[c][t], 0, 0, 0);
+                    acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(B.v[u][c].y, B.bv[u][1][t], acc[c][t], 0, 0, 0);
                 }
             }
     };
     // full trips unguarded (16-byte loads need an aligned A, checked by the
-    // host), then the ragged rows with bounds checks
-    const int nst = (m + 7) / 8, nfull = m / 8;
+    // host), software-pipelined over two register sets: the loads of the next
+    // trip are in flight while the current one is multiplied.  Then the
+    // ragged rows with bounds checks.
+    const int nst = (m + 7) / 8, nfull = m / 8, step = NWV * PF;
     int s0 = wv * PF;
-    for (; s0 + PF <= nfull; s0 += NW * PF) trip(s0, std::false_type{});
-    for (; s0 < nst; s0 += NW * PF) trip(s0, std::true_type{});
-    // partial results of the four waves: lane l, register v of a tile holds
-    // column 4 v + l / 16, vector l % 16
+    // full trips of this wave: s0 + i step for i < nfw.  The prefetch past the
+    // last one re-reads the last one (its values are never used), so the loop
+    // body has no branch and the loads stay ahead of the products.
+    const int nfw = (nfull - s0 >= PF) ? (nfull - s0 - PF) / step + 1 : 0;
+    if (nfw > 0) {
+        const int slast = s0 + (nfw - 1) * step;
+        Buf B0, B1;
+        ld(s0, B0, std::false_type{});
+        int i = 0;
+        for (; i + 2 <= nfw; i += 2) {
+            ld(s0 + step, B1, std::false_type{});
+            mm(B0);
+            ld(min(s0 + 2 * step, slast), B0, std::false_type{});
+            mm(B1);
+            s0 += 2 * step;
+        }
+        if (i < nfw) {
+            mm(B0);
+            s0 += step;
+        }
+    }
+    for (; s0 < nst; s0 += step) {
+        Buf B;
+        ld(s0, B, std::true_type{});
+        mm(B);
+    }
+    // partial results: lane l, register v of a tile holds column 4 v + l / 16,
+    // vector l % 16.  With eight waves, waves 4..7 first hand theirs to 0..3.
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        double r = rd[c];
-        r += __shfl_xor(r, 16, 64);
-        r += __shfl_xor(r, 32, 64);
-        Rs[wv][c][lane] = r;
+        rd[c] += __shfl_xor(rd[c], 16, 64);
+        rd[c] += __shfl_xor(rd[c], 32, 64);
+    }
+    if (NWV == 8) {
+        if (wv >= 4) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+            for (int c = 0; c < 4; ++c) {
+                Rs[wv - 4][c][lane] = rd[c];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Cs[wv][c][t][v][lane] = acc[c][t][v];
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Cs[wv - 4][c][t][v][lane] = acc[c][t][v];
+            }
+        }
+        __syncthreads();
+        if (wv < 4) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                rd[c] += Rs[wv][c][lane];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[c][t][v] += Cs[wv][c][t][v][lane];
+            }
+        }
+        __syncthreads();
+    }
+    if (wv < 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            Rs[wv][c][lane] = rd[c];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Cs[wv][c][t][v][lane] = acc[c][t][v];
+        }
     }
     __syncthreads();
     if (tid >= 64) return;
@@ -2229,8 +2287,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
                 const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
                 const int ev = kprof_begin(st);
                 const dim3 g((n + 63) / 64);
-                if (nvec <= 33) hipLaunchKernelGGL(lg_dual2<2>, g, dim3(WG), 0, st, ca);
-                else hipLaunchKernelGGL(lg_dual2<3>, g, dim3(WG), 0, st, ca);
+                if (nvec <= 33) hipLaunchKernelGGL((lg_dual2<2, 4, 2>), g, dim3(256), 0, st, ca);
+                else hipLaunchKernelGGL((lg_dual2<3, 4, 2>), g, dim3(256), 0, st, ca);
                 HIPCHK(hipGetLastError());
                 kprof_end(st, ev, bytes);
                 break;
