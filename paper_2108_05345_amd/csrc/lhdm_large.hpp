@@ -1171,38 +1171,45 @@ __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
     p.u2[j] = u2;
 }
 
-// Vectors of the dual update, row-major m x 64: vector gv of the whole set is
-// r (gv = 0), an added column of Q (1..kadd) or a dropped/trailing column of Q.
-// Dual pass in one launch when the block holds 18 .. 1 + 16 NT vectors:
-// w = A^T r (vector 0) on the vector units and the dot products of every
-// column of A with vectors 1 .. 16 NT on FP64 MFMA 16x16x4, followed by the
-// projected-norm update.  A workgroup owns 64 columns of A (four 16-column
-// tiles); its waves take interleaved pairs of 8-row steps, so at any time the
-// workgroup reads one contiguous block of rows of its 64 columns and the
-// vector block is read once per workgroup.  Lane (c = l % 16, g = l / 16)
-// reads 16 bytes of its column per step (64 contiguous bytes per column per
-// load instruction).  The waves meet once, to add their partial results.
-template <int NT, int NWV, int PF>   // PF: 8-row steps per wave and trip
-__global__ __launch_bounds__(64 * NWV) void lg_dual2(ColmatArgs a) {
-    static_assert(NWV == 4 || NWV == 8, "four or eight waves");
+// Column block times vector block on FP64 MFMA 16x16x4, X column-major.
+// The vectors are the columns of Dt (row-major m x ldd).  A workgroup owns CT
+// 16-column tiles of X; its four waves take interleaved trips of PF 8-row
+// steps over all CT tiles, so at any time the workgroup reads one contiguous
+// block of rows of its columns, and Dt is read once per workgroup.  Lane
+// (c = l % 16, g = l / 16) reads 16 bytes of its column per step (64
+// contiguous bytes per column per load instruction).  Each wave keeps two
+// register sets: the loads of the next trip are in flight while the current
+// one is multiplied.  The waves meet once, to add their partial results.
+//
+// DUAL: vector 0 of the dual update (Dt column 0 = r) goes through the vector
+// units and gives w = A^T r; Dt columns 1 .. 16 NT are the added, dropped or
+// trailing directions of Q, whose squared dot products update the projected
+// norms u2 (added: subtracted; others: added; exact mode: from zero).
+// PROJ: Dt columns 0 .. 16 NT - 1; out[t * ldo + j] = X[:, j] . Dt[:, t].
+template <int NT, int CT, int PF, bool DUAL>
+__global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
     if (a.skip && *a.skip) return;
-    __shared__ double Cs[4][4][NT][4][64];   // per wave, column tile, vector tile, register, lane
-    __shared__ double Rs[4][4][64];
+    constexpr int VO = DUAL ? 1 : 0;   // Dt column of MFMA vector 0
+    constexpr int NCOL = 16 * CT;
+    __shared__ double Cs[NW][CT][NT][4][64];   // per wave, column tile, vector tile, register, lane
+    __shared__ double Rs[NW][CT][64];
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_index(), g = lane >> 4, cl = lane & 15;
-    const int j0 = blockIdx.x * 64;
+    const int j0 = blockIdx.x * NCOL;
     const double* __restrict__ Dt = a.Dt;
     const int m = a.m, ldd = a.ldd;
-    const double* xc[4];
+    const double* xc[CT];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) xc[c] = a.X + (size_t)min(j0 + 16 * c + cl, a.ncols - 1) * a.ldx;
-    d4 acc[4][NT];
-    double rd[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < CT; ++c) xc[c] = a.X + (size_t)min(j0 + 16 * c + cl, a.ncols - 1) * a.ldx;
+    d4 acc[CT][NT];
+    double rd[CT];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < CT; ++c) {
+        rd[c] = 0.0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[c][t] = d4{0.0, 0.0, 0.0, 0.0};
+    }
     struct Buf {
-        double2 v[PF][4];
+        double2 v[PF][CT];
         double rv[PF][2], bv[PF][2][NT];
     };
     auto ld = [&](int s0, Buf& B, auto guard) {
@@ -1211,7 +1218,7 @@ __global__ __launch_bounds__(64 * NWV) void lg_dual2(ColmatArgs a) {
         for (int u = 0; u < PF; ++u) {
             const int row = (s0 + u) * 8 + 2 * g;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < CT; ++c) {
                 if (!G) {
                     B.v[u][c] = *reinterpret_cast<const double2*>(xc[c] + row);
                 } else {
@@ -1223,9 +1230,9 @@ __global__ __launch_bounds__(64 * NWV) void lg_dual2(ColmatArgs a) {
             for (int h = 0; h < 2; ++h) {
                 const bool ok = !G || row + h < m;
                 const double* drow = Dt + (size_t)(ok ? row + h : 0) * ldd;
-                B.rv[u][h] = ok ? drow[0] : 0.0;
+                if (DUAL) B.rv[u][h] = ok ? drow[0] : 0.0;
 #pragma unroll
-                for (int t = 0; t < NT; ++t) B.bv[u][h][t] = ok ? drow[1 + 16 * t + cl] : 0.0;
+                for (int t = 0; t < NT; ++t) B.bv[u][h][t] = ok ? drow[VO + 16 * t + cl] : 0.0;
             }
         }
     };
@@ -1233,9 +1240,11 @@ __global__ __launch_bounds__(64 * NWV) void lg_dual2(ColmatArgs a) {
 #pragma unroll
         for (int u = 0; u < PF; ++u)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                rd[c] = fma(B.v[u][c].x, B.rv[u][0], rd[c]);
-                rd[c] = fma(B.v[u][c].y, B.rv[u][1], rd[c]);
+            for (int c = 0; c < CT; ++c) {
+                if (DUAL) {
+                    rd[c] = fma(B.v[u][c].x, B.rv[u][0], rd[c]);
+                    rd[c] = fma(B.v[u][c].y, B.rv[u][1], rd[c]);
+                }
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(B.v[u][c].x, B.bv[u][0][t], acc[c][t], 0, 0, 0);
@@ -1243,11 +1252,9 @@ __global__ __launch_bounds__(64 * NWV) void lg_dual2(ColmatArgs a) {
                 }
             }
     };
-    // full trips unguarded (16-byte loads need an aligned A, checked by the
-    // host), software-pipelined over two register sets: the loads of the next
-    // trip are in flight while the current one is multiplied.  Then the
-    // ragged rows with bounds checks.
-    const int nst = (m + 7) / 8, nfull = m / 8, step = NWV * PF;
+    // Full trips unguarded (16-byte loads need an aligned X, checked by the
+    // host), then the ragged rows with bounds checks.
+    const int nst = (m + 7) / 8, nfull = m / 8, step = NW * PF;
     int s0 = wv * PF;
     // full trips of this wave: s0 + i step for i < nfw.  The prefetch past the
     // last one re-reads the last one (its values are never used), so the loop
@@ -1276,48 +1283,34 @@ __global__ __launch_bounds__(64 * NWV) void lg_dual2(ColmatArgs a) {
         mm(B);
     }
     // partial results: lane l, register v of a tile holds column 4 v + l / 16,
-    // vector l % 16.  With eight waves, waves 4..7 first hand theirs to 0..3.
+    // vector l % 16
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        rd[c] += __shfl_xor(rd[c], 16, 64);
-        rd[c] += __shfl_xor(rd[c], 32, 64);
-    }
-    if (NWV == 8) {
-        if (wv >= 4) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                Rs[wv - 4][c][lane] = rd[c];
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) Cs[wv - 4][c][t][v][lane] = acc[c][t][v];
-            }
+    for (int c = 0; c < CT; ++c) {
+        if (DUAL) {
+            double r = rd[c];
+            r += __shfl_xor(r, 16, 64);
+            r += __shfl_xor(r, 32, 64);
+            Rs[wv][c][lane] = r;
         }
-        __syncthreads();
-        if (wv < 4) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                rd[c] += Rs[wv][c][lane];
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[c][t][v] += Cs[wv][c][t][v][lane];
-            }
-        }
-        __syncthreads();
-    }
-    if (wv < 4) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            Rs[wv][c][lane] = rd[c];
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) Cs[wv][c][t][v][lane] = acc[c][t][v];
-        }
+            for (int v = 0; v < 4; ++v) Cs[wv][c][t][v][lane] = acc[c][t][v];
     }
     __syncthreads();
-    if (tid >= 64) return;
+    if (!DUAL) {
+        // element (vector q, column jj): tile jj / 16, register (jj % 16) / 4,
+        // lane (jj % 4) * 16 + q % 16, vector tile q / 16
+        for (int e = tid; e < a.nvec * NCOL; e += WG) {
+            const int q = e / NCOL, jj = e % NCOL, j = j0 + jj;
+            if (j >= a.ncols) continue;
+            const int c = jj >> 4, v = (jj & 15) >> 2, l = (jj & 3) * 16 + (q & 15), t = q >> 4;
+            a.out[(size_t)q * a.ldo + j] =
+                ((Cs[0][c][t][v][l] + Cs[1][c][t][v][l]) + Cs[2][c][t][v][l]) + Cs[3][c][t][v][l];
+        }
+        return;
+    }
+    if (tid >= NCOL) return;
     // thread tid: column j0 + tid, i.e. tile tid / 16, column 4 v + l / 16 = tid % 16
     const int c = tid >> 4, jc = tid & 15, v = jc >> 2;
     const int j = j0 + tid;
@@ -2065,6 +2058,28 @@ static int colmat_launch(hipStream_t st, ColmatArgs ca) {
     return 0;
 }
 
+// Pipelined column-block kernel when X allows 16-byte loads and the vector
+// block fits 48 MFMA vectors (one launch for the whole dual update); returns
+// false when it does not apply and the caller takes colmat_launch.
+static bool colmat2_launch(hipStream_t st, ColmatArgs ca) {
+    ca.al16 = ((((uintptr_t)ca.X) & 15) == 0) && ((ca.ldx & 1) == 0);
+    if (!ca.al16 || ca.ncols <= 0 || ca.nvec <= 0) return false;
+    if (ca.mode == MODE_DUAL) {
+        if (ca.v0 != 0 || ca.nvec != ca.vtot || ca.nvec > 49) return false;
+        const dim3 g((ca.ncols + 63) / 64);
+        if (ca.nvec <= 17) hipLaunchKernelGGL((lg_colmat2<1, 4, 2, true>), g, dim3(WG), 0, st, ca);
+        else if (ca.nvec <= 33) hipLaunchKernelGGL((lg_colmat2<2, 4, 2, true>), g, dim3(WG), 0, st, ca);
+        else hipLaunchKernelGGL((lg_colmat2<3, 4, 2, true>), g, dim3(WG), 0, st, ca);
+        return true;
+    }
+    if (ca.nvec > 48) return false;
+    const dim3 g((ca.ncols + 15) / 16);
+    if (ca.nvec <= 16) hipLaunchKernelGGL((lg_colmat2<1, 1, 4, false>), g, dim3(WG), 0, st, ca);
+    else if (ca.nvec <= 32) hipLaunchKernelGGL((lg_colmat2<2, 1, 4, false>), g, dim3(WG), 0, st, ca);
+    else hipLaunchKernelGGL((lg_colmat2<3, 1, 4, false>), g, dim3(WG), 0, st, ca);
+    return true;
+}
+
 // Host copy of the control words read at each decision point.
 // Host copy of the control block and the leading int fields of LgExtra, laid
 // out as in the workspace (LgExtra starts at the next 256-byte boundary after
@@ -2189,7 +2204,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             ca.ldo = m;
             ca.p = p;
             ca.nvec = mir->ctl.ncol;
-            if ((rc = colmat_launch(st, ca))) return rc;
+            if (!colmat2_launch(st, ca) && (rc = colmat_launch(st, ca))) return rc;
+            HIPCHK(hipGetLastError());
         }
         const int gblk = (m + GRAM_ROWS - 1) / GRAM_ROWS;
         if (mir->ctl.ncol > 1) {
@@ -2264,35 +2280,6 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         hipLaunchKernelGGL(lg_dual_plan, dim3(1), dim3(64), 0, st, a);
         for (int v0 = 0; v0 < nvec; v0 += 64) {
             hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, st, a, v0);
-            const bool al16 = ((((uintptr_t)A) & 15) == 0) && ((lda & 1) == 0);
-            if (al16 && nvec >= 18 && nvec <= 49) {
-                // the whole block in one pass
-                ColmatArgs ca{};
-                ca.X = A;
-                ca.ldx = lda;
-                ca.m = m;
-                ca.ncols = n;
-                ca.Dt = a.Dt;
-                ca.ldd = 64;
-                ca.mode = MODE_DUAL;
-                ca.nvec = nvec;
-                ca.v0 = 0;
-                ca.vtot = nvec;
-                ca.kadd = kadd;
-                ca.exact = exact;
-                ca.p = p;
-                ca.recomp = a.recomp;
-                ca.nrecomp = &a.ex->nrecomp;
-                ca.al16 = ((((uintptr_t)A) & 15) == 0) && ((lda & 1) == 0);
-                const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
-                const int ev = kprof_begin(st);
-                const dim3 g((n + 63) / 64);
-                if (nvec <= 33) hipLaunchKernelGGL((lg_dual2<2, 4, 2>), g, dim3(256), 0, st, ca);
-                else hipLaunchKernelGGL((lg_dual2<3, 4, 2>), g, dim3(256), 0, st, ca);
-                HIPCHK(hipGetLastError());
-                kprof_end(st, ev, bytes);
-                break;
-            }
             ColmatArgs ca{};
             ca.X = A;
             ca.ldx = lda;
@@ -2312,7 +2299,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             // algorithmic bytes: A once, the vector block, w written, u2 read and written
             const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
             const int ev = kprof_begin(st);
-            if ((rc = colmat_launch(st, ca))) return rc;
+            if (!colmat2_launch(st, ca) && (rc = colmat_launch(st, ca))) return rc;
+            HIPCHK(hipGetLastError());
             kprof_end(st, ev, bytes);
         }
         hipLaunchKernelGGL(lg_recompute, dim3(64), dim3(WG), 0, st, a);
