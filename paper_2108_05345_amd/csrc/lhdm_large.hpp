@@ -442,13 +442,25 @@ __global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, co
 }
 
 // Dt[row * 64 + t] = A[row, J[t]] (t < ncol), zero-padded to 64 columns.
-__global__ __launch_bounds__(WG) void lg_gather_cand(LgArgs a) {
+// Vector block element (row, t) -> Dt index: row-major (ldd 64) or the pair
+// layout of the pipelined column-block kernel.
+__device__ __forceinline__ void dt_coords(size_t e, int pair, int& row, int& t) {
+    if (pair) {
+        row = (int)(e / 128) * 2 + (int)(e & 1);
+        t = (int)((e / 2) % 64);
+    } else {
+        row = (int)(e / 64);
+        t = (int)(e % 64);
+    }
+}
+__global__ __launch_bounds__(WG) void lg_gather_cand(LgArgs a, int pair) {
     const Prob& p = a.p;
-    const int nc = a.ctl->ncol;
-    const size_t tot = (size_t)p.m * 64;
+    const int nc = a.ctl->ncol, m = p.m;
+    const size_t tot = (size_t)(pair ? (m + 1) / 2 * 2 : m) * 64;
     for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < tot; e += (size_t)gridDim.x * WG) {
-        const int row = (int)(e / 64), t = (int)(e % 64);
-        a.Dt[e] = (t < nc) ? p.A[(size_t)a.ctl->J[t] * p.lda + row] : 0.0;
+        int row, t;
+        dt_coords(e, pair, row, t);
+        a.Dt[e] = (t < nc && row < m) ? p.A[(size_t)a.ctl->J[t] * p.lda + row] : 0.0;
     }
 }
 
@@ -1172,7 +1184,10 @@ __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
 }
 
 // Column block times vector block on FP64 MFMA 16x16x4, X column-major.
-// The vectors are the columns of Dt (row-major m x ldd).  A workgroup owns CT
+// The vectors are the columns of Dt, stored in the pair layout: element
+// (row i, vector t) at ((i / 2) ldd + t) 2 + i % 2, with ldd vectors per row
+// and a zero row after an odd last row, so that one 16-byte load gives a
+// vector's values on the two rows that a lane feeds to consecutive MFMAs.  A workgroup owns CT
 // 16-column tiles of X; its four waves take interleaved trips of PF 8-row
 // steps over all CT tiles, so at any time the workgroup reads one contiguous
 // block of rows of its columns, and Dt is read once per workgroup.  Lane
@@ -1226,13 +1241,19 @@ __global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
                     B.v[u][c].y = (row + 1 < m) ? xc[c][row + 1] : 0.0;
                 }
             }
+            // rows row and row + 1 of the pair layout: one 16-byte load per vector
+            const bool ok = !G || row < m;
+            const double2* d2 = reinterpret_cast<const double2*>(Dt) + (size_t)(ok ? row >> 1 : 0) * ldd;
+            if (DUAL) {
+                const double2 x = ok ? d2[0] : double2{0.0, 0.0};
+                B.rv[u][0] = x.x;
+                B.rv[u][1] = x.y;
+            }
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const bool ok = !G || row + h < m;
-                const double* drow = Dt + (size_t)(ok ? row + h : 0) * ldd;
-                if (DUAL) B.rv[u][h] = ok ? drow[0] : 0.0;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) B.bv[u][h][t] = ok ? drow[VO + 16 * t + cl] : 0.0;
+            for (int t = 0; t < NT; ++t) {
+                const double2 x = ok ? d2[VO + 16 * t + cl] : double2{0.0, 0.0};
+                B.bv[u][0][t] = x.x;
+                B.bv[u][1][t] = x.y;
             }
         }
     };
@@ -1334,17 +1355,18 @@ __global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
     p.u2[j] = u2;
 }
 
-__global__ __launch_bounds__(WG) void lg_gather_dual(LgArgs a, int v0) {
+__global__ __launch_bounds__(WG) void lg_gather_dual(LgArgs a, int v0, int pair) {
     const LgExtra* ex = a.ex;
     if (a.ex->restart) return;
     const Prob& p = a.p;
     const int nP = a.ctl->nP, m = p.m;
-    const size_t tot = (size_t)m * 64;
+    const size_t tot = (size_t)(pair ? (m + 1) / 2 * 2 : m) * 64;
     for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < tot; e += (size_t)gridDim.x * WG) {
-        const int row = (int)(e / 64), t = (int)(e % 64);
+        int row, t;
+        dt_coords(e, pair, row, t);
         const int gv = v0 + t;
         double v = 0.0;
-        if (gv < ex->nvec) {
+        if (gv < ex->nvec && row < m) {
             if (gv == 0) v = p.r[row];
             else if (ex->exact) v = p.Q[(size_t)(nP + gv - 1) * m + row];
             else if (gv <= ex->kadd) v = p.Qadd[(size_t)(gv - 1) * m + row];
@@ -2022,7 +2044,7 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.slot, slot_bytes(m, n, kmax));
     put(L.ybuf, sizeof(double) * kc);
     put(L.Vt, sizeof(double) * (size_t)m * kq);
-    put(L.Dt, sizeof(double) * (size_t)m * 64);
+    put(L.Dt, sizeof(double) * (size_t)(m + 1) * 64);
     put(L.rot, sizeof(double) * 2 * kc * RQ);
     put(L.ocol, sizeof(int) * kc);
     put(L.lcnt, sizeof(int) * kc);
@@ -2058,26 +2080,29 @@ static int colmat_launch(hipStream_t st, ColmatArgs ca) {
     return 0;
 }
 
-// Pipelined column-block kernel when X allows 16-byte loads and the vector
-// block fits 48 MFMA vectors (one launch for the whole dual update); returns
-// false when it does not apply and the caller takes colmat_launch.
-static bool colmat2_launch(hipStream_t st, ColmatArgs ca) {
-    ca.al16 = ((((uintptr_t)ca.X) & 15) == 0) && ((ca.ldx & 1) == 0);
-    if (!ca.al16 || ca.ncols <= 0 || ca.nvec <= 0) return false;
+// The pipelined column-block kernel applies when X allows 16-byte loads and
+// the vector block fits 48 MFMA vectors (one launch for the whole dual
+// update); its vectors are in the pair layout.  Otherwise colmat_launch
+// (row-major vectors) is taken.
+static bool colmat2_fits(const ColmatArgs& ca) {
+    const bool al16 = ((((uintptr_t)ca.X) & 15) == 0) && ((ca.ldx & 1) == 0);
+    if (!al16 || ca.ncols <= 0 || ca.nvec <= 0) return false;
+    if (ca.mode == MODE_DUAL) return ca.v0 == 0 && ca.nvec == ca.vtot && ca.nvec <= 49;
+    return ca.nvec <= 48;
+}
+static void colmat2_launch(hipStream_t st, ColmatArgs ca) {
+    ca.al16 = 1;
     if (ca.mode == MODE_DUAL) {
-        if (ca.v0 != 0 || ca.nvec != ca.vtot || ca.nvec > 49) return false;
         const dim3 g((ca.ncols + 63) / 64);
         if (ca.nvec <= 17) hipLaunchKernelGGL((lg_colmat2<1, 4, 2, true>), g, dim3(WG), 0, st, ca);
         else if (ca.nvec <= 33) hipLaunchKernelGGL((lg_colmat2<2, 4, 2, true>), g, dim3(WG), 0, st, ca);
         else hipLaunchKernelGGL((lg_colmat2<3, 4, 2, true>), g, dim3(WG), 0, st, ca);
-        return true;
+        return;
     }
-    if (ca.nvec > 48) return false;
     const dim3 g((ca.ncols + 15) / 16);
-    if (ca.nvec <= 16) hipLaunchKernelGGL((lg_colmat2<1, 1, 4, false>), g, dim3(WG), 0, st, ca);
-    else if (ca.nvec <= 32) hipLaunchKernelGGL((lg_colmat2<2, 1, 4, false>), g, dim3(WG), 0, st, ca);
-    else hipLaunchKernelGGL((lg_colmat2<3, 1, 4, false>), g, dim3(WG), 0, st, ca);
-    return true;
+    if (ca.nvec <= 16) hipLaunchKernelGGL((lg_colmat2<1, 1, 2, false>), g, dim3(WG), 0, st, ca);
+    else if (ca.nvec <= 32) hipLaunchKernelGGL((lg_colmat2<2, 1, 2, false>), g, dim3(WG), 0, st, ca);
+    else hipLaunchKernelGGL((lg_colmat2<3, 1, 2, false>), g, dim3(WG), 0, st, ca);
 }
 
 // Host copy of the control words read at each decision point.
@@ -2190,7 +2215,6 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         if ((rc = read_ctl())) return rc;
         if (mir->ctl.done) break;
         // candidate projection G = Q^T A_J
-        hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, st, a);
         {
             ColmatArgs ca{};
             ca.X = p.Q;
@@ -2204,7 +2228,10 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             ca.ldo = m;
             ca.p = p;
             ca.nvec = mir->ctl.ncol;
-            if (!colmat2_launch(st, ca) && (rc = colmat_launch(st, ca))) return rc;
+            const bool pair = colmat2_fits(ca);
+            hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, st, a, (int)pair);
+            if (pair) colmat2_launch(st, ca);
+            else if ((rc = colmat_launch(st, ca))) return rc;
             HIPCHK(hipGetLastError());
         }
         const int gblk = (m + GRAM_ROWS - 1) / GRAM_ROWS;
@@ -2279,7 +2306,6 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         const int nvec = 1 + (exact ? (m - nP) : (kadd + ndrop));
         hipLaunchKernelGGL(lg_dual_plan, dim3(1), dim3(64), 0, st, a);
         for (int v0 = 0; v0 < nvec; v0 += 64) {
-            hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, st, a, v0);
             ColmatArgs ca{};
             ca.X = A;
             ca.ldx = lda;
@@ -2298,8 +2324,11 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             ca.nrecomp = &a.ex->nrecomp;
             // algorithmic bytes: A once, the vector block, w written, u2 read and written
             const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
+            const bool pair = colmat2_fits(ca);
+            hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, st, a, v0, (int)pair);
             const int ev = kprof_begin(st);
-            if (!colmat2_launch(st, ca) && (rc = colmat_launch(st, ca))) return rc;
+            if (pair) colmat2_launch(st, ca);
+            else if ((rc = colmat_launch(st, ca))) return rc;
             HIPCHK(hipGetLastError());
             kprof_end(st, ev, bytes);
         }

@@ -173,6 +173,25 @@ def test_device_engine_multiblock_sizes(lhdm):
         _check(lhdm.solve(A, b, kmax=1, engine="device"), xo, io, same_path=False, tag=f"dev-lh-{m}x{n}")
 
 
+def test_device_engine_padded_leading_dimension(lhdm):
+    # A given as a column-major view with a padded (even) leading dimension:
+    # odd m with even lda takes the 16-byte-load column-block kernel for the
+    # dual pass (its vector block then ends in a zero padding row), even m
+    # with lda = m + 2 takes it with a column stride different from m
+    for (m, n, k, seed, pad) in ((131, 420, 40, 41, 1), (257, 700, 70, 42, 1), (160, 500, 48, 43, 2)):
+        inst = make_small(m, n, k, seed, kind="uniform", noise_std=1e-2)
+        d = torch.device("cuda:0")
+        store = torch.zeros((n, m + pad), dtype=torch.float64, device=d)
+        store[:, :m] = torch.from_numpy(np.ascontiguousarray(inst.A.T)).to(d)
+        A = store[:, :m].t()
+        assert A.stride(0) == 1 and A.stride(1) == m + pad
+        b = torch.from_numpy(np.ascontiguousarray(inst.b)).to(d)
+        xo, io = oracle.oracle_lhdm(inst.A, inst.b)
+        _check(lhdm.solve(A, b, engine="device"), xo, io, same_path=False, tag=f"lda-{m}x{n}+{pad}")
+        xo, io = oracle.oracle_lh(inst.A, inst.b)
+        _check(lhdm.solve(A, b, kmax=1, engine="device"), xo, io, same_path=False, tag=f"lda-lh-{m}x{n}+{pad}")
+
+
 def test_c2_full_size(lhdm):
     # the 1024 x 4096 unit-column Gaussian instance, noiseless 128-sparse: unique
     from workloads import make_c2
