@@ -124,11 +124,13 @@ inline void kprof_end(hipStream_t st, int i, double bytes) {
     k.pending.push_back({i, bytes});
 }
 
-// Called after the stream has been synchronised.
+// Called once the stream has passed the recorded events (a wait for the end
+// event is then immediate).
 inline void kprof_drain() {
     KernelProfile& k = kprof();
     for (auto& pr : k.pending) {
         float ms = 0.f;
+        (void)hipEventSynchronize(k.pool[pr.first + 1]);
         if (hipEventElapsedTime(&ms, k.pool[pr.first], k.pool[pr.first + 1]) == hipSuccess) {
             k.ms += ms;
             k.launches += 1;

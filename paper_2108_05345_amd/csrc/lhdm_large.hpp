@@ -17,6 +17,7 @@
 #pragma once
 
 #include <climits>
+#include <cstddef>
 #include <type_traits>
 #include <vector>
 
@@ -54,6 +55,21 @@ struct LgExtra {
     int seg_off[RQ + 1];
 };
 
+// Host copy of the control block and of the head of LgExtra.  The kernels
+// that end with a host decision write it into fine-grained pinned host memory
+// and then store `seq`, which the host polls.
+constexpr size_t CTL_SPAN = (sizeof(Ctl) + 255) / 256 * 256;
+constexpr int EX_HEAD = 16;   // ints of LgExtra mirrored (inner_done .. gident and more)
+struct Mirror {
+    union {
+        Ctl ctl;
+        char raw[CTL_SPAN];
+    };
+    int ex_head[EX_HEAD];
+    int seq;
+};
+static_assert(sizeof(LgExtra) >= EX_HEAD * sizeof(int), "mirrored head of LgExtra");
+
 struct LgArgs {
     Prob p;
     DevParams prm;
@@ -75,6 +91,7 @@ struct LgArgs {
     int* candi;       // CAND_CAP: and column indices
     u64* pll;         // 2 * (2 PNW + 2) x (KM + 1) : panel partials (dots, pivot row)
     double* wpart;    // ceil(m / QCB) x kq x m : pass-1 partial products of the Q update
+    Mirror* hmir;     // device view of the host mirror
 };
 
 // --------------------------------------------------------------------------
@@ -93,6 +110,26 @@ __device__ inline void ctl_store(const WgShared& s, Ctl* g) {
     int* d = reinterpret_cast<int*>(g);
     for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int)); i += blockDim.x) d[i] = src[i];
     __syncthreads();
+}
+
+// Copy the control block and the head of LgExtra to the host mirror with
+// system-scope stores, then store the sequence number `seq` (release, system
+// scope).  Called by every thread of a single-workgroup kernel as its last step.
+__device__ inline void publish(const LgArgs& a, int seq) {
+    __syncthreads();
+    __threadfence();   // the workgroup's global writes of ctl and ex, before the reads below
+    constexpr int NC = (int)(sizeof(Ctl) / sizeof(int));
+    const int* sc = reinterpret_cast<const int*>(a.ctl);
+    const int* se = reinterpret_cast<const int*>(a.ex);
+    int* dc = reinterpret_cast<int*>(&a.hmir->ctl);
+    int* de = a.hmir->ex_head;
+    for (int i = threadIdx.x; i < NC + EX_HEAD; i += blockDim.x) {
+        if (i < NC) __hip_atomic_store(dc + i, sc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        else __hip_atomic_store(de + (i - NC), se[i - NC], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&a.hmir->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Low-latency hand-off: a double travels as two 8-byte words {32-bit half,
@@ -346,7 +383,7 @@ __global__ __launch_bounds__(WG) void lg_sel_cand(LgArgs a, const double* pv, co
 // kmax - 1 collected candidates in (w desc, index asc) order, each placed by
 // its rank among the collected ones.  More than CAND_CAP candidates falls back
 // to passes over memory.
-__global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, const int* pi) {
+__global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, const int* pi, int pub) {
     __shared__ WgShared s;
     __shared__ double cw[CAND_CAP];
     __shared__ int ci[CAND_CAP];
@@ -439,6 +476,7 @@ __global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, co
     }
     if (threadIdx.x == 0) s.nP0 = s.nP;
     ctl_store(s, a.ctl);
+    publish(a, pub);
 }
 
 // Dt[row * 64 + t] = A[row, J[t]] (t < ncol), zero-padded to 64 columns.
@@ -610,13 +648,12 @@ __device__ inline void compact_panel_row(const Prob& p, const int* gmap, int kr,
 constexpr int PNW = 32;                  // largest number of workgroups of the panel factorisation
 constexpr int PANEL_LDS_MAX = 128 * 1024;   // dynamic LDS of one workgroup of the panel factorisation
 constexpr int PSLOT = KM + 1;            // published values per workgroup and column
-constexpr int PGATHER = ((PNW + 1) * PSLOT + WG - 1) / WG;   // gathered values per thread
 
 __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) {
     extern __shared__ double pan[];   // rpw x (kr + 1), row-major
     __shared__ double red[NW][PSLOT];
-    __shared__ double gat[(PNW + 1) * PSLOT];   // partials of every workgroup, then the pivot row
-    __shared__ double dsum[PSLOT];
+    __shared__ double dpart[NW][PSLOT];   // per gathering wave: dots of the pivot column with columns t .. kr
+    __shared__ double prow[PSLOT];        // pivot row entries of columns t .. kr
     const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
     const int r0 = ctl->nP, kr = ctl->kr, m = p.m;
@@ -635,90 +672,110 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
     int* err = &a.ex->err;
     u64* DQl = a.pll;                          // [2][PNW][PSLOT] x 2 words, by column parity
     u64* PVl = a.pll + 2 * (2 * PNW * PSLOT);  // [2][PSLOT] x 2 words
-    for (int e = tid; e < nr * ld; e += WG) {
+    // rows nr .. rpw - 1 are zero: the update below runs over whole row
+    // groups without bounds checks and leaves them zero
+    for (int e = tid; e < rpw * ld; e += WG) {
         const int i = e / ld, q = e % ld;
-        pan[e] = (q < kr) ? p.G[(size_t)gmap[q] * m + rs + i] : p.bt[rs + i];
+        pan[e] = (i >= nr) ? 0.0 : (q < kr) ? p.G[(size_t)gmap[q] * m + rs + i] : p.bt[rs + i];
     }
     __syncthreads();
+    // local dots of column 0 with columns 0 .. kr: lanes take columns, waves
+    // take every fourth row (later columns' dots come out of the update)
+    {
+        const int i0 = max(0, r0 - rs);
+        for (int c = lane; c < ld; c += 64) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            int i = i0 + wv;
+            for (; i + 7 * NW < nr; i += 8 * NW) {
+                double xt[8], xq[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    xt[u] = pan[(i + u * NW) * ld];
+                    xq[u] = pan[(i + u * NW) * ld + c];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc[u & 3] += xt[u] * xq[u];
+            }
+            for (; i < nr; i += NW) acc[0] += pan[i * ld] * pan[i * ld + c];
+            red[wv][c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        }
+    }
+    // lanes of the fused update: H row groups of CW lanes, lane (h, cl) takes
+    // column t + 1 + cl of rows wv H + h + 4 H k
+    const int H = (kr <= 32) ? 2 : 1, CW = 64 / H;
+    const int hh = lane / CW, cl = lane % CW;
     for (int t = 0; t < kr; ++t) {
         const int rt = r0 + t, ep = ebase + t, par = t & 1;
         const int i0 = max(0, rt - rs);   // local rows with global index >= rt
         const int nq = kr + 1 - t;        // columns t .. kr
         const bool owner = rt >= rs && rt < re;
-        // local dots of column t with columns t .. kr: lanes take columns,
-        // waves take every fourth row
-        // (eight rows' loads issued before their products)
-        for (int c0 = 0; c0 < nq; c0 += 64) {
-            const int c = c0 + lane;
-            if (c < nq) {
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
-                int i = i0 + wv;
-                for (; i + 7 * NW < nr; i += 8 * NW) {
-                    double xt[8], xq[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        xt[u] = pan[(i + u * NW) * ld + t];
-                        xq[u] = pan[(i + u * NW) * ld + t + c];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) acc[u & 3] += xt[u] * xq[u];
-                }
-                for (; i < nr; i += NW) acc[0] += pan[i * ld + t] * pan[i * ld + t + c];
-                red[wv][c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-            }
-        }
         __syncthreads();
+        // publish this workgroup's dots (and, from the owner, the pivot row)
         for (int c = tid; c < nq; c += WG) {
             const double d = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
             ll_put(&DQl[2 * ((par * PNW + w) * PSLOT + c)], d, ep);
             if (owner) ll_put(&PVl[2 * (par * PSLOT + c)], pan[(rt - rs) * ld + t + c], ep);
         }
-        // gather: value e = u * nq + c is workgroup u's dot with column t + c
-        // (u < npw) or the pivot row entry (u == npw)
-        {
-            const int tot = (npw + 1) * nq;
-            double val[PGATHER];
-            bool ok[PGATHER];
+        // gather: wave wv polls the dots of workgroups u = 8 wv .. 8 wv + 7
+        // with column t + c (lane c) and adds them in workgroup order; wave 0
+        // also takes the pivot row entry.  Each round issues all of a lane's
+        // loads before checking any, so a round costs one memory round trip;
+        // slots u >= npw are read but never used.
+        static_assert(PNW == 8 * NW, "eight workgroups per gathering wave");
+        for (int c0 = 0; c0 < nq; c0 += 64) {
+            const int c = c0 + lane;
+            const int cc = (c < nq) ? c : 0;
+            const u64* dq = &DQl[2 * ((par * PNW + 8 * wv) * PSLOT + cc)];
+            const u64* pq = &PVl[2 * (par * PSLOT + cc)];
+            const u64 e = (u64)(unsigned)ep;
+            const int nu = min(8, max(0, npw - 8 * wv));   // workgroups of this wave
+            double val[8], pv = 0.0;
+            unsigned pend = 0;   // bit j: workgroup 8 wv + j, bit 8: pivot row
+            if (c < nq) pend = ((1u << nu) - 1) | ((wv == 0) ? (1u << 8) : 0u);
 #pragma unroll
-            for (int k = 0; k < PGATHER; ++k) {
-                val[k] = 0.0;
-                ok[k] = tid + k * WG >= tot;
-            }
+            for (int j = 0; j < 8; ++j) val[j] = 0.0;
             long long it = 0;
             while (true) {
-                bool all = true;
+                u64 w0[9], w1[9];
 #pragma unroll
-                for (int k = 0; k < PGATHER; ++k) {
-                    if (!ok[k]) {
-                        const int e = tid + k * WG, u = e / nq, c = e % nq;
-                        const u64* slot = (u < npw) ? &DQl[2 * ((par * PNW + u) * PSLOT + c)]
-                                                    : &PVl[2 * (par * PSLOT + c)];
-                        ok[k] = ll_try(slot, ep, val[k]);
-                    }
-                    all = all && ok[k];
+                for (int j = 0; j < 8; ++j) {
+                    w0[j] = __hip_atomic_load(dq + 2 * j * PSLOT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    w1[j] = __hip_atomic_load(dq + 2 * j * PSLOT + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
-                if (__all(all)) break;
+                if (wv == 0) {
+                    w0[8] = __hip_atomic_load(pq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    w1[8] = __hip_atomic_load(pq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                } else {
+                    w0[8] = w1[8] = 0;
+                }
+#pragma unroll
+                for (int j = 0; j <= 8; ++j) {
+                    const bool rdy = ((pend >> j) & 1) && (w0[j] >> 32) == e && (w1[j] >> 32) == e;
+                    const double v = __longlong_as_double((long long)((w1[j] << 32) | (w0[j] & 0xffffffffull)));
+                    if (j < 8) val[j] = rdy ? v : val[j];
+                    else pv = rdy ? v : pv;
+                    pend &= rdy ? ~(1u << j) : ~0u;
+                }
+                if (__all(pend == 0)) break;
                 if (++it > SPIN_LIMIT) {
                     if (lane == 0) atomicExch(err, 1);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
+            if (c < nq) {
+                // val[j] stays 0.0 for the workgroups past npw
+                double d = 0.0;
 #pragma unroll
-            for (int k = 0; k < PGATHER; ++k) {
-                const int e = tid + k * WG;
-                if (e < tot) gat[(e / nq) * PSLOT + e % nq] = val[k];
+                for (int j = 0; j < 8; ++j) d += val[j];
+                dpart[wv][c] = d;
+                if (wv == 0) prow[c] = pv;
             }
         }
         __syncthreads();
-        if (tid < nq) {
-            double d = 0.0;
-            for (int u = 0; u < npw; ++u) d += gat[u * PSLOT + tid];
-            dsum[tid] = d;
-        }
-        __syncthreads();
-        const double x0 = gat[npw * PSLOT];
-        const double normx = sqrt(dsum[0]);
+        auto dsum = [&](int q) { return ((dpart[0][q] + dpart[1][q]) + dpart[2][q]) + dpart[3][q]; };
+        const double x0 = prow[0];
+        const double normx = sqrt(dsum(0));
         double tau = 0.0, beta = x0, scal = 0.0;
         if (normx > 0.0) {
             beta = (x0 >= 0.0) ? -normx : normx;
@@ -729,35 +786,47 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
             a.ctl->tau[t] = tau;
             a.ctl->beta[t] = beta;
         }
-        // apply the reflector to columns t+1 .. kr of the local rows
-        for (int c0 = 1; c0 < nq; c0 += 64) {
-            const int c = c0 + lane;
-            if (c < nq) {
-                const double sq = tau * (scal * (dsum[c] - beta * gat[npw * PSLOT + c]));
-                int i = i0 + wv;
-                for (; i + 7 * NW < nr; i += 8 * NW) {
-                    double xt[8], xq[8];
+        // Apply the reflector to columns t+1 .. kr of the local rows >= rt,
+        // store the scaled reflector in column t (read by no later step) and
+        // accumulate the dots of the updated column t+1 with columns t+1 .. kr
+        // over the rows > rt.  Every lane also updates column t+1 of its row
+        // itself (same operands as the lane that owns it).  Rows are taken in
+        // aligned groups: rows < i0 get vi = 0 and keep their values, rows
+        // >= nr are zero.
+        const int ncu = nq - 1;
+        const bool act = cl < ncu;
+        double acc = 0.0;
+        if (act) {
+            const int c = t + 1 + cl;
+            const double sq = tau * (scal * (dsum(1 + cl) - beta * prow[1 + cl]));
+            const double sq1 = tau * (scal * (dsum(1) - beta * prow[1]));
+            const int rstep = NW * H, grp = 4 * rstep;   // rows per group: 32 (H = 2) or 16
+            const int roff = wv * H + hh;
+            for (int ib = (i0 / grp) * grp; ib < nr; ib += grp) {
+                double xt[4], xt1[4], xq[4];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        xt[u] = pan[(i + u * NW) * ld + t];
-                        xq[u] = pan[(i + u * NW) * ld + t + c];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int gi = i + u * NW;
-                        const double vi = (rs + gi == rt) ? 1.0 : xt[u] * scal;
-                        pan[gi * ld + t + c] = xq[u] - sq * vi;
-                    }
+                for (int u = 0; u < 4; ++u) {
+                    const int i = ib + u * rstep + roff;
+                    xt[u] = pan[i * ld + t];
+                    xt1[u] = pan[i * ld + t + 1];
+                    xq[u] = pan[i * ld + c];
                 }
-                for (; i < nr; i += NW) {
-                    const double vi = (rs + i == rt) ? 1.0 : pan[i * ld + t] * scal;
-                    pan[i * ld + t + c] -= sq * vi;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = ib + u * rstep + roff;
+                    const int gi = rs + i;
+                    const double vr = (gi == rt) ? 1.0 : xt[u] * scal;
+                    const double vi = (i < i0) ? 0.0 : vr;
+                    const double xn = xq[u] - sq * vi;
+                    const double pn = xt1[u] - sq1 * vi;
+                    pan[i * ld + c] = xn;
+                    pan[i * ld + t] = (i < i0) ? xt[u] : vr;
+                    acc = fma((gi > rt) ? pn : 0.0, xn, acc);
                 }
             }
         }
-        __syncthreads();
-        // store the scaled reflector in column t (read by no later step)
-        for (int i = i0 + tid; i < nr; i += WG) pan[i * ld + t] = (rs + i == rt) ? 1.0 : pan[i * ld + t] * scal;
+        if (H == 2) acc += __shfl_xor(acc, 32, 64);
+        if (hh == 0 && act) red[wv][cl] = acc;
     }
     __syncthreads();
     for (int e = tid; e < nr * ld; e += WG) {
@@ -921,8 +990,7 @@ __global__ __launch_bounds__(WG) void lg_commit(LgArgs a) {
 // removal set, and the per-column layout of the downdate.  A downdating sweep
 // handles at most RQ positions; further removals of the same iteration (their
 // x is already 0) are swept by the next call before any new step is taken.
-__global__ __launch_bounds__(WG) void lg_inner(LgArgs a) {
-    __shared__ WgShared s;
+__device__ void inner_body(LgArgs& a, WgShared& s) {
     ctl_load(s, a.ctl);
     LgExtra* ex = a.ex;
     if (s.k == 0) {
@@ -1002,6 +1070,11 @@ __global__ __launch_bounds__(WG) void lg_inner(LgArgs a) {
         a.roff[idx] = ex->seg_off[L] + L * (c - ex->seg_start[L]);
     }
     ctl_store(s, a.ctl);
+}
+__global__ __launch_bounds__(WG) void lg_inner(LgArgs a, int pub) {
+    __shared__ WgShared s;
+    inner_body(a, s);
+    publish(a, pub);
 }
 
 __global__ __launch_bounds__(WG) void lg_compact(LgArgs a) {
@@ -2109,14 +2182,6 @@ static void colmat2_launch(hipStream_t st, ColmatArgs ca) {
 // Host copy of the control block and the leading int fields of LgExtra, laid
 // out as in the workspace (LgExtra starts at the next 256-byte boundary after
 // Ctl) so that one transfer brings both.
-constexpr size_t CTL_SPAN = (sizeof(Ctl) + 255) / 256 * 256;
-struct Mirror {
-    union {
-        Ctl ctl;
-        char raw[CTL_SPAN];
-    };
-    int ex_head[16];
-};
 
 static int large_solve(hipStream_t st, int m, int n, const double* A, long long lda, const double* b,
                        const DevParams& prm, double* x, double* w, int* passive, lhdm_info* info, void* ws,
@@ -2164,9 +2229,6 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     unsigned long long* anmax_bits = (unsigned long long*)(base + L.misc);
     int* bad = (int*)(base + L.misc + 8);
 
-    // The chained kernels wait for flag == epoch.  Epochs only grow while the
-    // same flag buffers (same workspace, same kc) are reused; anything else
-    // clears the flags and restarts the epochs.
     // The hand-off buffers are matched by epoch.  Epochs only grow while the same
     // buffers (same workspace, same kc) are reused; anything else clears them and
     // restarts the epochs.
@@ -2179,16 +2241,45 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         last_ws = ws;
         last_kc = p.kc;
     }
+    // Host mirror in fine-grained (coherent) pinned memory: written by the
+    // kernels that end with a host decision, polled here through `seq`.
     static thread_local Mirror* mir = nullptr;
-    if (!mir) HIPCHK(hipHostMalloc((void**)&mir, sizeof(Mirror), hipHostMallocDefault));
+    static thread_local int pubseq = 0;
+    if (!mir) {
+        HIPCHK(hipHostMalloc((void**)&mir, sizeof(Mirror),
+                             hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent));
+        __atomic_store_n(&mir->seq, -1, __ATOMIC_RELEASE);
+    }
+    HIPCHK(hipHostGetDevicePointer((void**)&a.hmir, mir, 0));
 
+    // whole-stream synchronisation (start and end of the solve)
     auto read_ctl = [&]() -> int {
-        HIPCHK(hipMemcpyAsync(mir, a.ctl, sizeof(Mirror), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(mir, a.ctl, offsetof(Mirror, seq), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         kprof_drain();
         const LgExtra* hx = reinterpret_cast<const LgExtra*>(mir->ex_head);
         if (hx->err) return LHDM_EHIP;
         return 0;
+    };
+    // Wait for the mirror published with sequence number `want`.  The stream
+    // is queried now and then, so that a failed or drained stream ends the wait.
+    auto next_pub = [&]() {
+        pubseq = (pubseq + 1) & 0x3fffffff;
+        return pubseq;
+    };
+    auto wait_pub = [&](int want) -> int {
+        for (unsigned it = 1;; ++it) {
+            if (__atomic_load_n(&mir->seq, __ATOMIC_ACQUIRE) == want) break;
+            if ((it & 1023u) == 0) {
+                const hipError_t e = hipStreamQuery(st);
+                if (e == hipSuccess && __atomic_load_n(&mir->seq, __ATOMIC_ACQUIRE) == want) break;
+                if (e != hipErrorNotReady) return LHDM_EHIP;
+            }
+            __builtin_ia32_pause();
+        }
+        kprof_drain();
+        const LgExtra* hx = reinterpret_cast<const LgExtra*>(mir->ex_head);
+        return hx->err ? LHDM_EHIP : 0;
     };
     auto ex_h = [&]() { return reinterpret_cast<const LgExtra*>(mir->ex_head); };
 
@@ -2210,9 +2301,10 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         hipLaunchKernelGGL(lg_sel_part, dim3(NSEL), dim3(WG), 0, st, a, a.selv, a.seli);
         if (!prm.lh && prm.kmax > 1)
             hipLaunchKernelGGL(lg_sel_cand, dim3(NSEL), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli);
-        hipLaunchKernelGGL(lg_sel_main, dim3(1), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli);
+        const int ps = next_pub();
+        hipLaunchKernelGGL(lg_sel_main, dim3(1), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli, ps);
         HIPCHK(hipGetLastError());
-        if ((rc = read_ctl())) return rc;
+        if ((rc = wait_pub(ps))) return rc;
         if (mir->ctl.done) break;
         // candidate projection G = Q^T A_J
         {
@@ -2275,9 +2367,10 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         HIPCHK(hipGetLastError());
         bool restart = false;
         while (true) {
-            hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, st, a);
+            const int pi = next_pub();
+            hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, st, a, pi);
             HIPCHK(hipGetLastError());
-            if ((rc = read_ctl())) return rc;
+            if ((rc = wait_pub(pi))) return rc;
             if (ex_h()->restart) {
                 restart = true;
                 break;
