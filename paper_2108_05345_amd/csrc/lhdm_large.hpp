@@ -84,7 +84,7 @@ struct LgArgs {
     u64* rotll;       // 4 * kc * RQ : rotations published by the chained downdate
     int* recomp;      // n: columns whose projected norm is recomputed exactly
     double* rpart;    // RES_CHUNKS * m residual partial sums
-    double* gpart;    // partial Gram matrices (ceil(m / 256) blocks of 64 x 64)
+    double* gpart;    // partial Gram matrices (ceil(m / GRAM_ROWS) blocks of 64 x 64)
     double* selv;     // 3 * NSEL partial maxima of the selection
     int* seli;        // NSEL partial argmax indices
     double* candw;    // CAND_CAP: collected candidates' dual values
@@ -505,59 +505,54 @@ __global__ __launch_bounds__(WG) void lg_gather_cand(LgArgs a, int pair) {
 // Partial Gram matrix of X[r0:m, 0:c] (column-major, ld ldx) over row blocks of
 // 256 rows, on the matrix cores; symmetric tiles ti <= tj only.  which = 0: the
 // projected candidates (G, c = ncol); which = 1: the reflectors (V, c = kr).
-constexpr int GRAM_ROWS = 256;
+constexpr int GRAM_ROWS = 128;   // rows per workgroup of the partial Gram
 
+// Partial Gram X^T X over one block of GRAM_ROWS rows of the trailing part
+// (rows >= n_P): X = G (projected candidates, which = 0) or V (reflectors,
+// which = 1), c columns.  The block is staged in LDS with coalesced loads
+// (columns past c are zero); each wave takes upper 16 x 16 tiles and runs two
+// independent MFMA accumulators over the block.  Block blk writes its tiles
+// to part[blk][64][64] (row-major, upper tiles only).
 __global__ __launch_bounds__(WG) void lg_gram_part(LgArgs a, int which, double* part) {
+    __shared__ double xs[GRAM_ROWS][KM + 1];
     const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
     const int r0 = ctl->nP, m = p.m;
     const int c = which ? ctl->kr : ctl->ncol;
     const double* X = which ? p.V : p.G;
-    const int ldx = m;
     const int rs = r0 + blockIdx.x * GRAM_ROWS;
     if (rs >= m || c <= 0) return;
-    const int re = min(m, rs + GRAM_ROWS);
-    const int lane = threadIdx.x & 63, wv = wave_index();
+    const int nr = min(m, rs + GRAM_ROWS) - rs;
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_index();
     const int nt = (c + 15) / 16;
-    int tile = 0;
+    for (int e = tid; e < GRAM_ROWS * nt * 16; e += WG) {
+        const int q = e / GRAM_ROWS, i = e % GRAM_ROWS;
+        xs[i][q] = (i < nr && q < c) ? X[(size_t)q * m + rs + i] : 0.0;
+    }
+    __syncthreads();
     double* out = part + (size_t)blockIdx.x * 64 * 64;
+    int tile = 0;
     for (int ti = 0; ti < nt; ++ti)
         for (int tj = ti; tj < nt; ++tj, ++tile) {
             if ((tile % NW) != wv) continue;
-            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-            const int ca = ti * 16 + (lane & 15), cbb = tj * 16 + (lane & 15);
-            for (int r = rs; r < re; r += 4) {
-                const int row = r + (lane >> 4);
-                const double av = (row < re && ca < c) ? X[(size_t)ca * ldx + row] : 0.0;
-                const double bv = (row < re && cbb < c) ? X[(size_t)cbb * ldx + row] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+            const int ca = ti * 16 + (lane & 15), cb = tj * 16 + (lane & 15), g = lane >> 4;
+#pragma unroll 4
+            for (int r = 0; r < GRAM_ROWS; r += 8) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[r + g][ca], xs[r + g][cb], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[r + 4 + g][ca], xs[r + 4 + g][cb], acc1, 0, 0, 0);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) out[(ti * 16 + 4 * v + (lane >> 4)) * 64 + tj * 16 + (lane & 15)] = acc[v];
+            for (int v = 0; v < 4; ++v)
+                out[(ti * 16 + 4 * v + (lane >> 4)) * 64 + tj * 16 + (lane & 15)] = acc0[v] + acc1[v];
         }
 }
 
-// Sum of the partial Grams in block order, mirrored into a symmetric matrix
-// (ld kq): T for the candidates, W for the reflectors.
-__global__ __launch_bounds__(WG) void lg_gram_reduce(LgArgs a, int which, const double* part) {
-    const Ctl* ctl = a.ctl;
-    const Prob& p = a.p;
-    const int r0 = ctl->nP, m = p.m, kq = p.kq;
-    const int c = which ? ctl->kr : ctl->ncol;
-    const int nblk = (m - r0 + GRAM_ROWS - 1) / GRAM_ROWS;
-    double* dst = which ? p.W : p.T;
-    for (int e = threadIdx.x; e < c * c; e += WG) {
-        const int i = e / c, j = e % c;
-        if (i > j) continue;
-        const int ti = i / 16, tj = j / 16;
-        double sum = 0.0;
-        for (int blk = 0; blk < nblk; ++blk) {
-            const double* pp = part + (size_t)blk * 64 * 64;
-            sum += (ti <= tj) ? pp[i * 64 + j] : pp[j * 64 + i];
-        }
-        dst[(size_t)j * kq + i] = sum;
-        dst[(size_t)i * kq + j] = sum;
-    }
+// Entry (i, j), i <= j, of the Gram summed over the partial blocks in block order.
+__device__ inline double gram_entry(const double* part, int nblk, int i, int j) {
+    double sum = 0.0;
+    for (int blk = 0; blk < nblk; ++blk) sum += part[(size_t)blk * 64 * 64 + i * 64 + j];
+    return sum;
 }
 
 // Deviation maximization's greedy test (Algorithm 2) on the candidates' Gram
@@ -566,7 +561,7 @@ __global__ __launch_bounds__(WG) void lg_gram_reduce(LgArgs a, int which, const 
 // the greedy scan in candidate order is then one mask test per candidate.
 // Accepted candidates' panel columns go to gmap; the panel factorisation
 // reads the candidate panel through it.
-__global__ __launch_bounds__(WG) void lg_greedy(LgArgs a) {
+__global__ __launch_bounds__(WG) void lg_greedy(LgArgs a, const double* part) {
     __shared__ WgShared s;
     __shared__ double Tl[KM][KM + 1];
     __shared__ double sq[KM];
@@ -577,9 +572,11 @@ __global__ __launch_bounds__(WG) void lg_greedy(LgArgs a) {
     LgExtra* ex = a.ex;
     const int c = s.ncol, kq = p.kq, tid = threadIdx.x;
     if (c > 1) {
+        // the candidates' Gram matrix from the partial blocks (upper part)
+        const int nblk = (p.m - s.nP + GRAM_ROWS - 1) / GRAM_ROWS;
         for (int e = tid; e < c * c; e += WG) {
             const int ra = e / c, t = e % c;
-            Tl[ra][t] = p.T[(size_t)ra * kq + t];
+            if (ra <= t) Tl[ra][t] = gram_entry(part, nblk, ra, t);
         }
         __syncthreads();
         if (tid < c) sq[tid] = sqrt(Tl[tid][tid]);
@@ -875,7 +872,7 @@ __global__ __launch_bounds__(WG) void lg_panel_v(LgArgs a) {
 // Compact-WY factor (from V^T V in W), new R columns, feasibility loop on J.
 // T and the new diagonal block of R are staged in LDS; the J-loop's triangular
 // solves run on one wave (one row per lane).
-__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a) {
+__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part) {
     __shared__ WgShared s;
     __shared__ double Tl[KM][KM + 1];
     __shared__ double Wl[KM][KM + 1];
@@ -883,10 +880,12 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a) {
     Wg wg(a.p, a.prm, s);
     const Prob& p = a.p;
     const int kr = s.kr, kq = p.kq, tid = threadIdx.x;
-    // T: column t = -tau_t T[0:t, 0:t] (V^T V)[0:t, t], diagonal tau
+    // T: column t = -tau_t T[0:t, 0:t] (V^T V)[0:t, t], diagonal tau; V^T V
+    // from the partial blocks
+    const int nblk = (p.m - s.nP + GRAM_ROWS - 1) / GRAM_ROWS;
     for (int e = tid; e < kr * kr; e += WG) {
         const int i = e % kr, t = e / kr;
-        Wl[i][t] = (i < t) ? p.W[(size_t)t * kq + i] : 0.0;
+        Wl[i][t] = (i < t) ? gram_entry(part, nblk, i, t) : 0.0;
         Tl[i][t] = 0.0;
     }
     __syncthreads();
@@ -2124,7 +2123,7 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.roff, sizeof(int) * kc);
     put(L.recomp, sizeof(int) * (size_t)n);
     put(L.rpart, sizeof(double) * (size_t)RES_CHUNKS * m);
-    put(L.gpart, sizeof(double) * (size_t)((m + 255) / 256) * 64 * 64);
+    put(L.gpart, sizeof(double) * (size_t)((m + GRAM_ROWS - 1) / GRAM_ROWS) * 64 * 64);
     put(L.selv, sizeof(double) * 3 * 64);
     put(L.seli, sizeof(int) * 64);
     put(L.candw, sizeof(double) * CAND_CAP);
@@ -2329,9 +2328,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         const int gblk = (m + GRAM_ROWS - 1) / GRAM_ROWS;
         if (mir->ctl.ncol > 1) {
             hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 0, a.gpart);
-            hipLaunchKernelGGL(lg_gram_reduce, dim3(1), dim3(WG), 0, st, a, 0, (const double*)a.gpart);
         }
-        hipLaunchKernelGGL(lg_greedy, dim3(1), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_greedy, dim3(1), dim3(WG), 0, st, a, (const double*)a.gpart);
         {
             const int mp = m - mir->ctl.nP;
             int rpw = std::max(64, (mp + PNW - 1) / PNW);
@@ -2354,9 +2352,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         hipLaunchKernelGGL(lg_panel_v, dim3(64), dim3(WG), 0, st, a);
         if (mir->ctl.ncol > 1) {
             hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 1, a.gpart);
-            hipLaunchKernelGGL(lg_gram_reduce, dim3(1), dim3(WG), 0, st, a, 1, (const double*)a.gpart);
         }
-        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, st, a, (const double*)a.gpart);
         hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, st, a);
         if (mir->ctl.ncol <= 32) hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
         else hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
