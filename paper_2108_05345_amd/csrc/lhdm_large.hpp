@@ -549,9 +549,19 @@ __global__ __launch_bounds__(WG) void lg_gram_part(LgArgs a, int which, double* 
 }
 
 // Entry (i, j), i <= j, of the Gram summed over the partial blocks in block order.
+// Loads are issued eight blocks at a time; the additions keep block order.
 __device__ inline double gram_entry(const double* part, int nblk, int i, int j) {
+    const double* q = part + i * 64 + j;
     double sum = 0.0;
-    for (int blk = 0; blk < nblk; ++blk) sum += part[(size_t)blk * 64 * 64 + i * 64 + j];
+    int blk = 0;
+    for (; blk + 8 <= nblk; blk += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = q[(size_t)(blk + u) * 64 * 64];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; blk < nblk; ++blk) sum += q[(size_t)blk * 64 * 64];
     return sum;
 }
 
@@ -872,6 +882,31 @@ __global__ __launch_bounds__(WG) void lg_panel_v(LgArgs a) {
 // Compact-WY factor (from V^T V in W), new R columns, feasibility loop on J.
 // T and the new diagonal block of R are staged in LDS; the J-loop's triangular
 // solves run on one wave (one row per lane).
+// T of the compact WY form I - V T V^T of kr reflectors.  Its inverse is
+// striu(V^T V) + diag(1 / tau) (the recurrence of the block reflector's T and
+// this inverse agree in exact arithmetic), so lane j solves for column j of T
+// by itself: T[j][j] = tau_j, T[i][j] = -tau_i sum_{k=i+1..j} (V^T V)[i][k]
+// T[k][j], bottom-up, the sums accumulated right-looking as entries become
+// known.  Multiplying by tau_i (rather than dividing by 1 / tau_i) keeps a
+// zero tau exact.  N >= kr rows are unrolled (register partial sums).
+template <int N>
+__device__ inline void wy_t_columns(const double (*Wl)[KM + 1], const double* tau, int kr, double (*Tl)[KM + 1],
+                                    int j) {
+    double acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0.0;
+    const bool col = j < kr;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        if (i >= kr) continue;   // uniform
+        const double ti = tau[i];
+        const double tij = (!col || i > j) ? 0.0 : (i == j) ? ti : -ti * acc[i];
+        if (col) Tl[i][j] = tij;
+#pragma unroll
+        for (int i2 = 0; i2 < i; ++i2) acc[i2] = fma(Wl[i2][i], tij, acc[i2]);
+    }
+}
+
 __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part) {
     __shared__ WgShared s;
     __shared__ double Tl[KM][KM + 1];
@@ -880,24 +915,30 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part) {
     Wg wg(a.p, a.prm, s);
     const Prob& p = a.p;
     const int kr = s.kr, kq = p.kq, tid = threadIdx.x;
-    // T: column t = -tau_t T[0:t, 0:t] (V^T V)[0:t, t], diagonal tau; V^T V
-    // from the partial blocks
+    // T of the compact WY form, from V^T V (summed from the partial blocks)
     const int nblk = (p.m - s.nP + GRAM_ROWS - 1) / GRAM_ROWS;
     for (int e = tid; e < kr * kr; e += WG) {
-        const int i = e % kr, t = e / kr;
+        const int t = e % kr, i = e / kr;   // consecutive threads: consecutive t (coalesced)
         Wl[i][t] = (i < t) ? gram_entry(part, nblk, i, t) : 0.0;
-        Tl[i][t] = 0.0;
     }
     __syncthreads();
-    for (int t = 0; t < kr; ++t) {
-        if (tid < t) {
-            double acc = 0.0;
-            for (int l = tid; l < t; ++l) acc += Tl[tid][l] * Wl[l][t];
-            Tl[tid][t] = -s.tau[t] * acc;
+    if (tid < 64) {
+        if (kr <= 32) {
+            wy_t_columns<32>(Wl, s.tau, kr, Tl, tid);
+        } else {
+            // same order of operations, the partial sums kept in Tl itself
+            const int j = tid;
+            if (j < kr) {
+                for (int i = 0; i < kr; ++i) Tl[i][j] = 0.0;
+                for (int i = kr - 1; i >= 0; --i) {
+                    const double tij = (i > j) ? 0.0 : (i == j) ? s.tau[i] : -s.tau[i] * Tl[i][j];
+                    Tl[i][j] = tij;
+                    for (int i2 = 0; i2 < i; ++i2) Tl[i2][j] = fma(Wl[i2][i], tij, Tl[i2][j]);
+                }
+            }
         }
-        if (tid == 0) Tl[t][t] = s.tau[t];
-        __syncthreads();
     }
+    __syncthreads();
     for (int e = tid; e < kr * kq; e += WG) {
         const int i = e % kq, t = e / kq;
         p.T[(size_t)t * kq + i] = (i < kr) ? Tl[i][t] : 0.0;
