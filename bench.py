@@ -17,6 +17,7 @@ events on the solve's stream),
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
 import os
@@ -37,9 +38,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source():
+    """Source text of the dual kernel: its argument struct, the lg_colmat2
+    template and its launcher (a change anywhere else leaves the counters valid)."""
+    with open(KERNEL_SRC) as f:
+        src = f.read()
+    parts = []
+    for start, end in (("struct ColmatArgs {", "\n};\n"),
+                       ("template <int NT, int CT, int PF, bool DUAL>", "\n}\n"),
+                       ("static void colmat2_launch(", "\n}\n")):
+        i = src.index(start)
+        parts.append(src[i:src.index(end, i) + len(end)])
+    return "".join(parts)
+
+
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    return hashlib.sha256(kernel_source().encode()).hexdigest()[:16]
 
 
 def measured_traffic():
@@ -74,6 +88,41 @@ def cpu_baseline(inst, delta, outer_total, max_outer):
                       f"in {dt:.1f} s on the host, scaled by {done}/{outer_total}"}
 
 
+def _pmc_rows(path, counter):
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def write_traffic(fetch_csv, write_csv):
+    """HBM bytes per launch of the dual kernel from FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    1 GiB copy of --copy-calibration (1 GiB read, 1 GiB written)."""
+    out = {"kernel": "lg_colmat2<NT, 4, 2, true>", "workload": "gauss-4096x16384-k820-noise1e-3-seed3000"}
+    total = 0.0
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _pmc_rows(path, name)
+        dual = [v for k, v in rows if "lg_colmat2" in k and "true>" in k]
+        # the 1 GiB copy is by far the largest non-solver dispatch (blit or elementwise kernel)
+        copy = [v for k, v in rows if "lg_" not in k and ("copy" in k.lower() or "elementwise" in k.lower())]
+        if not dual or not copy:
+            raise SystemExit(f"write-traffic: no dual or copy dispatches with {name} in {path}")
+        copy_kib = max(copy)
+        scale = (1 << 20) / copy_kib            # counter KiB -> true KiB for a known 1 GiB stream
+        per = sum(dual) / len(dual) * scale * 1024.0
+        out[name.lower()] = {"dispatches": len(dual), "raw_kib_per_dispatch": sum(dual) / len(dual),
+                             "copy_kib": copy_kib, "scale": scale, "bytes_per_launch": per}
+        total += per
+    out["bytes_per_launch"] = total
+    out["kernel_src_sha256_16"] = kernel_hash()
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    log("wrote", TRAFFIC_FILE, out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,9 +133,17 @@ def main():
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer steps of the oracle sample (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--max-outer", type=int, default=0,
+                    help="cap on the outer steps of each solve (0: none; for short counter runs)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic file from two rocprofv3 --pmc counter_collection.csv "
+                         "files (FETCH_SIZE, WRITE_SIZE) of a --copy-calibration run, then exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 
@@ -114,7 +171,7 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     for _ in range(args.warmup):
-        r = lhdm.solve(A, b, delta=args.delta)
+        r = lhdm.solve(A, b, delta=args.delta, max_outer=args.max_outer)
         log("warmup lhdm", r.info)
     torch.cuda.synchronize()
 
@@ -124,7 +181,7 @@ def main():
     t0 = time.perf_counter()
     infos = []
     for _ in range(args.steps):
-        r = lhdm.solve(A, b, delta=args.delta)
+        r = lhdm.solve(A, b, delta=args.delta, max_outer=args.max_outer)
         infos.append(r.info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -157,7 +214,7 @@ def main():
         traffic = measured_traffic()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "dual pass: lg_dual2 / lg_colmat_dot (w = A^T r fused with the projected-norm update)",
+                "kernel": "dual pass: lg_colmat2<NT, 4, 2, DUAL> (w = A^T r fused with the projected-norm update)",
                 "launches": int(kl.value), "avg_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": bytes_per}
 
