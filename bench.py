@@ -117,6 +117,11 @@ def write_traffic(fetch_csv, write_csv):
                              "copy_kib": copy_kib, "scale": scale, "bytes_per_launch": per}
         total += per
     out["bytes_per_launch"] = total
+    out["commands"] = [f"rocprofv3 --pmc {c} --output-format csv -d pmc_{c} -o run -- python3 bench.py --steps 1 "
+                       "--warmup 0 --lh-steps 0 --cpu-outer 0 --max-outer 4 --copy-calibration"
+                       for c in ("FETCH_SIZE", "WRITE_SIZE")]
+    out["commands"].append("python3 bench.py --write-traffic pmc_FETCH_SIZE/run_counter_collection.csv "
+                           "pmc_WRITE_SIZE/run_counter_collection.csv")
     out["kernel_src_sha256_16"] = kernel_hash()
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
