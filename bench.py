@@ -45,7 +45,7 @@ def kernel_source():
         src = f.read()
     parts = []
     for start, end in (("struct ColmatArgs {", "\n};\n"),
-                       ("template <int NT, int CT, int PF, bool DUAL>", "\n}\n"),
+                       ("template <int NT, int CT, int PF, bool DUAL, int DEPTH = 2>", "\n}\n"),
                        ("static void colmat2_launch(", "\n}\n")):
         i = src.index(start)
         parts.append(src[i:src.index(end, i) + len(end)])
@@ -101,7 +101,7 @@ def write_traffic(fetch_csv, write_csv):
     """HBM bytes per launch of the dual kernel from FETCH_SIZE and WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
     1 GiB copy of --copy-calibration (1 GiB read, 1 GiB written)."""
-    out = {"kernel": "lg_colmat2<NT, 4, 2, true>", "workload": "gauss-4096x16384-k820-noise1e-3-seed3000"}
+    out = {"kernel": "lg_colmat2<NT, 4, 2, true, DEPTH>", "workload": "gauss-4096x16384-k820-noise1e-3-seed3000"}
     total = 0.0
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _pmc_rows(path, name)
@@ -219,7 +219,7 @@ def main():
         traffic = measured_traffic()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "dual pass: lg_colmat2<NT, 4, 2, DUAL> (w = A^T r fused with the projected-norm update)",
+                "kernel": "dual pass: lg_colmat2<NT, 4, 2, true, DEPTH> (w = A^T r fused with the projected-norm update)",
                 "launches": int(kl.value), "avg_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": bytes_per}
 

@@ -1314,8 +1314,9 @@ __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
 // trailing directions of Q, whose squared dot products update the projected
 // norms u2 (added: subtracted; others: added; exact mode: from zero).
 // PROJ: Dt columns 0 .. 16 NT - 1; out[t * ldo + j] = X[:, j] . Dt[:, t].
-template <int NT, int CT, int PF, bool DUAL>
+template <int NT, int CT, int PF, bool DUAL, int DEPTH = 2>
 __global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
+    static_assert(DEPTH == 2 || DEPTH == 3, "two or three register sets");
     if (a.skip && *a.skip) return;
     constexpr int VO = DUAL ? 1 : 0;   // Dt column of MFMA vector 0
     constexpr int NCOL = 16 * CT;
@@ -1394,7 +1395,7 @@ __global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
     // last one re-reads the last one (its values are never used), so the loop
     // body has no branch and the loads stay ahead of the products.
     const int nfw = (nfull - s0 >= PF) ? (nfull - s0 - PF) / step + 1 : 0;
-    if (nfw > 0) {
+    if (nfw > 0 && DEPTH == 2) {
         const int slast = s0 + (nfw - 1) * step;
         Buf B0, B1;
         ld(s0, B0, std::false_type{});
@@ -1408,6 +1409,31 @@ __global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
         }
         if (i < nfw) {
             mm(B0);
+            s0 += step;
+        }
+    } else if (nfw > 0) {
+        // three register sets: the loads run two trips ahead of the products
+        const int slast = s0 + (nfw - 1) * step;
+        Buf B0, B1, B2;
+        ld(s0, B0, std::false_type{});
+        ld(min(s0 + step, slast), B1, std::false_type{});
+        int i = 0;
+        for (; i + 3 <= nfw; i += 3) {
+            ld(min(s0 + 2 * step, slast), B2, std::false_type{});
+            mm(B0);
+            ld(min(s0 + 3 * step, slast), B0, std::false_type{});
+            mm(B1);
+            ld(min(s0 + 4 * step, slast), B1, std::false_type{});
+            mm(B2);
+            s0 += 3 * step;
+        }
+        // B0 and B1 hold trips i and i + 1 where they exist
+        if (i < nfw) {
+            mm(B0);
+            s0 += step;
+        }
+        if (i + 1 < nfw) {
+            mm(B1);
             s0 += step;
         }
     }
@@ -2208,8 +2234,8 @@ static void colmat2_launch(hipStream_t st, ColmatArgs ca) {
     if (ca.mode == MODE_DUAL) {
         const dim3 g((ca.ncols + 63) / 64);
         if (ca.nvec <= 17) hipLaunchKernelGGL((lg_colmat2<1, 4, 2, true>), g, dim3(WG), 0, st, ca);
-        else if (ca.nvec <= 33) hipLaunchKernelGGL((lg_colmat2<2, 4, 2, true>), g, dim3(WG), 0, st, ca);
-        else hipLaunchKernelGGL((lg_colmat2<3, 4, 2, true>), g, dim3(WG), 0, st, ca);
+        else if (ca.nvec <= 33) hipLaunchKernelGGL((lg_colmat2<2, 4, 2, true, 3>), g, dim3(WG), 0, st, ca);
+        else hipLaunchKernelGGL((lg_colmat2<3, 4, 2, true, 3>), g, dim3(WG), 0, st, ca);
         return;
     }
     const dim3 g((ca.ncols + 15) / 16);
