@@ -1887,51 +1887,74 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
         const bool unit = __builtin_amdgcn_readlane(lc_l, 0) == 1 && lc_last == 1 && ne == GB;
         const int off = __builtin_amdgcn_readlane(ro_l, 0);
         const int rlo = first + e0;
+        bool fallback = false;   // a unit block whose own rotations need the scaled path
         if (unit) {
             // rotation e of this block acts on rows (rlo + e, rlo + e + 1)
             double x[GB + 1];
+            double* cp = col + rlo;   // per-lane base: the 65 accesses take immediate offsets
 #pragma unroll
-            for (int r = 0; r <= GB; ++r) x[r] = col[rlo + r];
+            for (int r = 0; r <= GB; ++r) x[r] = cp[r];
             if (!own) {
                 if (bb != b - 1) ll_wait_word(&a.rotll[4 * (off + GB - 1) + 3], epoch, err);
                 const double rcv = ll_get<true>(&a.rotll[4 * (off + lane)], true, epoch, err);
                 const double rsv = ll_get<true>(&a.rotll[4 * (off + lane) + 2], true, epoch, err);
+                // rotation e reaches every lane through LDS (the loads run ahead
+                // of the dependent updates)
+                rcl[lane] = rcv;
+                rsl[lane] = rsv;
+                wave_lds_sync();
 #pragma unroll
                 for (int e = 0; e < GB; ++e) {
-                    const double cs = readlane_d(rcv, e), sn = readlane_d(rsv, e);
+                    const double cs = rcl[e], sn = rsl[e];
                     const double x0 = x[e], x1 = x[e + 1];
                     x[e] = cs * x0 + sn * x1;
                     x[e + 1] = -sn * x0 + cs * x1;
                 }
+                wave_lds_sync();
             } else {
-                // every lane evaluates a rotation from its own entries; lane t's is used
-                double mc = 1.0, ms = 0.0;
+                // Every lane evaluates a rotation from its own entries; lane t's
+                // is used at step t.  All lanes apply it (rows t and t + 1 of the
+                // columns left of t are below their diagonal), so the step needs
+                // no per-lane branch or mask; the rotation is kept in LDS and the
+                // exact zero below lane t's diagonal is stored after the write-
+                // back.  The unscaled rotation is taken on speculation: if any
+                // step's inputs could leave the normal range, the block is redone
+                // by the general path below (scaled rotations) from the unchanged
+                // column storage.
+                int bad = 0;
 #pragma unroll
                 for (int t = 0; t < GB; ++t) {
-                    double cs, sn;
-                    givens_lane(x[t], x[t + 1], t, cs, sn);
-                    cs = readlane_d(cs, t);
-                    sn = readlane_d(sn, t);
-                    if (lane == t) {
-                        mc = cs;
-                        ms = sn;
-                    }
-                    if (lane >= t) {
-                        const double x0 = x[t], x1 = x[t + 1];
-                        x[t] = cs * x0 + sn * x1;
-                        x[t + 1] = (lane == t) ? 0.0 : -sn * x0 + cs * x1;
-                    }
+                    const double xa = x[t], xb = x[t + 1];
+                    const double y = rsqrt(fma(xa, xa, xb * xb));
+                    const bool zb = xb == 0.0;
+                    const double cl = zb ? 1.0 : xa * y, sl = zb ? 0.0 : xb * y;
+                    const double mx = fmax(fabs(xa), fabs(xb));
+                    const int bd = (int)(!zb) & (int)(!((mx > 0x1p-480) & (mx < 0x1p480)));
+                    const double cs = readlane_d(cl, t), sn = readlane_d(sl, t);
+                    bad |= __builtin_amdgcn_readlane(bd, t);
+                    rcl[t] = cs;
+                    rsl[t] = sn;
+                    x[t] = cs * xa + sn * xb;
+                    x[t + 1] = -sn * xa + cs * xb;
                 }
-                ll_put(&a.rotll[4 * (off + lane)], mc, epoch);
-                ll_put(&a.rotll[4 * (off + lane) + 2], ms, epoch);
-                a.rotbuf[2 * (off + lane)] = mc;
-                a.rotbuf[2 * (off + lane) + 1] = ms;
+                fallback = bad != 0;
+                if (!fallback) {
+                    wave_lds_sync();
+                    const double mc = rcl[lane], ms = rsl[lane];
+                    ll_put(&a.rotll[4 * (off + lane)], mc, epoch);
+                    ll_put(&a.rotll[4 * (off + lane) + 2], ms, epoch);
+                    a.rotbuf[2 * (off + lane)] = mc;
+                    a.rotbuf[2 * (off + lane) + 1] = ms;
+                }
+                wave_lds_sync();
             }
-            if (valid) {
+            if (valid && !fallback) {
 #pragma unroll
-                for (int r = 0; r <= GB; ++r) col[rlo + r] = x[r];
+                for (int r = 0; r <= GB; ++r) cp[r] = x[r];
+                if (own) cp[lane + 1] = 0.0;   // the entry this lane's rotation zeroed
             }
-        } else {
+        }
+        if (!unit || fallback) {
             // rows rlo .. rhi of this lane's column in the LDS window
             const int rhi = rlo + ne - 1 + lc_last;
             for (int r0 = rlo; r0 <= rhi; r0 += 8) {
