@@ -1843,6 +1843,7 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
 // per lane and broadcast by readlane, so no scalar load sits on the chain.
 // --------------------------------------------------------------------------
 constexpr int GW = GB + RQ;   // rows of a block's LDS window
+constexpr int RCH = 16;       // rotations per chunk a unit block publishes while rotating
 
 // Rotation zeroing b in (a, b) on every lane without branching; the scaled
 // path is taken (uniformly) only when the lane that matters needs it.
@@ -1894,8 +1895,8 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
             double* cp = col + rlo;   // per-lane base: the 65 accesses take immediate offsets
 #pragma unroll
             for (int r = 0; r <= GB; ++r) x[r] = cp[r];
-            if (!own) {
-                if (bb != b - 1) ll_wait_word(&a.rotll[4 * (off + GB - 1) + 3], epoch, err);
+            if (!own && bb != b - 1) {
+                ll_wait_word(&a.rotll[4 * (off + GB - 1) + 3], epoch, err);
                 const double rcv = ll_get<true>(&a.rotll[4 * (off + lane)], true, epoch, err);
                 const double rsv = ll_get<true>(&a.rotll[4 * (off + lane) + 2], true, epoch, err);
                 // rotation e reaches every lane through LDS (the loads run ahead
@@ -1911,40 +1912,77 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                     x[e + 1] = -sn * x0 + cs * x1;
                 }
                 wave_lds_sync();
+            } else if (!own) {
+                // the previous block is still rotating: take its rotations in
+                // the chunks it publishes them in
+#pragma unroll
+                for (int ch = 0; ch < GB / RCH; ++ch) {
+                    const int k = ch * RCH + (lane & (RCH - 1));
+                    const double rcv = ll_get<true>(&a.rotll[4 * (off + k)], lane < RCH, epoch, err);
+                    const double rsv = ll_get<true>(&a.rotll[4 * (off + k) + 2], lane < RCH, epoch, err);
+                    if (lane < RCH) {
+                        rcl[k] = rcv;
+                        rsl[k] = rsv;
+                    }
+                    wave_lds_sync();
+#pragma unroll
+                    for (int e = ch * RCH; e < ch * RCH + RCH; ++e) {
+                        const double cs = rcl[e], sn = rsl[e];
+                        const double x0 = x[e], x1 = x[e + 1];
+                        x[e] = cs * x0 + sn * x1;
+                        x[e + 1] = -sn * x0 + cs * x1;
+                    }
+                }
+                wave_lds_sync();
             } else {
+                int bad = -1;   // last step whose chunk passed the check
                 // Every lane evaluates a rotation from its own entries; lane t's
                 // is used at step t.  All lanes apply it (rows t and t + 1 of the
                 // columns left of t are below their diagonal), so the step needs
                 // no per-lane branch or mask; the rotation is kept in LDS and the
                 // exact zero below lane t's diagonal is stored after the write-
-                // back.  The unscaled rotation is taken on speculation: if any
-                // step's inputs could leave the normal range, the block is redone
-                // by the general path below (scaled rotations) from the unchanged
-                // column storage.
-                int bad = 0;
+                // back.  The unscaled rotation is taken on speculation: inputs
+                // whose squares leave the normal range give a rotation that is
+                // not finite or not of unit norm, and the block is then redone by
+                // the general path below (scaled rotations) from the unchanged
+                // column storage.  Chunks published before the check are
+                // recomputed there with the same formulas up to rounding.
 #pragma unroll
                 for (int t = 0; t < GB; ++t) {
                     const double xa = x[t], xb = x[t + 1];
-                    const double y = rsqrt(fma(xa, xa, xb * xb));
-                    const bool zb = xb == 0.0;
-                    const double cl = zb ? 1.0 : xa * y, sl = zb ? 0.0 : xb * y;
-                    const double mx = fmax(fabs(xa), fabs(xb));
-                    const int bd = (int)(!zb) & (int)(!((mx > 0x1p-480) & (mx < 0x1p480)));
+                    // 1 / sqrt(q) from the hardware estimate and one third-order
+                    // correction, folded into c and s directly
+                    const double q = fma(xa, xa, xb * xb);
+                    const double y0 = __builtin_amdgcn_rsq(q);
+                    const double e = fma(-q * y0, y0, 1.0);
+                    const double pe = fma(e, 0.375, 0.5);
+                    const double ca = ((xb == 0.0) ? fabs(xa) : xa) * y0, sa = xb * y0;
+                    const double cl = fma(ca * e, pe, ca), sl = fma(sa * e, pe, sa);
                     const double cs = readlane_d(cl, t), sn = readlane_d(sl, t);
-                    bad |= __builtin_amdgcn_readlane(bd, t);
                     rcl[t] = cs;
                     rsl[t] = sn;
                     x[t] = cs * xa + sn * xb;
                     x[t + 1] = -sn * xa + cs * xb;
+                    if ((t % RCH) == RCH - 1) {
+                        // publish rotations t - RCH + 1 .. t for the next block
+                        // once they are checked
+                        wave_lds_sync();
+                        const int k = t - RCH + 1 + (lane & (RCH - 1));
+                        const double ck = rcl[k], sk = rsl[k];
+                        const double nk = fma(ck, ck, sk * sk) - 1.0;
+                        if (__any(!(fabs(nk) < 0x1p-40))) break;   // leaves the unrolled chain
+                        if (lane < RCH) {
+                            ll_put(&a.rotll[4 * (off + k)], ck, epoch);
+                            ll_put(&a.rotll[4 * (off + k) + 2], sk, epoch);
+                        }
+                        bad = t;
+                    }
                 }
-                fallback = bad != 0;
+                fallback = bad != GB - 1;   // the last checked step is not the last one
                 if (!fallback) {
                     wave_lds_sync();
-                    const double mc = rcl[lane], ms = rsl[lane];
-                    ll_put(&a.rotll[4 * (off + lane)], mc, epoch);
-                    ll_put(&a.rotll[4 * (off + lane) + 2], ms, epoch);
-                    a.rotbuf[2 * (off + lane)] = mc;
-                    a.rotbuf[2 * (off + lane) + 1] = ms;
+                    a.rotbuf[2 * (off + lane)] = rcl[lane];
+                    a.rotbuf[2 * (off + lane) + 1] = rsl[lane];
                 }
                 wave_lds_sync();
             }
