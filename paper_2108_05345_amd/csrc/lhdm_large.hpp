@@ -1879,6 +1879,12 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     __shared__ double rcl[RQ], rsl[RQ];
     // lanes past the last new column read the last one's storage (never written)
     double* col = p.R + (size_t)p.slot[a.ocol[valid ? idx : nd - 1]] * p.kc;
+    // A full own block's rows 1..64 are touched by no earlier block: they are
+    // staged in the LDS window while the previous block's rotations stream in,
+    // and its row 0 is the previous pass's last row (kept in a register).
+    const bool own_full = (b + 1) * GB <= nd;
+    double x64 = 0.0;
+    bool pre = false;
     for (int bb = 0; bb <= b; ++bb) {
         const bool own = bb == b;
         const int e0 = bb * GB, e1 = min(nd, e0 + GB), ne = e1 - e0;
@@ -1893,8 +1899,14 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
             // rotation e of this block acts on rows (rlo + e, rlo + e + 1)
             double x[GB + 1];
             double* cp = col + rlo;   // per-lane base: the 65 accesses take immediate offsets
+            if (own && pre) {
+                x[0] = x64;
 #pragma unroll
-            for (int r = 0; r <= GB; ++r) x[r] = cp[r];
+                for (int r = 1; r <= GB; ++r) x[r] = win[r - 1][lane];
+            } else {
+#pragma unroll
+                for (int r = 0; r <= GB; ++r) x[r] = cp[r];
+            }
             if (!own && bb != b - 1) {
                 ll_wait_word(&a.rotll[4 * (off + GB - 1) + 3], epoch, err);
                 const double rcv = ll_get<true>(&a.rotll[4 * (off + lane)], true, epoch, err);
@@ -1917,6 +1929,11 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                 // the chunks it publishes them in
 #pragma unroll
                 for (int ch = 0; ch < GB / RCH; ++ch) {
+                    double st[RCH];   // own rows 1 + ch RCH .. in flight during this chunk
+                    if (own_full) {
+#pragma unroll
+                        for (int u = 0; u < RCH; ++u) st[u] = cp[GB + 1 + ch * RCH + u];
+                    }
                     const int k = ch * RCH + (lane & (RCH - 1));
                     const double rcv = ll_get<true>(&a.rotll[4 * (off + k)], lane < RCH, epoch, err);
                     const double rsv = ll_get<true>(&a.rotll[4 * (off + k) + 2], lane < RCH, epoch, err);
@@ -1931,6 +1948,10 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                         const double x0 = x[e], x1 = x[e + 1];
                         x[e] = cs * x0 + sn * x1;
                         x[e + 1] = -sn * x0 + cs * x1;
+                    }
+                    if (own_full) {
+#pragma unroll
+                        for (int u = 0; u < RCH; ++u) win[ch * RCH + u][lane] = st[u];
                     }
                 }
                 wave_lds_sync();
@@ -1991,6 +2012,8 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
                 for (int r = 0; r <= GB; ++r) cp[r] = x[r];
                 if (own) cp[lane + 1] = 0.0;   // the entry this lane's rotation zeroed
             }
+            x64 = x[GB];
+            pre = !own && bb == b - 1 && own_full;
         }
         if (!unit || fallback) {
             // rows rlo .. rhi of this lane's column in the LDS window
