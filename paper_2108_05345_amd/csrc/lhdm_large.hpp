@@ -2111,7 +2111,7 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
 // rotation touches.  Ring columns are reused only below the lowest column the
 // rotating wave still needs; every wait is bounded.
 constexpr int QC = 64;        // new columns per chunk
-constexpr int QW = 256;       // ring columns (a chunk touches at most QC + RQ)
+constexpr int QW = 256;       // ring columns (a chunk touches at most QC + RQ); a power of two
 constexpr int QNL = 3;        // loader waves
 constexpr int QLB = 64;       // columns per loader block
 
@@ -2119,15 +2119,17 @@ __global__ __launch_bounds__(64 * (1 + QNL)) void lg_qrot(LgArgs a) {
     __shared__ double win[QW][64];
     __shared__ int lprog[QNL];   // blocks completed by each loader
     __shared__ int consumed;     // lowest column the rotating wave still needs
+    __shared__ double2 rcs[QC];  // the chunk's rotations (c, s), read by broadcast
     const LgExtra* ex = a.ex;
     const Prob& p = a.p;
     const int m = p.m, nd = ex->ndown, first = ex->first;
     if (nd <= 0) return;
     const int lane = threadIdx.x & 63, wv = wave_index();
     const int row = blockIdx.x * 64 + lane;
-    const bool valid = row <= m;
-    double* base = (row < m) ? p.Q + row : p.bt;
-    const size_t stride = (row < m) ? (size_t)m : 1;
+    // rows past bt read and write a slot of the residual scratch (rewritten
+    // before its next use), so no access below needs a lane mask
+    double* base = (row < m) ? p.Q + row : (row == m) ? p.bt : a.rpart + lane;
+    const size_t stride = (row < m) ? (size_t)m : (row == m) ? 1 : 0;
     const int* lcnt = a.lcnt;
     const double* rot = a.rotbuf;
     int* err = &a.ex->err;
@@ -2151,10 +2153,10 @@ __global__ __launch_bounds__(64 * (1 + QNL)) void lg_qrot(LgArgs a) {
             }
             double v[QLB];
 #pragma unroll
-            for (int u = 0; u < QLB; ++u) v[u] = (valid && cb + u <= rend) ? base[(size_t)(cb + u) * stride] : 0.0;
+            for (int u = 0; u < QLB; ++u) v[u] = (cb + u <= rend) ? base[(size_t)(cb + u) * stride] : 0.0;
 #pragma unroll
             for (int u = 0; u < QLB; ++u)
-                if (cb + u <= rend) win[(cb + u) % QW][lane] = v[u];
+                if (cb + u <= rend) win[(cb + u) & (QW - 1)][lane] = v[u];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
             ++done;
             if (lane == 0) __hip_atomic_store(&lprog[l], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -2206,40 +2208,66 @@ __global__ __launch_bounds__(64 * (1 + QNL)) void lg_qrot(LgArgs a) {
         }
         if (lcnt[e0] == 1 && lcnt[e1 - 1] == 1) {
             // column e rotates rows (first + e, first + e + 1) with rotation roff[e]
-            double x = win[(first + e0) % QW][lane];
+            const int s0 = (first + e0) & (QW - 1);
+            double x = win[s0][lane];
+            double* q = base + (size_t)(first + e0) * stride;
+            if (e1 - e0 == QC) {
+                // whole chunk: rotations and ring entries read sixteen at a time
+                // ahead of the dependent updates
+                rcs[lane] = double2{rc_cur, rs_cur};
+                wave_lds_sync();
 #pragma unroll
-            for (int u = 0; u < QC; ++u) {
-                if (e0 + u < e1) {
-                    const double cs = readlane_d(rc_cur, u), sn = readlane_d(rs_cur, u);
-                    const double y = win[(first + e0 + u + 1) % QW][lane];
-                    if (valid) base[(size_t)(first + e0 + u) * stride] = cs * x + sn * y;
-                    x = -sn * x + cs * y;
+                for (int g0 = 0; g0 < QC; g0 += 16) {
+                    double yv[16];
+                    double2 r2[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        yv[u] = win[(s0 + g0 + u + 1) & (QW - 1)][lane];
+                        r2[u] = rcs[g0 + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const double cs = r2[u].x, sn = r2[u].y;
+                        *q = cs * x + sn * yv[u];
+                        q += stride;
+                        x = -sn * x + cs * yv[u];
+                    }
+                }
+                wave_lds_sync();
+            } else {
+#pragma unroll
+                for (int u = 0; u < QC; ++u) {
+                    if (e0 + u < e1) {
+                        const double cs = readlane_d(rc_cur, u), sn = readlane_d(rs_cur, u);
+                        const double y = win[(s0 + u + 1) & (QW - 1)][lane];
+                        *q = cs * x + sn * y;
+                        q += stride;
+                        x = -sn * x + cs * y;
+                    }
                 }
             }
-            win[(first + e1) % QW][lane] = x;
+            win[(first + e1) & (QW - 1)][lane] = x;
         } else {
             for (int e = e0; e < e1; ++e) {
                 // bottom-up: rotation gg acts on rows (op - gg - 1, op - gg)
                 const int L = lcnt[e], off = a.roff[e], op = a.ocol[e];
-                double r = win[op % QW][lane];
+                double r = win[op & (QW - 1)][lane];
                 for (int gg = 0; gg < L; ++gg) {
                     const int i = op - gg;
                     const double cs = rot[2 * (off + gg)], sn = rot[2 * (off + gg) + 1];
-                    const double v0 = win[(i - 1) % QW][lane];
-                    win[i % QW][lane] = -sn * v0 + cs * r;
+                    const double v0 = win[(i - 1) & (QW - 1)][lane];
+                    win[i & (QW - 1)][lane] = -sn * v0 + cs * r;
                     r = cs * v0 + sn * r;
                 }
-                win[(op - L) % QW][lane] = r;
+                win[(op - L) & (QW - 1)][lane] = r;
             }
-            if (valid)
-                for (int rr = first + e0; rr < first + e1; ++rr) base[(size_t)rr * stride] = win[rr % QW][lane];
+            for (int rr = first + e0; rr < first + e1; ++rr) base[(size_t)rr * stride] = win[rr & (QW - 1)][lane];
         }
         // columns below first + e1 are final: their ring slots may be reused
         wave_lds_sync();
         if (lane == 0) __hip_atomic_store(&consumed, first + e1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    if (valid)
-        for (int rr = first + nd; rr <= rend; ++rr) base[(size_t)rr * stride] = win[rr % QW][lane];
+    for (int rr = first + nd; rr <= rend; ++rr) base[(size_t)rr * stride] = win[rr & (QW - 1)][lane];
 }
 
 // --------------------------------------------------------------------------
