@@ -105,7 +105,7 @@ def write_traffic(fetch_csv, write_csv):
     total = 0.0
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _pmc_rows(path, name)
-        dual = [v for k, v in rows if "lg_colmat2" in k and "true>" in k]
+        dual = [v for k, v in rows if "lg_colmat2" in k and "true" in k]
         # the 1 GiB copy is by far the largest non-solver dispatch (blit or elementwise kernel)
         copy = [v for k, v in rows if "lg_" not in k and ("copy" in k.lower() or "elementwise" in k.lower())]
         if not dual or not copy:
