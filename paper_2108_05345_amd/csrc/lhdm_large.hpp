@@ -112,13 +112,14 @@ __device__ inline void ctl_store(const WgShared& s, Ctl* g) {
     __syncthreads();
 }
 
-// Copy the control block and the head of LgExtra to the host mirror with
+// Copy the scalar head of the control block (the fields before its arrays,
+// all the host reads) and the head of LgExtra to the host mirror with
 // system-scope stores, then store the sequence number `seq` (release, system
 // scope).  Called by every thread of a single-workgroup kernel as its last step.
 __device__ inline void publish(const LgArgs& a, int seq) {
     __syncthreads();
     __threadfence();   // the workgroup's global writes of ctl and ex, before the reads below
-    constexpr int NC = (int)(sizeof(Ctl) / sizeof(int));
+    constexpr int NC = (int)(offsetof(Ctl, J) / sizeof(int));
     const int* sc = reinterpret_cast<const int*>(a.ctl);
     const int* se = reinterpret_cast<const int*>(a.ex);
     int* dc = reinterpret_cast<int*>(&a.hmir->ctl);
