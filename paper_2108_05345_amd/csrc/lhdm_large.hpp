@@ -662,6 +662,7 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
     __shared__ double red[NW][PSLOT];
     __shared__ double dpart[NW][PSLOT];   // per gathering wave: dots of the pivot column with columns t .. kr
     __shared__ double prow[PSLOT];        // pivot row entries of columns t .. kr
+    __shared__ double betal[PSLOT];       // new diagonal entries (the same in every workgroup)
     const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
     const int r0 = ctl->nP, kr = ctl->kr, m = p.m;
@@ -669,9 +670,13 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
     const int w = blockIdx.x;
     const int* gmap = a.ex->gmap;
     if (w >= npw) {
-        // workgroups past the panel: accepted candidates' rows above the panel
+        // workgroups past the panel: accepted candidates' rows above the panel,
+        // which are also the new R columns' rows above the panel
         const int row = (w - npw) * WG + threadIdx.x;
-        if (!a.ex->gident && row < r0) compact_panel_row(p, gmap, kr, row);
+        if (row < r0) {
+            if (!a.ex->gident) compact_panel_row(p, gmap, kr, row);
+            for (int t = 0; t < kr; ++t) p.R[(size_t)p.slot[r0 + t] * p.kc + row] = p.G[(size_t)t * m + row];
+        }
         return;
     }
     const int rs = r0 + w * rpw, re = min(m, rs + rpw), nr = re - rs;
@@ -794,6 +799,7 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
             a.ctl->tau[t] = tau;
             a.ctl->beta[t] = beta;
         }
+        if (tid == 0) betal[t] = beta;
         // Apply the reflector to columns t+1 .. kr of the local rows >= rt,
         // store the scaled reflector in column t (read by no later step) and
         // accumulate the dots of the updated column t+1 with columns t+1 .. kr
@@ -841,6 +847,19 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
         const int i = e / ld, q = e % ld;
         if (q < kr) p.G[(size_t)q * m + rs + i] = pan[e];
         else p.bt[rs + i] = pan[e];
+    }
+    // The reflectors V (column-major) and V^T (row-major) of this workgroup's
+    // rows, zero above each pivot (rows above the panel and columns >= kr are
+    // never read), and its rows of the new R columns (beta on the diagonal).
+    for (int e = tid; e < kr * nr; e += WG) {
+        const int t = e / nr, i = e % nr, row = rs + i;
+        const double pv = pan[i * ld + t];
+        p.V[(size_t)t * m + row] = (row >= r0 + t) ? pv : 0.0;
+        if (row <= r0 + t) p.R[(size_t)p.slot[r0 + t] * p.kc + row] = (row < r0 + t) ? pv : betal[t];
+    }
+    for (int e = tid; e < nr * kr; e += WG) {
+        const int i = e / kr, t = e % kr, row = rs + i;
+        p.Vt[(size_t)row * p.kq + t] = (row >= r0 + t) ? pan[i * ld + t] : 0.0;
     }
 }
 
@@ -2523,13 +2542,15 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
                 attr_set = true;
             }
             ++ep_p;
-            if (lds <= (size_t)PANEL_LDS_MAX)
+            if (lds <= (size_t)PANEL_LDS_MAX) {
+                // also writes V, V^T and the new R columns
                 hipLaunchKernelGGL(lg_panel_mw, dim3(npw + (mir->ctl.nP + WG - 1) / WG), dim3(WG), lds, st, a, rpw,
                                    ep_p * 256);
-            else
+            } else {
                 hipLaunchKernelGGL(lg_panel_1wg, dim3(1), dim3(WG), 0, st, a);
+                hipLaunchKernelGGL(lg_panel_v, dim3(64), dim3(WG), 0, st, a);
+            }
         }
-        hipLaunchKernelGGL(lg_panel_v, dim3(64), dim3(WG), 0, st, a);
         if (mir->ctl.ncol > 1) {
             hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 1, a.gpart);
         }
