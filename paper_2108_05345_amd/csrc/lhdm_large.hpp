@@ -1535,6 +1535,48 @@ __global__ __launch_bounds__(WG) void lg_gather_dual(LgArgs a, int v0, int pair)
     }
 }
 
+// First vector block of the dual update in one launch: the sizes of the
+// update (exact mode when the trailing columns are fewer), r = b - A_P x_P
+// from the residual partials (added in chunk order) as vector 0, and vectors
+// 1 .. 63 (added, dropped or trailing columns of Q).
+__global__ __launch_bounds__(WG) void lg_dual_prep(LgArgs a, int pair) {
+    LgExtra* ex = a.ex;
+    if (ex->restart) return;
+    const Ctl* c = a.ctl;
+    const Prob& p = a.p;
+    const int m = p.m, nP = c->nP, kadd = c->k, ndrop = c->nPa - c->nP;
+    const int exact = (m - nP) <= kadd + ndrop;
+    const int nvec = 1 + (exact ? (m - nP) : (kadd + ndrop));
+    const int gid = blockIdx.x * WG + threadIdx.x, gs = gridDim.x * WG;
+    if (gid == 0) {
+        ex->exact = exact;
+        ex->kadd = kadd;
+        ex->nvec = nvec;
+        ex->nrecomp = 0;
+    }
+    for (int row = gid; row < m; row += gs) {
+        double acc = 0.0;
+        for (int ch = 0; ch < RES_CHUNKS; ++ch) acc += a.rpart[(size_t)ch * m + row];
+        const double rv = p.b[row] - acc;
+        p.r[row] = rv;
+        a.Dt[pair ? (size_t)(row >> 1) * 128 + (row & 1) : (size_t)row * 64] = rv;
+    }
+    if (pair && (m & 1) && gid == 0) a.Dt[(size_t)(m >> 1) * 128 + 1] = 0.0;   // zero row after an odd last row
+    const size_t tot = (size_t)(pair ? (m + 1) / 2 * 2 : m) * 64;
+    for (size_t e = gid; e < tot; e += gs) {
+        int row, t;
+        dt_coords(e, pair, row, t);
+        if (t == 0) continue;
+        double v = 0.0;
+        if (t < nvec && row < m) {
+            if (exact) v = p.Q[(size_t)(nP + t - 1) * m + row];
+            else if (t <= kadd) v = p.Qadd[(size_t)(t - 1) * m + row];
+            else v = p.Q[(size_t)(nP + t - 1 - kadd) * m + row];
+        }
+        a.Dt[e] = v;
+    }
+}
+
 // Dt[:, 0] = r, other columns 0 (dual refresh when the solve stops early).
 __global__ __launch_bounds__(WG) void lg_gather_r(LgArgs a) {
     const size_t tot = (size_t)a.p.m * 64;
@@ -1542,18 +1584,6 @@ __global__ __launch_bounds__(WG) void lg_gather_r(LgArgs a) {
         a.Dt[e] = ((e % 64) == 0) ? a.p.r[e / 64] : 0.0;
 }
 
-// Sizes of the dual update (exact mode when the trailing columns are fewer).
-__global__ void lg_dual_plan(LgArgs a) {
-    if (threadIdx.x != 0) return;
-    LgExtra* ex = a.ex;
-    const Ctl* c = a.ctl;
-    if (ex->restart) return;
-    const int m = a.p.m, nP = c->nP, kadd = c->k, ndrop = c->nPa - c->nP;
-    ex->exact = (m - nP) <= kadd + ndrop;
-    ex->kadd = kadd;
-    ex->nvec = 1 + (ex->exact ? (m - nP) : (kadd + ndrop));
-    ex->nrecomp = 0;
-}
 
 // Exact u2 for flagged columns: sum over the trailing columns of Q.
 __global__ __launch_bounds__(WG) void lg_recompute(LgArgs a) {
@@ -2588,14 +2618,16 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         if (restart) continue;
         if (!stop) hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, st, a);
-        hipLaunchKernelGGL(lg_residual_sum, dim3(rgrid), dim3(WG), 0, st, a);
+        if (stop) {
+            hipLaunchKernelGGL(lg_residual_sum, dim3(rgrid), dim3(WG), 0, st, a);
+            HIPCHK(hipGetLastError());
+            break;
+        }
         HIPCHK(hipGetLastError());
-        if (stop) break;
         // dual w = A^T r fused with the projected-norm update
         const int nP = mir->ctl.nP, kadd = mir->ctl.k, ndrop = mir->ctl.nPa - mir->ctl.nP;
         const int exact = (m - nP) <= kadd + ndrop;
         const int nvec = 1 + (exact ? (m - nP) : (kadd + ndrop));
-        hipLaunchKernelGGL(lg_dual_plan, dim3(1), dim3(64), 0, st, a);
         for (int v0 = 0; v0 < nvec; v0 += 64) {
             ColmatArgs ca{};
             ca.X = A;
@@ -2616,7 +2648,9 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             // algorithmic bytes: A once, the vector block, w written, u2 read and written
             const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
             const bool pair = colmat2_fits(ca);
-            hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, st, a, v0, (int)pair);
+            // the first block also forms r and the sizes of the update
+            if (v0 == 0) hipLaunchKernelGGL(lg_dual_prep, dim3(ggrid), dim3(WG), 0, st, a, (int)pair);
+            else hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, st, a, v0, (int)pair);
             const int ev = kprof_begin(st);
             if (pair) colmat2_launch(st, ca);
             else if ((rc = colmat_launch(st, ca))) return rc;
