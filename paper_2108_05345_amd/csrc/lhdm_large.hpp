@@ -1799,11 +1799,13 @@ __global__ __launch_bounds__(WG) void lg_qup2(LgArgs a) {
 // barrier in the loop); the R entries of a dependency block are loaded before
 // its part of y is awaited.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch) {
+// outer != 0: the solve of an outer step, started before the append is
+// committed (n_P is then the step's starting n_P plus the accepted columns).
+__global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch, int outer) {
     const Ctl* ctl = a.ctl;
     if (ctl->k == 0) return;
     const Prob& p = a.p;
-    const int nP = ctl->nP;
+    const int nP = outer ? ctl->nP0 + ctl->k : ctl->nP;
     const int nb = (nP + TB - 1) / TB;
     const int g = blockIdx.x;
     if (g >= nb) return;
@@ -2521,6 +2523,20 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     int rc = read_ctl();
     if (rc) return rc;
 
+    // side stream (default priority) and fork/join events, per host thread and device
+    static thread_local int side_dev = -1;
+    static thread_local hipStream_t side = nullptr;
+    static thread_local hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        if (side_dev != dev) {
+            HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+            side_dev = dev;
+        }
+    }
     const int ggrid = 256;
     const int tgrid = (p.kc + TB - 1) / TB;
     const int rgrid = (m + WG - 1) / WG;
@@ -2585,14 +2601,21 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 1, a.gpart);
         }
         hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, st, a, (const double*)a.gpart);
+        // the triangular solve needs R, bt and the accepted count only: it runs
+        // on the side stream while the Q update and the commit run here
+        HIPCHK(hipEventRecord(ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+        ++ep_t;
+        hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, side, a, ep_t, 1);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(ev_join, side));
         hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, st, a);
         if (mir->ctl.ncol <= 32) hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
         else hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, st, a);
-        ++ep_t;
-        hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t);
         HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
         bool restart = false;
         while (true) {
             const int pi = next_pub();
@@ -2612,7 +2635,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a);
             hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a);
             ++ep_t;
-            hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t);
+            hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t, 0);
             HIPCHK(hipGetLastError());
         }
         if (restart) continue;
