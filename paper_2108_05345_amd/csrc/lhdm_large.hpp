@@ -1137,12 +1137,58 @@ __global__ __launch_bounds__(WG) void lg_inner(LgArgs a, int pub) {
     publish(a, pub);
 }
 
-__global__ __launch_bounds__(WG) void lg_compact(LgArgs a) {
+// bt (one more row of Q) through the rotations of a downdate in which every
+// new column carries one rotation: rotation e acts on entries first + e and
+// first + e + 1, as x_{e+1} = -s_e x_e + c_e y_e (x_e the running entry, y_e =
+// bt[first + e + 1]) and bt[first + e] = c_e x_e + s_e y_e.  The recurrence is
+// affine in x, so each chunk of 64 rotations is one inclusive scan of the
+// maps x -> a x + b across the lanes (six shuffle steps) instead of 64
+// dependent steps; the running entry carries from chunk to chunk.
+__device__ inline void rotate_bt_unit(const LgArgs& a) {
+    const LgExtra* ex = a.ex;
+    const int nd = ex->ndown, lane = threadIdx.x & 63;
+    double* bt = a.p.bt + ex->first;
+    double x0 = bt[0];
+    for (int e0 = 0; e0 < nd; e0 += 64) {
+        const int ne = min(64, nd - e0);
+        double c = 1.0, sn = 0.0, y = 0.0;
+        if (lane < ne) {
+            const int ro = a.roff[e0 + lane];
+            c = a.rotbuf[2 * ro];
+            sn = a.rotbuf[2 * ro + 1];
+            y = bt[e0 + lane + 1];
+        }
+        // map of rotation `lane` (identity past the chunk), then the scan:
+        // (A, B) <- (A, B) after (A', B') of lane - d
+        double A = (lane < ne) ? -sn : 1.0, B = (lane < ne) ? c * y : 0.0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double Ap = __shfl_up(A, d, 64), Bp = __shfl_up(B, d, 64);
+            if (lane >= d) {
+                B = fma(A, Bp, B);
+                A = A * Ap;
+            }
+        }
+        // x after rotation `lane`; the input of rotation `lane` comes from lane - 1
+        // (the shuffle runs on every lane: a source lane must be active)
+        const double xa = fma(A, x0, B);
+        const double xu = __shfl_up(xa, 1, 64);
+        const double xin = (lane == 0) ? x0 : xu;
+        if (lane < ne) bt[e0 + lane] = c * xin + sn * y;
+        x0 = readlane_d(xa, ne - 1);
+    }
+    if (lane == 0) bt[nd] = x0;
+}
+
+// rotbt != 0: also rotate bt (the downdate's columns all carry one rotation;
+// the Q rotations then leave bt alone).
+__global__ __launch_bounds__(WG) void lg_compact(LgArgs a, int rotbt) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
     wg.compact();
     ctl_store(s, a.ctl);
+    if (rotbt && threadIdx.x < 64) rotate_bt_unit(a);
 }
 
 __global__ __launch_bounds__(WG) void lg_copy_x(LgArgs a) {
@@ -2167,7 +2213,8 @@ constexpr int QW = 256;       // ring columns (a chunk touches at most QC + RQ);
 constexpr int QNL = 3;        // loader waves
 constexpr int QLB = 64;       // columns per loader block
 
-__global__ __launch_bounds__(64 * (1 + QNL)) void lg_qrot(LgArgs a) {
+// skipbt != 0: bt is rotated elsewhere (lg_compact); its lane works on scratch.
+__global__ __launch_bounds__(64 * (1 + QNL)) void lg_qrot(LgArgs a, int skipbt) {
     __shared__ double win[QW][64];
     __shared__ int lprog[QNL];   // blocks completed by each loader
     __shared__ int consumed;     // lowest column the rotating wave still needs
@@ -2180,8 +2227,9 @@ __global__ __launch_bounds__(64 * (1 + QNL)) void lg_qrot(LgArgs a) {
     const int row = blockIdx.x * 64 + lane;
     // rows past bt read and write a slot of the residual scratch (rewritten
     // before its next use), so no access below needs a lane mask
-    double* base = (row < m) ? p.Q + row : (row == m) ? p.bt : a.rpart + lane;
-    const size_t stride = (row < m) ? (size_t)m : (row == m) ? 1 : 0;
+    const bool isbt = row == m && !skipbt;
+    double* base = (row < m) ? p.Q + row : isbt ? p.bt : a.rpart + lane;
+    const size_t stride = (row < m) ? (size_t)m : isbt ? 1 : 0;
     const int* lcnt = a.lcnt;
     const double* rot = a.rotbuf;
     int* err = &a.ex->err;
@@ -2632,11 +2680,26 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             ++ep_g;
             hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ep_g);
-            hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a);
-            hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a);
-            ++ep_t;
-            hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t, 0);
-            HIPCHK(hipGetLastError());
+            if (ex_h()->totrot == ex_h()->ndown) {
+                // one rotation per column: bt is rotated with the compaction, and
+                // the triangular solve runs on the side stream beside the Q rotations
+                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a, 1);
+                HIPCHK(hipEventRecord(ev_fork, st));
+                HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+                ++ep_t;
+                hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, side, a, ep_t, 0);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipEventRecord(ev_join, side));
+                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a, 1);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+            } else {
+                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a, 0);
+                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a, 0);
+                ++ep_t;
+                hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t, 0);
+                HIPCHK(hipGetLastError());
+            }
         }
         if (restart) continue;
         if (!stop) hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, st, a);
