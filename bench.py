@@ -39,13 +39,16 @@ def log(*a):
 
 
 def kernel_source():
-    """Source text of the dual kernel: its argument struct, the lg_colmat2
-    template and its launcher (a change anywhere else leaves the counters valid)."""
+    """Source text of the dual kernels: their argument struct, the lg_dual_ws
+    and lg_colmat2 templates and the launcher (a change anywhere else leaves the
+    counters valid)."""
     with open(KERNEL_SRC) as f:
         src = f.read()
     parts = []
     for start, end in (("struct ColmatArgs {", "\n};\n"),
                        ("template <int NT, int CT, int PF, bool DUAL, int DEPTH = 2>", "\n}\n"),
+                       ("constexpr int DW_ROWS", "\n\n"),
+                       ("template <int NT>\n__global__ __launch_bounds__(DW_WG) void lg_dual_ws", "\n}\n"),
                        ("static void colmat2_launch(", "\n}\n")):
         i = src.index(start)
         parts.append(src[i:src.index(end, i) + len(end)])
@@ -101,11 +104,12 @@ def write_traffic(fetch_csv, write_csv):
     """HBM bytes per launch of the dual kernel from FETCH_SIZE and WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
     1 GiB copy of --copy-calibration (1 GiB read, 1 GiB written)."""
-    out = {"kernel": "lg_colmat2<NT, 4, 2, true, DEPTH>", "workload": "gauss-4096x16384-k820-noise1e-3-seed3000"}
+    out = {"kernel": "dual pass (lg_dual_ws<NT>, lg_colmat2<3, 4, 2, true, 3>)",
+           "workload": "gauss-4096x16384-k820-noise1e-3-seed3000"}
     total = 0.0
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _pmc_rows(path, name)
-        dual = [v for k, v in rows if "lg_colmat2" in k and "true" in k]
+        dual = [v for k, v in rows if "lg_dual_ws" in k or ("lg_colmat2" in k and "true" in k)]
         # the 1 GiB copy is by far the largest non-solver dispatch (blit or elementwise kernel)
         copy = [v for k, v in rows if "lg_" not in k and ("copy" in k.lower() or "elementwise" in k.lower())]
         if not dual or not copy:
@@ -219,7 +223,8 @@ def main():
         traffic = measured_traffic()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "dual pass: lg_colmat2<NT, 4, 2, true, DEPTH> (w = A^T r fused with the projected-norm update)",
+                "kernel": "dual pass: lg_dual_ws<NT> up to 32 directions, lg_colmat2<3, 4, 2, true, 3> up to 48 "
+                          "(w = A^T r fused with the projected-norm update)",
                 "launches": int(kl.value), "avg_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": bytes_per}
 

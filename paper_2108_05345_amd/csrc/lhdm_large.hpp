@@ -1560,6 +1560,188 @@ __global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
     p.u2[j] = u2;
 }
 
+// Dual pass with producer and consumer waves, for up to 32 MFMA vectors.
+// A workgroup owns 64 columns of A and walks down them in stages of
+// DW_ROWS rows.  Four producer waves read a stage with one column per load
+// instruction (128 consecutive rows, 1 KB, non-temporal: A is read once and
+// must not push the vector block out of L2) and write it to one of two
+// padded LDS buffers; four consumer waves take the previous stage from LDS in
+// the MFMA operand layout of lg_colmat2 (lane (cl, g): column 16 c + cl, rows
+// 2 g and 2 g + 1 of an 8-row group; the 16-byte column padding makes those
+// reads conflict-free) together with the vector block rows from L2, and
+// accumulate w = A^T r on the vector units and the products with the
+// directions on v_mfma_f64_16x16x4f64.  The loads never wait behind the
+// products: the two roles are separate waves on each SIMD.  The epilogue is
+// that of lg_colmat2 (same partial layout, same order of the four-way sum).
+constexpr int DW_ROWS = 128;              // rows of A per stage
+constexpr int DW_CB = DW_ROWS + 2;        // padded column length of a stage in LDS (doubles)
+constexpr int DW_WG = 512;                // four producer and four consumer waves
+typedef double dw_d2v __attribute__((ext_vector_type(2)));
+
+// Workgroup barrier without a memory fence (the stage hand-off waits for its
+// own LDS stores; a fence would also wait for the next stage's loads); the
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void dw_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int NT>
+__global__ __launch_bounds__(DW_WG) void lg_dual_ws(ColmatArgs a) {
+    static_assert(NT == 1 || NT == 2, "one or two vector tiles");
+    if (a.skip && *a.skip) return;
+    constexpr int NCOL = 64;
+    __shared__ __attribute__((aligned(16))) double st[2 * NCOL * DW_CB];
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_index();
+    const int m = a.m, j0 = blockIdx.x * NCOL;
+    const int ns = (m + DW_ROWS - 1) / DW_ROWS, nfull = m / DW_ROWS;
+    d4 acc[4][NT];
+    double rd[4];
+    if (wv < 4) {
+        // producer wave wv: columns 16 wv .. 16 wv + 15 of the block (clamped
+        // to the last column; those results are never written)
+        const double* xc[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) xc[i] = a.X + (size_t)min(j0 + 16 * wv + i, a.ncols - 1) * a.ldx + 2 * lane;
+        auto load = [&](int s, double2 (&R)[16]) {
+            const int row = s * DW_ROWS + 2 * lane;
+            if (s < nfull) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const dw_d2v v = __builtin_nontemporal_load(reinterpret_cast<const dw_d2v*>(xc[i] + s * DW_ROWS));
+                    R[i].x = v.x;
+                    R[i].y = v.y;
+                }
+            } else {
+                // ragged last stage: rows past m are zero
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    R[i].x = (row < m) ? xc[i][s * DW_ROWS] : 0.0;
+                    R[i].y = (row + 1 < m) ? xc[i][s * DW_ROWS + 1] : 0.0;
+                }
+            }
+        };
+        auto store = [&](int buf, const double2 (&R)[16]) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                *reinterpret_cast<double2*>(st + (buf * NCOL + 16 * wv + i) * DW_CB + 2 * lane) = R[i];
+            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the stage is in LDS
+        };
+        // stage s + 1 is in flight while stage s is stored; one barrier per stage
+        double2 R0[16], R1[16];
+        load(0, R0);
+        for (int s = 0; s < ns; s += 2) {
+            if (s + 1 < ns) load(s + 1, R1);
+            store(0, R0);
+            dw_barrier();
+            if (s + 1 < ns) {
+                if (s + 2 < ns) load(s + 2, R0);
+                store(1, R1);
+                dw_barrier();
+            }
+        }
+    } else {
+        // consumer wave q: rows 32 q .. 32 q + 31 of every stage, all 64 columns
+        const int q = wv - 4, g = lane >> 4, cl = lane & 15;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            rd[c] = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[c][t] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+        // vector block rows of row group G (stage G / 4, group G % 4), two
+        // groups ahead of their use; rows past m are clamped (A is zero there)
+        auto dload = [&](int G, double2 (&D)[1 + NT]) {
+            const int row = min((G >> 2) * DW_ROWS + 32 * q + 8 * (G & 3) + 2 * g, m - 1);
+            const double2* d2 = reinterpret_cast<const double2*>(a.Dt) + (size_t)(row >> 1) * a.ldd;
+            D[0] = d2[0];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) D[1 + t] = d2[1 + 16 * t + cl];
+            asm volatile("" ::: "memory");   // keep the prefetch where it is issued
+        };
+        auto xload = [&](int buf, int rg, double2 (&X)[4]) {
+            const double* sb = st + (buf * NCOL + cl) * DW_CB + 32 * q + 8 * rg + 2 * g;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) X[c] = *reinterpret_cast<const double2*>(sb + 16 * c * DW_CB);
+        };
+        auto mm = [&](const double2 (&X)[4], const double2 (&D)[1 + NT]) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                rd[c] = fma(X[c].x, D[0].x, rd[c]);
+                rd[c] = fma(X[c].y, D[0].y, rd[c]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[c].x, D[1 + t].x, acc[c][t], 0, 0, 0);
+                    acc[c][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[c].y, D[1 + t].y, acc[c][t], 0, 0, 0);
+                }
+            }
+        };
+        double2 D0[1 + NT], D1[1 + NT], D2[1 + NT], D3[1 + NT];
+        dload(0, D0);
+        dload(1, D1);
+        for (int s = 0; s < ns; ++s) {
+            dw_barrier();
+            const int buf = s & 1, G = 4 * s;
+            double2 X0[4], X1[4];
+            xload(buf, 0, X0);
+            dload(G + 2, D2);
+            xload(buf, 1, X1);
+            mm(X0, D0);
+            dload(G + 3, D3);
+            xload(buf, 2, X0);
+            mm(X1, D1);
+            dload(G + 4, D0);
+            xload(buf, 3, X1);
+            mm(X0, D2);
+            dload(G + 5, D1);
+            mm(X1, D3);
+        }
+    }
+    __syncthreads();   // every stage consumed: the stage buffers take the partial results
+    double* Cs = st;                              // [consumer][c][t][register][lane]
+    double* Rs = st + 4 * 4 * NT * 4 * 64;        // [consumer][c][lane]
+    if (wv >= 4) {
+        const int q = wv - 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double r = rd[c];
+            r += __shfl_xor(r, 16, 64);
+            r += __shfl_xor(r, 32, 64);
+            Rs[(q * 4 + c) * 64 + lane] = r;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Cs[(((q * 4 + c) * NT + t) * 4 + v) * 64 + lane] = acc[c][t][v];
+        }
+    }
+    __syncthreads();
+    if (tid >= NCOL) return;
+    // thread tid: column j0 + tid, i.e. tile tid / 16, column 4 v + l / 16 = tid % 16
+    const int c = tid >> 4, jc = tid & 15, v = jc >> 2;
+    const int j = j0 + tid;
+    if (j >= a.ncols) return;
+    const auto part = [&](int qq, int t, int l) { return Cs[(((qq * 4 + c) * NT + t) * 4 + v) * 64 + l]; };
+    const auto rpart = [&](int qq) { return Rs[(qq * 4 + c) * 64 + jc]; };
+    const double rsum = ((rpart(0) + rpart(1)) + rpart(2)) + rpart(3);
+    const Prob& p = a.p;
+    p.w[j] = rsum;
+    double u2 = a.exact ? 0.0 : p.u2[j];
+    for (int qv = 0; qv + 1 < a.nvec; ++qv) {
+        // vector 1 + qv: tile qv / 16, lane (jc % 4) * 16 + qv % 16, register v
+        const int t = qv >> 4, l = (jc & 3) * 16 + (qv & 15);
+        const double d = ((part(0, t, l) + part(1, t, l)) + part(2, t, l)) + part(3, t, l);
+        if (!a.exact && qv + 1 <= a.kadd) u2 -= d * d;
+        else u2 += d * d;
+    }
+    u2 = fmax(u2, 0.0);
+    if (!a.exact && p.pos[j] < 0 && u2 < RECOMP_FRAC * p.an2[j]) {
+        const int slotn = atomicAdd(a.nrecomp, 1);
+        a.recomp[slotn] = j;
+    }
+    p.u2[j] = u2;
+}
+
 __global__ __launch_bounds__(WG) void lg_gather_dual(LgArgs a, int v0, int pair) {
     const LgExtra* ex = a.ex;
     if (a.ex->restart) return;
@@ -2444,9 +2626,11 @@ static bool colmat2_fits(const ColmatArgs& ca) {
 static void colmat2_launch(hipStream_t st, ColmatArgs ca) {
     ca.al16 = 1;
     if (ca.mode == MODE_DUAL) {
+        // up to 32 directions: producer/consumer kernel; 33 to 48: the products
+        // outweigh the stream and the single-role kernel keeps the MFMAs busier
         const dim3 g((ca.ncols + 63) / 64);
-        if (ca.nvec <= 17) hipLaunchKernelGGL((lg_colmat2<1, 4, 2, true>), g, dim3(WG), 0, st, ca);
-        else if (ca.nvec <= 33) hipLaunchKernelGGL((lg_colmat2<2, 4, 2, true, 3>), g, dim3(WG), 0, st, ca);
+        if (ca.nvec <= 17) hipLaunchKernelGGL((lg_dual_ws<1>), g, dim3(DW_WG), 0, st, ca);
+        else if (ca.nvec <= 33) hipLaunchKernelGGL((lg_dual_ws<2>), g, dim3(DW_WG), 0, st, ca);
         else hipLaunchKernelGGL((lg_colmat2<3, 4, 2, true, 3>), g, dim3(WG), 0, st, ca);
         return;
     }
