@@ -34,6 +34,7 @@ struct WgShared : Ctl {
 };
 
 struct Wg {
+    static constexpr int LB = 8;   // gathered loads issued together per thread
     Prob& p;
     const DevParams& prm;
     WgShared& s;
@@ -557,13 +558,29 @@ struct Wg {
         al = vmin(al);
         const int chunk = (nP + WG - 1) / WG;
         const int c0 = tid * chunk, c1 = min(nP, c0 + chunk);
-        for (int c = c0; c < c1; ++c) {
-            const int j = p.P[c];
-            const double xc = p.x[j], yc = yv[c];
-            double xn = xc + al * (yc - xc);
-            if (yc <= 0.0 && xc / (xc - yc) == al) xn = 0.0;
-            if (xn <= 0.0) xn = 0.0;
-            p.x[j] = xn;
+        // the positions of a chunk are distinct columns, so a batch's loads all
+        // go out before its stores (a store per position would order every
+        // later gathered load behind it)
+        for (int cb = c0; cb < c1; cb += LB) {
+            int j[LB];
+            double xc[LB], yc[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int c = min(cb + u, c1 - 1);
+                j[u] = p.P[c];
+                yc[u] = yv[c];
+            }
+#pragma unroll
+            for (int u = 0; u < LB; ++u) xc[u] = p.x[j[u]];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                if (cb + u < c1) {
+                    double xn = xc[u] + al * (yc[u] - xc[u]);
+                    if (yc[u] <= 0.0 && xc[u] / (xc[u] - yc[u]) == al) xn = 0.0;
+                    if (xn <= 0.0) xn = 0.0;
+                    p.x[j[u]] = xn;
+                }
+            }
         }
         collect_removals();
     }
@@ -573,24 +590,47 @@ struct Wg {
         const int nP = s.nP;
         const int chunk = (nP + WG - 1) / WG;
         const int c0 = tid * chunk, c1 = min(nP, c0 + chunk);
+        // flags of the chunk in batches of gathered loads; kept as a bit mask
+        // when the chunk has at most 64 positions
         int mine = 0;
-        for (int c = c0; c < c1; ++c)
-            if (p.x[p.P[c]] <= 0.0) ++mine;
-        s.cnt[tid] = mine;
-        __syncthreads();
-        if (tid == 0) {
-            int run = 0;
-            for (int t = 0; t < WG; ++t) {
-                const int v = s.cnt[t];
-                s.cnt[t] = run;
-                run += v;
-            }
-            s.q = run;
+        unsigned long long mask = 0;
+        for (int cb = c0; cb < c1; cb += LB) {
+            int j[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) j[u] = p.P[min(cb + u, c1 - 1)];
+            double xv[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) xv[u] = p.x[j[u]];
+#pragma unroll
+            for (int u = 0; u < LB; ++u)
+                if (cb + u < c1 && xv[u] <= 0.0) {
+                    ++mine;
+                    if (cb + u - c0 < 64) mask |= 1ull << (cb + u - c0);
+                }
+        }
+        // exclusive prefix sum of the counts in thread order: a scan within
+        // each wave, then the totals of the waves before it
+        int incl = mine;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += v;
         }
         __syncthreads();
-        int o = s.cnt[tid];
-        for (int c = c0; c < c1; ++c)
-            if (p.x[p.P[c]] <= 0.0) p.rm[o++] = c;
+        if (lane == 63) s.cnt[wid] = incl;
+        __syncthreads();
+        int o = incl - mine;
+        for (int w = 0; w < wid; ++w) o += s.cnt[w];
+        if (tid == WG - 1) s.q = o + mine;
+        if (chunk <= 64) {
+            while (mask) {
+                p.rm[o++] = c0 + __builtin_ctzll(mask);
+                mask &= mask - 1;
+            }
+        } else {
+            for (int c = c0; c < c1; ++c)
+                if (p.x[p.P[c]] <= 0.0) p.rm[o++] = c;
+        }
         __syncthreads();
     }
 
