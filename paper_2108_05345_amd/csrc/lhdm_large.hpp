@@ -2020,6 +2020,92 @@ __global__ __launch_bounds__(WG) void lg_qup2(LgArgs a) {
     }
 }
 
+// Pass 2 for panels of at most 32 reflectors and an even m, in two kernels.
+// lg_qw2 forms W2 = W T once for all rows (W the sum of pass 1's tile
+// partials, added in tile order, as in lg_qup2) and stores it by reflector,
+// W2[s m + row], in the W scratch.  lg_qup2v then applies Q_t -= W2 V^T on the
+// vector units: wave w of workgroup (bx, by) owns rows 512 bx + 128 w + 2 lane
+// and + 1, so each load and store of a column is 16 bytes per lane and 1 KB
+// per wave; its lanes keep their two rows of W2 in registers and the
+// reflector entries of the workgroup's QV_COLS trailing columns are broadcast
+// from LDS.  The products are about 7 us of FP64 FMA at n_P = m / 2 against
+// ~50 us of HBM time, so the pass is bound by the stream of Q.
+constexpr int QV_COLS = 64;   // trailing columns per workgroup of lg_qup2v
+
+__global__ __launch_bounds__(WG) void lg_qw2(LgArgs a) {
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int kr = ctl->kr, r0 = ctl->nP0, m = p.m, kq = p.kq;
+    if (kr == 0) return;
+    __shared__ double Wt[16][KM + 1];
+    const int i0 = blockIdx.x * 16;
+    const int ncb = (m - r0 + QCB - 1) / QCB;   // column tiles of pass 1
+    for (int e = threadIdx.x; e < 16 * kr; e += WG) {
+        const int rr = e % 16, sc = e / 16;
+        double w = 0.0;
+        if (i0 + rr < m)
+            for (int cb = 0; cb < ncb; ++cb) w += a.wpart[((size_t)cb * kq + sc) * m + i0 + rr];
+        Wt[rr][sc] = w;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * kr; e += WG) {
+        const int rr = e % 16, sc = e / 16;
+        double sum = 0.0;
+        for (int l = 0; l <= sc; ++l) sum += Wt[rr][l] * p.T[(size_t)sc * kq + l];
+        if (i0 + rr < m) p.W[(size_t)sc * m + i0 + rr] = sum;
+    }
+}
+
+__global__ __launch_bounds__(WG) void lg_qup2v(LgArgs a) {
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int kr = ctl->kr, r0 = ctl->nP0, m = p.m, kq = p.kq;
+    if (kr == 0) return;
+    const int cbeg = r0 + QV_COLS * blockIdx.y;
+    if (cbeg >= m) return;
+    const int nc = min(m, cbeg + QV_COLS) - cbeg;
+    __shared__ __attribute__((aligned(16))) double vs[QV_COLS][32];   // V[column][s], zero for s >= kr
+    for (int e = threadIdx.x; e < QV_COLS * 32; e += WG) {
+        const int cc = e >> 5, sc = e & 31;
+        vs[cc][sc] = (cc < nc && sc < kr) ? p.Vt[(size_t)(cbeg + cc) * kq + sc] : 0.0;
+    }
+    const int lane = threadIdx.x & 63, wv = wave_index();
+    const int row = blockIdx.x * 512 + 128 * wv + 2 * lane;   // even; row + 1 < m when row < m (m even)
+    const bool ok = row < m;
+    double w2[32][2];
+#pragma unroll
+    for (int sc = 0; sc < 32; ++sc) {
+        double2 v = double2{0.0, 0.0};
+        if (ok && sc < kr) v = *reinterpret_cast<const double2*>(p.W + (size_t)sc * m + row);
+        w2[sc][0] = v.x;
+        w2[sc][1] = v.y;
+    }
+    __syncthreads();
+    double* qc = p.Q + (size_t)cbeg * m + (ok ? row : 0);
+    constexpr int CU = 8;   // columns in flight per lane
+    for (int c0 = 0; c0 < nc; c0 += CU) {
+        double2 q[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) q[u] = *reinterpret_cast<const double2*>(qc + (size_t)min(c0 + u, nc - 1) * m);
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            if (c0 + u < nc) {
+                const int cc = c0 + u;
+                double o0 = 0.0, o1 = 0.0;
+#pragma unroll
+                for (int sc = 0; sc < 32; sc += 2) {
+                    const double2 v = *reinterpret_cast<const double2*>(&vs[cc][sc]);
+                    o0 = fma(w2[sc][0], v.x, o0);
+                    o1 = fma(w2[sc][1], v.x, o1);
+                    o0 = fma(w2[sc + 1][0], v.y, o0);
+                    o1 = fma(w2[sc + 1][1], v.y, o1);
+                }
+                if (ok) *reinterpret_cast<double2*>(qc + (size_t)cc * m) = double2{q[u].x - o0, q[u].y - o1};
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------------------------
 // R y = bt[0:nP]: workgroup g solves row block nb-1-g after the blocks below
 // it have published their part of y (epoch-tagged).  Each wave of the
@@ -2842,8 +2928,15 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev_join, side));
         hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, st, a);
-        if (mir->ctl.ncol <= 32) hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
-        else hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+        if (mir->ctl.ncol <= 32 && (m & 1) == 0) {
+            hipLaunchKernelGGL(lg_qw2, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+            hipLaunchKernelGGL(lg_qup2v, dim3((m + 511) / 512, (m - mir->ctl.nP + QV_COLS - 1) / QV_COLS), dim3(WG),
+                               0, st, a);
+        } else if (mir->ctl.ncol <= 32) {
+            hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+        } else {
+            hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+        }
         hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, st, a);
         HIPCHK(hipGetLastError());
