@@ -2027,8 +2027,9 @@ __global__ __launch_bounds__(WG) void lg_qup2(LgArgs a) {
 // vector units: wave w of workgroup (bx, by) owns rows 512 bx + 128 w + 2 lane
 // and + 1, so each load and store of a column is 16 bytes per lane and 1 KB
 // per wave; its lanes keep their two rows of W2 in registers and the
-// reflector entries of the workgroup's QV_COLS trailing columns are broadcast
-// from LDS.  The products are about 7 us of FP64 FMA at n_P = m / 2 against
+// reflector entries of the workgroup's cpw (<= QV_COLS) trailing columns are
+// broadcast from LDS (the host picks cpw so that the grid has ~512
+// workgroups).  The products are about 7 us of FP64 FMA at n_P = m / 2 against
 // ~50 us of HBM time, so the pass is bound by the stream of Q.
 constexpr int QV_COLS = 64;   // trailing columns per workgroup of lg_qup2v
 
@@ -2056,14 +2057,14 @@ __global__ __launch_bounds__(WG) void lg_qw2(LgArgs a) {
     }
 }
 
-__global__ __launch_bounds__(WG) void lg_qup2v(LgArgs a) {
+__global__ __launch_bounds__(WG) void lg_qup2v(LgArgs a, int cpw) {
     const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
     const int kr = ctl->kr, r0 = ctl->nP0, m = p.m, kq = p.kq;
     if (kr == 0) return;
-    const int cbeg = r0 + QV_COLS * blockIdx.y;
+    const int cbeg = r0 + cpw * blockIdx.y;
     if (cbeg >= m) return;
-    const int nc = min(m, cbeg + QV_COLS) - cbeg;
+    const int nc = min(m, cbeg + cpw) - cbeg;
     __shared__ __attribute__((aligned(16))) double vs[QV_COLS][32];   // V[column][s], zero for s >= kr
     for (int e = threadIdx.x; e < QV_COLS * 32; e += WG) {
         const int cc = e >> 5, sc = e & 31;
@@ -2929,9 +2930,10 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         HIPCHK(hipEventRecord(ev_join, side));
         hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, st, a);
         if (mir->ctl.ncol <= 32 && (m & 1) == 0) {
+            const int mp = m - mir->ctl.nP, gx = (m + 511) / 512;
+            const int cpw = std::min(QV_COLS, std::max(8, (mp * gx / 512) / 8 * 8));
             hipLaunchKernelGGL(lg_qw2, dim3((m + 15) / 16), dim3(WG), 0, st, a);
-            hipLaunchKernelGGL(lg_qup2v, dim3((m + 511) / 512, (m - mir->ctl.nP + QV_COLS - 1) / QV_COLS), dim3(WG),
-                               0, st, a);
+            hipLaunchKernelGGL(lg_qup2v, dim3(gx, (mp + cpw - 1) / cpw), dim3(WG), 0, st, a, cpw);
         } else if (mir->ctl.ncol <= 32) {
             hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
         } else {
