@@ -1848,10 +1848,22 @@ __global__ __launch_bounds__(WG) void lg_residual_part(LgArgs a) {
     if (row >= p.m) return;
     const int per = (nP + RES_CHUNKS - 1) / RES_CHUNKS;
     const int c0 = chunk * per, c1 = min(nP, c0 + per);
+    // eight columns' loads go out together; the sum keeps the column order
+    constexpr int RB = 8;
     double acc = 0.0;
-    for (int cc = c0; cc < c1; ++cc) {
-        const int j = p.P[cc];
-        acc += p.A[(size_t)j * p.lda + row] * p.x[j];
+    for (int cb = c0; cb < c1; cb += RB) {
+        int j[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) j[u] = p.P[min(cb + u, c1 - 1)];
+        double av[RB], xv[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            av[u] = p.A[(size_t)j[u] * p.lda + row];
+            xv[u] = p.x[j[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+            if (cb + u < c1) acc += av[u] * xv[u];
     }
     a.rpart[(size_t)chunk * p.m + row] = acc;
 }
