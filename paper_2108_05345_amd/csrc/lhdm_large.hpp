@@ -2032,7 +2032,7 @@ __global__ __launch_bounds__(WG) void lg_qup2(LgArgs a) {
     }
 }
 
-// Pass 2 for panels of at most 32 reflectors and an even m, in two kernels.
+// Pass 2 for panels of 3 to 32 reflectors and an even m, in two kernels.
 // lg_qw2 forms W2 = W T once for all rows (W the sum of pass 1's tile
 // partials, added in tile order, as in lg_qup2) and stores it by reflector,
 // W2[s m + row], in the W scratch.  lg_qup2v then applies Q_t -= W2 V^T on the
@@ -2941,7 +2941,9 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ev_join, side));
         hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, st, a);
-        if (mir->ctl.ncol <= 32 && (m & 1) == 0) {
+        // one or two reflectors (plain LH): the single-kernel pass 2 is cheaper
+        // than forming W2 in a launch of its own
+        if (mir->ctl.ncol <= 32 && mir->ctl.ncol > 2 && (m & 1) == 0) {
             const int mp = m - mir->ctl.nP, gx = (m + 511) / 512;
             const int cpw = std::min(QV_COLS, std::max(8, (mp * gx / 512) / 8 * 8));
             hipLaunchKernelGGL(lg_qw2, dim3((m + 15) / 16), dim3(WG), 0, st, a);

@@ -711,27 +711,54 @@ struct Wg {
         if (q == 0) return;
         int* oldP = p.itmp;
         int* oldS = p.itmp + p.kc;
-        for (int c = tid; c < nP; c += WG) {
-            oldP[c] = p.P[c];
-            oldS[c] = p.slot[c];
+        // the int arrays may alias as far as the compiler knows: each batch's
+        // loads go out before its stores, instead of one round trip per position
+        for (int c0 = tid; c0 < nP; c0 += WG * LB) {
+            int pv[LB], sv[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int c = min(c0 + WG * u, nP - 1);
+                pv[u] = p.P[c];
+                sv[u] = p.slot[c];
+            }
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int c = c0 + WG * u;
+                if (c < nP) {
+                    oldP[c] = pv[u];
+                    oldS[c] = sv[u];
+                }
+            }
         }
         __syncthreads();
-        for (int c = tid; c < nP; c += WG) {
-            int lo = 0, hi = q;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (p.rm[mid] < c) lo = mid + 1;
-                else hi = mid;
+        for (int c0 = tid; c0 < nP; c0 += WG * LB) {
+            int pv[LB], sv[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int c = min(c0 + WG * u, nP - 1);
+                pv[u] = oldP[c];
+                sv[u] = oldS[c];
             }
-            const int j = oldP[c];
-            if (lo < q && p.rm[lo] == c) {
-                p.pos[j] = -1;
-                p.slot[nP - q + lo] = oldS[c];
-            } else {
-                const int w = c - lo;
-                p.P[w] = j;
-                p.slot[w] = oldS[c];
-                p.pos[j] = w;
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int c = c0 + WG * u;
+                if (c >= nP) continue;
+                int lo = 0, hi = q;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (p.rm[mid] < c) lo = mid + 1;
+                    else hi = mid;
+                }
+                const int j = pv[u];
+                if (lo < q && p.rm[lo] == c) {
+                    p.pos[j] = -1;
+                    p.slot[nP - q + lo] = sv[u];
+                } else {
+                    const int w = c - lo;
+                    p.P[w] = j;
+                    p.slot[w] = sv[u];
+                    p.pos[j] = w;
+                }
             }
         }
         __syncthreads();
