@@ -493,6 +493,7 @@ __device__ __forceinline__ void dt_coords(size_t e, int pair, int& row, int& t) 
     }
 }
 __global__ __launch_bounds__(WG) void lg_gather_cand(LgArgs a, int pair) {
+    if (a.ctl->done) return;   // launched before the host reads the selection
     const Prob& p = a.p;
     const int nc = a.ctl->ncol, m = p.m;
     const size_t tot = (size_t)(pair ? (m + 1) / 2 * 2 : m) * 64;
@@ -1191,9 +1192,11 @@ __global__ __launch_bounds__(WG) void lg_compact(LgArgs a, int rotbt) {
     if (rotbt && threadIdx.x < 64) rotate_bt_unit(a);
 }
 
+// x = y on the passive set once the inner loop has accepted y; launched
+// before the host reads the inner decision, so it checks that decision itself.
 __global__ __launch_bounds__(WG) void lg_copy_x(LgArgs a) {
     const Ctl* c = a.ctl;
-    if (c->k == 0) return;
+    if (c->k == 0 || !a.ex->inner_done || c->status == LHDM_STATUS_MAXITER) return;
     const Prob& p = a.p;
     const int nP = c->nP;
     for (int i = blockIdx.x * WG + threadIdx.x; i < nP; i += gridDim.x * WG) p.x[p.P[i]] = p.ybuf[i];
@@ -2245,6 +2248,7 @@ __device__ __forceinline__ void givens_lane(double a, double b, int t, double& c
 
 __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     const LgExtra* ex = a.ex;
+    if (ex->inner_done) return;   // launched before the host reads the inner decision
     const Prob& p = a.p;
     const int nd = ex->ndown, first = ex->first;
     const int nb = (nd + GB - 1) / GB;
@@ -2879,21 +2883,32 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         const int ps = next_pub();
         hipLaunchKernelGGL(lg_sel_main, dim3(1), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli, ps);
         HIPCHK(hipGetLastError());
+        // candidate projection G = Q^T A_J.  When the pipelined kernel can take
+        // all kq panel columns it goes out before the selection is read: the
+        // gather and the projection read J and its size on the device and skip
+        // when the selection ended the solve (columns past ncol come out zero).
+        ColmatArgs ca{};
+        ca.X = p.Q;
+        ca.ldx = m;
+        ca.m = m;
+        ca.ncols = m;
+        ca.Dt = a.Dt;
+        ca.ldd = 64;
+        ca.mode = MODE_PROJ;
+        ca.out = p.G;
+        ca.ldo = m;
+        ca.p = p;
+        ca.nvec = p.kq;
+        const bool early = colmat2_fits(ca);
+        if (early) {
+            ca.skip = &a.ctl->done;
+            hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, st, a, 1);
+            colmat2_launch(st, ca);
+            HIPCHK(hipGetLastError());
+        }
         if ((rc = wait_pub(ps))) return rc;
         if (mir->ctl.done) break;
-        // candidate projection G = Q^T A_J
-        {
-            ColmatArgs ca{};
-            ca.X = p.Q;
-            ca.ldx = m;
-            ca.m = m;
-            ca.ncols = m;
-            ca.Dt = a.Dt;
-            ca.ldd = 64;
-            ca.mode = MODE_PROJ;
-            ca.out = p.G;
-            ca.ldo = m;
-            ca.p = p;
+        if (!early) {
             ca.nvec = mir->ctl.ncol;
             const bool pair = colmat2_fits(ca);
             hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, st, a, (int)pair);
@@ -2961,6 +2976,12 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         while (true) {
             const int pi = next_pub();
             hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, st, a, pi);
+            // both continuations go out before the decision is read, each
+            // checking it on the device: the downdate of an inner step, and
+            // x = y when the inner loop ends
+            ++ep_g;
+            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ep_g);
+            hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, st, a);
             HIPCHK(hipGetLastError());
             if ((rc = wait_pub(pi))) return rc;
             if (ex_h()->restart) {
@@ -2971,8 +2992,6 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
                 if (mir->ctl.status == LHDM_STATUS_MAXITER) stop = true;
                 break;
             }
-            ++ep_g;
-            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ep_g);
             if (ex_h()->totrot == ex_h()->ndown) {
                 // one rotation per column: bt is rotated with the compaction, and
                 // the triangular solve runs on the side stream beside the Q rotations
@@ -2995,7 +3014,6 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
         }
         if (restart) continue;
-        if (!stop) hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, st, a);
         hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, st, a);
         if (stop) {
             hipLaunchKernelGGL(lg_residual_sum, dim3(rgrid), dim3(WG), 0, st, a);
