@@ -2818,6 +2818,10 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     HIPCHK(hipHostGetDevicePointer((void**)&a.hmir, mir, 0));
 
     // whole-stream synchronisation (start and end of the solve)
+    // the loop runs on `cs` and forks the triangular solve onto `os`; at each
+    // join the roles swap, so that the next kernel follows the solve on its own
+    // stream and only waits on the other chain, which is usually done by then
+    hipStream_t cs = st, os = nullptr;
     auto read_ctl = [&]() -> int {
         HIPCHK(hipMemcpyAsync(mir, a.ctl, offsetof(Mirror, seq), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -2836,7 +2840,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         for (unsigned it = 1;; ++it) {
             if (__atomic_load_n(&mir->seq, __ATOMIC_ACQUIRE) == want) break;
             if ((it & 1023u) == 0) {
-                const hipError_t e = hipStreamQuery(st);
+                const hipError_t e = hipStreamQuery(cs);
                 if (e == hipSuccess && __atomic_load_n(&mir->seq, __ATOMIC_ACQUIRE) == want) break;
                 if (e != hipErrorNotReady) return LHDM_EHIP;
             }
@@ -2872,16 +2876,17 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             side_dev = dev;
         }
     }
+    os = side;
     const int ggrid = 256;
     const int tgrid = (p.kc + TB - 1) / TB;
     const int rgrid = (m + WG - 1) / WG;
     bool stop = mir->ctl.status != LHDM_STATUS_OK;
     while (!stop) {
-        hipLaunchKernelGGL(lg_sel_part, dim3(NSEL), dim3(WG), 0, st, a, a.selv, a.seli);
+        hipLaunchKernelGGL(lg_sel_part, dim3(NSEL), dim3(WG), 0, cs, a, a.selv, a.seli);
         if (!prm.lh && prm.kmax > 1)
-            hipLaunchKernelGGL(lg_sel_cand, dim3(NSEL), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli);
+            hipLaunchKernelGGL(lg_sel_cand, dim3(NSEL), dim3(WG), 0, cs, a, (const double*)a.selv, (const int*)a.seli);
         const int ps = next_pub();
-        hipLaunchKernelGGL(lg_sel_main, dim3(1), dim3(WG), 0, st, a, (const double*)a.selv, (const int*)a.seli, ps);
+        hipLaunchKernelGGL(lg_sel_main, dim3(1), dim3(WG), 0, cs, a, (const double*)a.selv, (const int*)a.seli, ps);
         HIPCHK(hipGetLastError());
         // candidate projection G = Q^T A_J.  When the pipelined kernel can take
         // all kq panel columns it goes out before the selection is read: the
@@ -2902,8 +2907,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         const bool early = colmat2_fits(ca);
         if (early) {
             ca.skip = &a.ctl->done;
-            hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, st, a, 1);
-            colmat2_launch(st, ca);
+            hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, cs, a, 1);
+            colmat2_launch(cs, ca);
             HIPCHK(hipGetLastError());
         }
         if ((rc = wait_pub(ps))) return rc;
@@ -2911,16 +2916,16 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         if (!early) {
             ca.nvec = mir->ctl.ncol;
             const bool pair = colmat2_fits(ca);
-            hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, st, a, (int)pair);
-            if (pair) colmat2_launch(st, ca);
-            else if ((rc = colmat_launch(st, ca))) return rc;
+            hipLaunchKernelGGL(lg_gather_cand, dim3(ggrid), dim3(WG), 0, cs, a, (int)pair);
+            if (pair) colmat2_launch(cs, ca);
+            else if ((rc = colmat_launch(cs, ca))) return rc;
             HIPCHK(hipGetLastError());
         }
         const int gblk = (m + GRAM_ROWS - 1) / GRAM_ROWS;
         if (mir->ctl.ncol > 1) {
-            hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 0, a.gpart);
+            hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, cs, a, 0, a.gpart);
         }
-        hipLaunchKernelGGL(lg_greedy, dim3(1), dim3(WG), 0, st, a, (const double*)a.gpart);
+        hipLaunchKernelGGL(lg_greedy, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart);
         {
             const int mp = m - mir->ctl.nP;
             int rpw = std::max(64, (mp + PNW - 1) / PNW);
@@ -2936,52 +2941,53 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             ++ep_p;
             if (lds <= (size_t)PANEL_LDS_MAX) {
                 // also writes V, V^T and the new R columns
-                hipLaunchKernelGGL(lg_panel_mw, dim3(npw + (mir->ctl.nP + WG - 1) / WG), dim3(WG), lds, st, a, rpw,
+                hipLaunchKernelGGL(lg_panel_mw, dim3(npw + (mir->ctl.nP + WG - 1) / WG), dim3(WG), lds, cs, a, rpw,
                                    ep_p * 256);
             } else {
-                hipLaunchKernelGGL(lg_panel_1wg, dim3(1), dim3(WG), 0, st, a);
-                hipLaunchKernelGGL(lg_panel_v, dim3(64), dim3(WG), 0, st, a);
+                hipLaunchKernelGGL(lg_panel_1wg, dim3(1), dim3(WG), 0, cs, a);
+                hipLaunchKernelGGL(lg_panel_v, dim3(64), dim3(WG), 0, cs, a);
             }
         }
         if (mir->ctl.ncol > 1) {
-            hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, st, a, 1, a.gpart);
+            hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, cs, a, 1, a.gpart);
         }
-        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, st, a, (const double*)a.gpart);
+        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart);
         // the triangular solve needs R, bt and the accepted count only: it runs
-        // on the side stream while the Q update and the commit run here
-        HIPCHK(hipEventRecord(ev_fork, st));
-        HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+        // on the other stream while the Q update and the commit run here
+        HIPCHK(hipEventRecord(ev_fork, cs));
+        HIPCHK(hipStreamWaitEvent(os, ev_fork, 0));
         ++ep_t;
-        hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, side, a, ep_t, 1);
+        hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, os, a, ep_t, 1);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipEventRecord(ev_join, side));
-        hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, cs, a);
         // one or two reflectors (plain LH): the single-kernel pass 2 is cheaper
         // than forming W2 in a launch of its own
         if (mir->ctl.ncol <= 32 && mir->ctl.ncol > 2 && (m & 1) == 0) {
             const int mp = m - mir->ctl.nP, gx = (m + 511) / 512;
             const int cpw = std::min(QV_COLS, std::max(8, (mp * gx / 512) / 8 * 8));
-            hipLaunchKernelGGL(lg_qw2, dim3((m + 15) / 16), dim3(WG), 0, st, a);
-            hipLaunchKernelGGL(lg_qup2v, dim3(gx, (mp + cpw - 1) / cpw), dim3(WG), 0, st, a, cpw);
+            hipLaunchKernelGGL(lg_qw2, dim3((m + 15) / 16), dim3(WG), 0, cs, a);
+            hipLaunchKernelGGL(lg_qup2v, dim3(gx, (mp + cpw - 1) / cpw), dim3(WG), 0, cs, a, cpw);
         } else if (mir->ctl.ncol <= 32) {
-            hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+            hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, cs, a);
         } else {
-            hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, st, a);
+            hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, cs, a);
         }
-        hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, st, a);
-        hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, cs, a);
+        hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, cs, a);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+        HIPCHK(hipEventRecord(ev_join, cs));
+        HIPCHK(hipStreamWaitEvent(os, ev_join, 0));
+        std::swap(cs, os);
         bool restart = false;
         while (true) {
             const int pi = next_pub();
-            hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, st, a, pi);
+            hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, cs, a, pi);
             // both continuations go out before the decision is read, each
             // checking it on the device: the downdate of an inner step, and
             // x = y when the inner loop ends
             ++ep_g;
-            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ep_g);
-            hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, st, a);
+            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, cs, a, ep_g);
+            hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, cs, a);
             HIPCHK(hipGetLastError());
             if ((rc = wait_pub(pi))) return rc;
             if (ex_h()->restart) {
@@ -2994,29 +3000,30 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             if (ex_h()->totrot == ex_h()->ndown) {
                 // one rotation per column: bt is rotated with the compaction, and
-                // the triangular solve runs on the side stream beside the Q rotations
-                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a, 1);
-                HIPCHK(hipEventRecord(ev_fork, st));
-                HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+                // the triangular solve runs on the other stream beside the Q rotations
+                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, cs, a, 1);
+                HIPCHK(hipEventRecord(ev_fork, cs));
+                HIPCHK(hipStreamWaitEvent(os, ev_fork, 0));
                 ++ep_t;
-                hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, side, a, ep_t, 0);
+                hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, os, a, ep_t, 0);
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipEventRecord(ev_join, side));
-                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a, 1);
+                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, cs, a, 1);
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+                HIPCHK(hipEventRecord(ev_join, cs));
+                HIPCHK(hipStreamWaitEvent(os, ev_join, 0));
+                std::swap(cs, os);
             } else {
-                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a, 0);
-                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a, 0);
+                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, cs, a, 0);
+                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, cs, a, 0);
                 ++ep_t;
-                hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, st, a, ep_t, 0);
+                hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, cs, a, ep_t, 0);
                 HIPCHK(hipGetLastError());
             }
         }
         if (restart) continue;
-        hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, cs, a);
         if (stop) {
-            hipLaunchKernelGGL(lg_residual_sum, dim3(rgrid), dim3(WG), 0, st, a);
+            hipLaunchKernelGGL(lg_residual_sum, dim3(rgrid), dim3(WG), 0, cs, a);
             HIPCHK(hipGetLastError());
             break;
         }
@@ -3046,20 +3053,20 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
             const bool pair = colmat2_fits(ca);
             // the first block also forms r and the sizes of the update
-            if (v0 == 0) hipLaunchKernelGGL(lg_dual_prep, dim3(ggrid), dim3(WG), 0, st, a, (int)pair);
-            else hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, st, a, v0, (int)pair);
-            const int ev = kprof_begin(st);
-            if (pair) colmat2_launch(st, ca);
-            else if ((rc = colmat_launch(st, ca))) return rc;
+            if (v0 == 0) hipLaunchKernelGGL(lg_dual_prep, dim3(ggrid), dim3(WG), 0, cs, a, (int)pair);
+            else hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, cs, a, v0, (int)pair);
+            const int ev = kprof_begin(cs);
+            if (pair) colmat2_launch(cs, ca);
+            else if ((rc = colmat_launch(cs, ca))) return rc;
             HIPCHK(hipGetLastError());
-            kprof_end(st, ev, bytes);
+            kprof_end(cs, ev, bytes);
         }
-        hipLaunchKernelGGL(lg_recompute, dim3(64), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_recompute, dim3(64), dim3(WG), 0, cs, a);
         HIPCHK(hipGetLastError());
     }
     if (stop && mir->ctl.status == LHDM_STATUS_MAXITER) {
         // x is the last feasible iterate: refresh w for it
-        hipLaunchKernelGGL(lg_gather_r, dim3(ggrid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL(lg_gather_r, dim3(ggrid), dim3(WG), 0, cs, a);
         ColmatArgs ca{};
         ca.X = A;
         ca.ldx = lda;
@@ -3072,9 +3079,14 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         ca.ldo = n;
         ca.nvec = 1;
         ca.p = p;
-        if ((rc = colmat_launch(st, ca))) return rc;
+        if ((rc = colmat_launch(cs, ca))) return rc;
     }
-    hipLaunchKernelGGL(lg_finalize, dim3(1), dim3(WG), 0, st, a);
+    hipLaunchKernelGGL(lg_finalize, dim3(1), dim3(WG), 0, cs, a);
+    if (cs != st) {
+        // the caller's stream takes over from the one the loop ended on
+        HIPCHK(hipEventRecord(ev_join, cs));
+        HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+    }
     HIPCHK(hipGetLastError());
     if ((rc = read_ctl())) return rc;
     return 0;
