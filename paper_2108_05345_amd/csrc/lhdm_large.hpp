@@ -1843,7 +1843,9 @@ __global__ __launch_bounds__(WG) void lg_recompute(LgArgs a) {
 // fixed-order reduction.
 __global__ __launch_bounds__(WG) void lg_residual_part(LgArgs a) {
     const Ctl* c = a.ctl;
-    if (a.ex->restart) return;
+    // launched before the host reads the inner decision: runs once the inner
+    // loop has ended (and the outer step appended something)
+    if (a.ex->restart || !a.ex->inner_done) return;
     const Prob& p = a.p;
     const int nP = c->nP;
     const int row = blockIdx.x * WG + threadIdx.x;
@@ -2984,10 +2986,11 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, cs, a, pi);
             // both continuations go out before the decision is read, each
             // checking it on the device: the downdate of an inner step, and
-            // x = y when the inner loop ends
+            // x = y and the residual partials when the inner loop ends
             ++ep_g;
             hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, cs, a, ep_g);
             hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, cs, a);
+            hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, cs, a);
             HIPCHK(hipGetLastError());
             if ((rc = wait_pub(pi))) return rc;
             if (ex_h()->restart) {
@@ -3021,7 +3024,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
         }
         if (restart) continue;
-        hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, cs, a);
+        // r's partials are already queued (they ran once the inner loop ended)
         if (stop) {
             hipLaunchKernelGGL(lg_residual_sum, dim3(rgrid), dim3(WG), 0, cs, a);
             HIPCHK(hipGetLastError());
