@@ -132,6 +132,97 @@ def write_traffic(fetch_csv, write_csv):
     log("wrote", TRAFFIC_FILE, out)
 
 
+def _summary(infos):
+    st = {}
+    for i in infos:
+        st[str(i["status"])] = st.get(str(i["status"]), 0) + 1
+    return {"status_counts": st, "kkt_max": max(i["kkt_residual"] for i in infos),
+            "outer_mean": sum(i["outer_iters"] for i in infos) / len(infos),
+            "inner_mean": sum(i["inner_iters"] for i in infos) / len(infos),
+            "passive_mean": sum(i["n_passive"] for i in infos) / len(infos)}
+
+
+def _timed(fn, reps):
+    """Median wall time (s) of `reps` synchronised calls after one untimed call."""
+    import torch
+    out = fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    return ts[len(ts) // 2], out
+
+
+def run_config(name, reps):
+    """Throughput of the other workloads: C1 and C4 (batched, one persistent
+    launch), C2 (single solves on the whole-device engine), C5 (batched forward
+    and the backward).  Prints one JSON line; the default run (C3) is the
+    headline measurement."""
+    import numpy as np
+    import torch
+
+    import paper_2108_05345_amd as lhdm
+    from workloads import make_c1, make_c2, make_c4_batch, make_c5_batch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    out = {"config": name, "data": "synthetic", "dtype": "f64", "timing": f"median of {reps} after 1 warm-up"}
+    if name in ("c1", "c4", "c5"):
+        if name == "c1":
+            insts = [make_c1(1000 + i) for i in range(1000)]
+        elif name == "c4":
+            insts = make_c4_batch(4000)
+        else:
+            insts = make_c5_batch(5000)
+        As = [torch.from_numpy(np.ascontiguousarray(i.A)).to(dev) for i in insts]
+        bs = [torch.from_numpy(i.b).to(dev) for i in insts]
+        pool = lhdm.pack(As, bs)
+        del As, bs
+        B = len(insts)
+        out["instances"] = B
+        out["a_bytes"] = int(pool.A.numel() * 8)
+        for meth, use_lh in (("lhdm", False), ("lh", True)):
+            t, (x, passive, infos) = _timed(lambda: lhdm.solve_pooled(pool, use_lh=use_lh), reps)
+            out[meth] = {"solves_per_s": B / t, "ms_per_batch": 1e3 * t, **_summary(infos)}
+            log(name, meth, out[meth])
+            if name == "c5" and meth == "lhdm":
+                # backward of L = sum ||x_i - t_i||^2 through the final passive sets
+                t_all = torch.from_numpy(np.concatenate([i.t for i in insts])).to(dev)
+                gx = 2.0 * (x - t_all)
+                tb, _ = _timed(lambda: lhdm.backward_pooled(pool, x, passive, gx), reps)
+                out["backward"] = {"instances_per_s": B / tb, "ms_per_batch": 1e3 * tb,
+                                   "grad_a_bytes_written": int(pool.A.numel() * 8)}
+                log(name, "backward", out["backward"])
+    elif name == "c2":
+        count = 20
+        res = {"lhdm": [], "lh": []}
+        infos = {"lhdm": [], "lh": []}
+        for i in range(count):
+            inst = make_c2(2000 + i)
+            A = torch.from_numpy(np.asfortranarray(inst.A)).to(dev)
+            b = torch.from_numpy(inst.b).to(dev)
+            for meth in ("lhdm", "lh"):
+                fn = (lambda: lhdm.solve(A, b)) if meth == "lhdm" else (lambda: lhdm.lh_solve(A, b))
+                t, r = _timed(fn, max(1, reps // 5))
+                res[meth].append(t)
+                infos[meth].append(r.info)
+            log(name, i, {k: round(1e3 * v[-1], 2) for k, v in res.items()})
+            del A, b
+        out["instances"] = count
+        for meth in ("lhdm", "lh"):
+            ts = sorted(res[meth])
+            out[meth] = {"solves_per_s": count / sum(ts), "ms_median": 1e3 * ts[len(ts) // 2],
+                         **_summary(infos[meth])}
+    else:
+        raise SystemExit(f"unknown config {name}")
+    out["lhdm_over_lh"] = out["lhdm"]["solves_per_s"] / out["lh"]["solves_per_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,7 +238,16 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic file from two rocprofv3 --pmc counter_collection.csv "
                          "files (FETCH_SIZE, WRITE_SIZE) of a --copy-calibration run, then exit")
+    ap.add_argument("--config", choices=("c1", "c2", "c4", "c5"),
+                    help="measure another workload instead of the headline one (one JSON line)")
+    ap.add_argument("--reps", type=int, default=10, help="timed repeats for --config")
     args = ap.parse_args()
+    if args.config:
+        if args.gpus != 1:
+            print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+            sys.exit(2)
+        run_config(args.config, args.reps)
+        return
     if args.write_traffic:
         write_traffic(*args.write_traffic)
         return

@@ -30,10 +30,13 @@ struct BwdIn {
     size_t ws_off;   // byte offset of this instance's scratch
 };
 
+constexpr int BWD_MREG = 512;   // instances up to this m keep the reflector in LDS and columns in registers
+
 struct BwdShared {
     double rd[NW];
     double z[YMAX];
     double c[YMAX];
+    double vl[BWD_MREG];   // reflector of the current step (rows below the pivot)
     double tau;
     int nP;
 };
@@ -71,7 +74,71 @@ __global__ __launch_bounds__(WG) void backward_kernel(const BwdIn* __restrict__ 
     for (int c = tid; c < nP; c += WG) s.c[c] = in.g[in.passive[c]];
     __syncthreads();
     // Householder QR of F (m x nP), R in the upper triangle
-    for (int t = 0; t < nP; ++t) {
+    for (int t = 0; t < nP && m <= BWD_MREG; ++t) {
+        // the reflector stays in LDS (only R is used afterwards); each wave
+        // takes four columns at a time, their rows held in registers, so their
+        // loads go out together and no store waits in between
+        constexpr int RM = BWD_MREG / 64, CB = 4;
+        const double* v = F + (size_t)t * m;
+        double part = 0.0;
+        for (int i = t + tid; i < m; i += WG) {
+            const double vi = v[i];
+            s.vl[i] = vi;
+            part += vi * vi;
+        }
+        const double nrm = sqrt(wsum(part));
+        const double x0 = s.vl[t];
+        double tau = 0.0, beta = x0, scal = 0.0;
+        if (nrm > 0.0) {
+            beta = (x0 >= 0.0) ? -nrm : nrm;
+            tau = (beta - x0) / beta;
+            scal = 1.0 / (x0 - beta);
+        }
+        for (int i = t + 1 + tid; i < m; i += WG) s.vl[i] *= scal;
+        __syncthreads();
+        const int r0 = t + 1;
+        for (int cb = t + 1 + wid * CB; cb < nP; cb += NW * CB) {
+            double fv[CB][RM], d[CB], ft[CB];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const double* f = F + (size_t)min(cb + u, nP - 1) * m;
+                ft[u] = f[t];
+                d[u] = (lane == 0) ? ft[u] : 0.0;
+#pragma unroll
+                for (int k = 0; k < RM; ++k) {
+                    const int i = r0 + lane + 64 * k;
+                    fv[u][k] = (i < m) ? f[i] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < RM; ++k) {
+                const int i = r0 + lane + 64 * k;
+                if (i < m) {
+                    const double vi = s.vl[i];
+#pragma unroll
+                    for (int u = 0; u < CB; ++u) d[u] += vi * fv[u][k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CB; ++u) d[u] = wave_sum(d[u]) * tau;
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                if (cb + u < nP) {
+                    double* f = F + (size_t)(cb + u) * m;
+                    if (lane == 0) f[t] = ft[u] - d[u];
+#pragma unroll
+                    for (int k = 0; k < RM; ++k) {
+                        const int i = r0 + lane + 64 * k;
+                        if (i < m) f[i] = fv[u][k] - d[u] * s.vl[i];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) F[(size_t)t * m + t] = beta;
+        __syncthreads();
+    }
+    for (int t = 0; t < nP && m > BWD_MREG; ++t) {
         double* v = F + (size_t)t * m;
         double part = 0.0;
         for (int i = t + tid; i < m; i += WG) part += v[i] * v[i];
