@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <mutex>
 #include <vector>
@@ -115,6 +116,31 @@ inline int kprof_begin(hipStream_t st) {
     k.next += 2;
     (void)hipEventRecord(k.pool[i], st);
     return i;
+}
+
+// Event slot for a launch that records its own start and stop events
+// (hipExtLaunchKernelGGL: no separate event packets on the stream); -1 when off.
+inline int kprof_slot() {
+    KernelProfile& k = kprof();
+    if (!k.on) return -1;
+    if (k.pool.empty()) {
+        k.pool.resize(2048);
+        for (auto& e : k.pool)
+            if (hipEventCreate(&e) != hipSuccess) {
+                k.pool.clear();
+                k.on = false;
+                return -1;
+            }
+    }
+    if (k.next + 2 > (int)k.pool.size()) return -1;
+    const int i = k.next;
+    k.next += 2;
+    return i;
+}
+inline hipEvent_t kprof_event(int i) { return i < 0 ? nullptr : kprof().pool[i]; }
+// Register a launch timed through slot i (from kprof_slot).
+inline void kprof_commit(int i, double bytes) {
+    if (i >= 0) kprof().pending.push_back({i, bytes});
 }
 
 inline void kprof_end(hipStream_t st, int i, double bytes) {

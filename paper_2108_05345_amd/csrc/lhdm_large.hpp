@@ -2728,15 +2728,17 @@ static bool colmat2_fits(const ColmatArgs& ca) {
     if (ca.mode == MODE_DUAL) return ca.v0 == 0 && ca.nvec == ca.vtot && ca.nvec <= 49;
     return ca.nvec <= 48;
 }
-static void colmat2_launch(hipStream_t st, ColmatArgs ca) {
+// ev0 / ev1 (dual pass only, may be null): events the launch itself records at
+// the kernel's start and end.
+static void colmat2_launch(hipStream_t st, ColmatArgs ca, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     ca.al16 = 1;
     if (ca.mode == MODE_DUAL) {
         // up to 32 directions: producer/consumer kernel; 33 to 48: the products
         // outweigh the stream and the single-role kernel keeps the MFMAs busier
         const dim3 g((ca.ncols + 63) / 64);
-        if (ca.nvec <= 17) hipLaunchKernelGGL((lg_dual_ws<1>), g, dim3(DW_WG), 0, st, ca);
-        else if (ca.nvec <= 33) hipLaunchKernelGGL((lg_dual_ws<2>), g, dim3(DW_WG), 0, st, ca);
-        else hipLaunchKernelGGL((lg_colmat2<3, 4, 2, true, 3>), g, dim3(WG), 0, st, ca);
+        if (ca.nvec <= 17) hipExtLaunchKernelGGL((lg_dual_ws<1>), g, dim3(DW_WG), 0, st, ev0, ev1, 0, ca);
+        else if (ca.nvec <= 33) hipExtLaunchKernelGGL((lg_dual_ws<2>), g, dim3(DW_WG), 0, st, ev0, ev1, 0, ca);
+        else hipExtLaunchKernelGGL((lg_colmat2<3, 4, 2, true, 3>), g, dim3(WG), 0, st, ev0, ev1, 0, ca);
         return;
     }
     const dim3 g((ca.ncols + 15) / 16);
@@ -3058,11 +3060,18 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             // the first block also forms r and the sizes of the update
             if (v0 == 0) hipLaunchKernelGGL(lg_dual_prep, dim3(ggrid), dim3(WG), 0, cs, a, (int)pair);
             else hipLaunchKernelGGL(lg_gather_dual, dim3(ggrid), dim3(WG), 0, cs, a, v0, (int)pair);
-            const int ev = kprof_begin(cs);
-            if (pair) colmat2_launch(cs, ca);
-            else if ((rc = colmat_launch(cs, ca))) return rc;
-            HIPCHK(hipGetLastError());
-            kprof_end(cs, ev, bytes);
+            if (pair) {
+                // the launch records its own start and stop events
+                const int ev = kprof_slot();
+                colmat2_launch(cs, ca, kprof_event(ev), kprof_event(ev < 0 ? -1 : ev + 1));
+                HIPCHK(hipGetLastError());
+                kprof_commit(ev, bytes);
+            } else {
+                const int ev = kprof_begin(cs);
+                if ((rc = colmat_launch(cs, ca))) return rc;
+                HIPCHK(hipGetLastError());
+                kprof_end(cs, ev, bytes);
+            }
         }
         hipLaunchKernelGGL(lg_recompute, dim3(64), dim3(WG), 0, cs, a);
         HIPCHK(hipGetLastError());
