@@ -1192,16 +1192,6 @@ __global__ __launch_bounds__(WG) void lg_compact(LgArgs a, int rotbt) {
     if (rotbt && threadIdx.x < 64) rotate_bt_unit(a);
 }
 
-// x = y on the passive set once the inner loop has accepted y; launched
-// before the host reads the inner decision, so it checks that decision itself.
-__global__ __launch_bounds__(WG) void lg_copy_x(LgArgs a) {
-    const Ctl* c = a.ctl;
-    if (c->k == 0 || !a.ex->inner_done || c->status == LHDM_STATUS_MAXITER) return;
-    const Prob& p = a.p;
-    const int nP = c->nP;
-    for (int i = blockIdx.x * WG + threadIdx.x; i < nP; i += gridDim.x * WG) p.x[p.P[i]] = p.ybuf[i];
-}
-
 __global__ __launch_bounds__(WG) void lg_finalize(LgArgs a) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
@@ -1840,7 +1830,9 @@ __global__ __launch_bounds__(WG) void lg_recompute(LgArgs a) {
 }
 
 // r = b - A_P x_P in two passes: partial sums over column chunks, then a
-// fixed-order reduction.
+// fixed-order reduction.  The first pass also accepts y: unless the inner loop
+// stopped at its iteration limit (x then stays the last feasible iterate),
+// x_P = y, the sums use y directly and the first row block writes x.
 __global__ __launch_bounds__(WG) void lg_residual_part(LgArgs a) {
     const Ctl* c = a.ctl;
     // launched before the host reads the inner decision: runs once the inner
@@ -1848,11 +1840,14 @@ __global__ __launch_bounds__(WG) void lg_residual_part(LgArgs a) {
     if (a.ex->restart || !a.ex->inner_done) return;
     const Prob& p = a.p;
     const int nP = c->nP;
+    const bool accept = c->status != LHDM_STATUS_MAXITER;
     const int row = blockIdx.x * WG + threadIdx.x;
     const int chunk = blockIdx.y;
-    if (row >= p.m) return;
     const int per = (nP + RES_CHUNKS - 1) / RES_CHUNKS;
     const int c0 = chunk * per, c1 = min(nP, c0 + per);
+    if (accept && blockIdx.x == 0)
+        for (int cc = c0 + threadIdx.x; cc < c1; cc += WG) p.x[p.P[cc]] = p.ybuf[cc];
+    if (row >= p.m) return;
     // eight columns' loads go out together; the sum keeps the column order
     constexpr int RB = 8;
     double acc = 0.0;
@@ -1864,7 +1859,7 @@ __global__ __launch_bounds__(WG) void lg_residual_part(LgArgs a) {
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
             av[u] = p.A[(size_t)j[u] * p.lda + row];
-            xv[u] = p.x[j[u]];
+            xv[u] = accept ? p.ybuf[min(cb + u, c1 - 1)] : p.x[j[u]];
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u)
@@ -2988,10 +2983,9 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, cs, a, pi);
             // both continuations go out before the decision is read, each
             // checking it on the device: the downdate of an inner step, and
-            // x = y and the residual partials when the inner loop ends
+            // x = y with the residual partials when the inner loop ends
             ++ep_g;
             hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, cs, a, ep_g);
-            hipLaunchKernelGGL(lg_copy_x, dim3(16), dim3(WG), 0, cs, a);
             hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, cs, a);
             HIPCHK(hipGetLastError());
             if ((rc = wait_pub(pi))) return rc;
@@ -3026,7 +3020,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
         }
         if (restart) continue;
-        // r's partials are already queued (they ran once the inner loop ended)
+        // x = y and r's partials are already queued (they ran once the inner loop ended)
         if (stop) {
             hipLaunchKernelGGL(lg_residual_sum, dim3(rgrid), dim3(WG), 0, cs, a);
             HIPCHK(hipGetLastError());
