@@ -84,7 +84,7 @@ struct LgArgs {
     u64* rotll;       // 4 * kc * RQ : rotations published by the chained downdate
     int* recomp;      // n: columns whose projected norm is recomputed exactly
     double* rpart;    // RES_CHUNKS * m residual partial sums
-    double* gpart;    // partial Gram matrices (ceil(m / GRAM_ROWS) blocks of 64 x 64)
+    double* gpart;    // partial Gram matrices (max(ceil(m / GRAM_ROWS), PNW) blocks of 64 x 64)
     double* selv;     // 3 * NSEL partial maxima of the selection
     int* seli;        // NSEL partial argmax indices
     double* candw;    // CAND_CAP: collected candidates' dual values
@@ -862,6 +862,33 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
         const int i = e / kr, t = e % kr, row = rs + i;
         p.Vt[(size_t)row * p.kq + t] = (row >= r0 + t) ? pan[i * ld + t] : 0.0;
     }
+    // Partial V^T V over this workgroup's rows into slot w of gpart (the layout
+    // of lg_gram_part; lg_panel_b adds the npw slots in order): upper 16 x 16
+    // tiles on the matrix cores, V read from LDS with the same zeros as above
+    // (the padding rows past nr are zero).
+    {
+        double* out = a.gpart + (size_t)w * 64 * 64;
+        const int nt = (kr + 15) / 16;
+        const int g = lane >> 4;
+        auto vv = [&](int i, int q) {
+            const double x = pan[i * ld + min(q, kr - 1)];
+            return (q < kr && rs + i >= r0 + q) ? x : 0.0;
+        };
+        int tile = 0;
+        for (int ti = 0; ti < nt; ++ti)
+            for (int tj = ti; tj < nt; ++tj, ++tile) {
+                if ((tile % NW) != wv) continue;
+                d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+                const int ca = ti * 16 + (lane & 15), cb = tj * 16 + (lane & 15);
+                for (int r = 0; r < rpw; r += 8) {
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(vv(r + g, ca), vv(r + g, cb), acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vv(r + 4 + g, ca), vv(r + 4 + g, cb), acc1, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    out[(ti * 16 + 4 * v + (lane >> 4)) * 64 + tj * 16 + (lane & 15)] = acc0[v] + acc1[v];
+            }
+    }
 }
 
 // Single-workgroup panel factorisation (used when a row chunk of the panel
@@ -928,7 +955,8 @@ __device__ inline void wy_t_columns(const double (*Wl)[KM + 1], const double* ta
     }
 }
 
-__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part) {
+// part: nblk partial Gram blocks of V (the panel's workgroups, or 128-row blocks)
+__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, int nblk) {
     __shared__ WgShared s;
     __shared__ double Tl[KM][KM + 1];
     __shared__ double Wl[KM][KM + 1];
@@ -937,7 +965,6 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part) {
     const Prob& p = a.p;
     const int kr = s.kr, kq = p.kq, tid = threadIdx.x;
     // T of the compact WY form, from V^T V (summed from the partial blocks)
-    const int nblk = (p.m - s.nP + GRAM_ROWS - 1) / GRAM_ROWS;
     for (int e = tid; e < kr * kr; e += WG) {
         const int t = e % kr, i = e / kr;   // consecutive threads: consecutive t (coalesced)
         Wl[i][t] = (i < t) ? gram_entry(part, nblk, i, t) : 0.0;
@@ -2684,7 +2711,7 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.roff, sizeof(int) * kc);
     put(L.recomp, sizeof(int) * (size_t)n);
     put(L.rpart, sizeof(double) * (size_t)RES_CHUNKS * m);
-    put(L.gpart, sizeof(double) * (size_t)((m + GRAM_ROWS - 1) / GRAM_ROWS) * 64 * 64);
+    put(L.gpart, sizeof(double) * (size_t)std::max((m + GRAM_ROWS - 1) / GRAM_ROWS, PNW) * 64 * 64);
     put(L.selv, sizeof(double) * 3 * 64);
     put(L.seli, sizeof(int) * 64);
     put(L.candw, sizeof(double) * CAND_CAP);
@@ -2925,6 +2952,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, cs, a, 0, a.gpart);
         }
         hipLaunchKernelGGL(lg_greedy, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart);
+        int pblk = 0;   // partial Gram blocks of V read by lg_panel_b
         {
             const int mp = m - mir->ctl.nP;
             int rpw = std::max(64, (mp + PNW - 1) / PNW);
@@ -2939,18 +2967,18 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             ++ep_p;
             if (lds <= (size_t)PANEL_LDS_MAX) {
-                // also writes V, V^T and the new R columns
+                // also writes V, V^T, the new R columns and the partial V^T V
                 hipLaunchKernelGGL(lg_panel_mw, dim3(npw + (mir->ctl.nP + WG - 1) / WG), dim3(WG), lds, cs, a, rpw,
                                    ep_p * 256);
+                pblk = npw;
             } else {
                 hipLaunchKernelGGL(lg_panel_1wg, dim3(1), dim3(WG), 0, cs, a);
                 hipLaunchKernelGGL(lg_panel_v, dim3(64), dim3(WG), 0, cs, a);
+                hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, cs, a, 1, a.gpart);
+                pblk = (m - mir->ctl.nP + GRAM_ROWS - 1) / GRAM_ROWS;   // the blocks of rows >= n_P
             }
         }
-        if (mir->ctl.ncol > 1) {
-            hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, cs, a, 1, a.gpart);
-        }
-        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart);
+        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart, pblk);
         // the triangular solve needs R, bt and the accepted count only: it runs
         // on the other stream while the Q update and the commit run here
         HIPCHK(hipEventRecord(ev_fork, cs));
