@@ -2083,8 +2083,19 @@ __global__ __launch_bounds__(WG) void lg_qw2(LgArgs a) {
     for (int e = threadIdx.x; e < 16 * kr; e += WG) {
         const int rr = e % 16, sc = e / 16;
         double w = 0.0;
-        if (i0 + rr < m)
-            for (int cb = 0; cb < ncb; ++cb) w += a.wpart[((size_t)cb * kq + sc) * m + i0 + rr];
+        if (i0 + rr < m) {
+            // eight tiles' loads at a time; the sum keeps tile order
+            const double* q = a.wpart + (size_t)sc * m + i0 + rr;
+            int cb = 0;
+            for (; cb + 8 <= ncb; cb += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = q[(size_t)(cb + u) * kq * m];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) w += v[u];
+            }
+            for (; cb < ncb; ++cb) w += q[(size_t)cb * kq * m];
+        }
         Wt[rr][sc] = w;
     }
     __syncthreads();
