@@ -1173,39 +1173,79 @@ __global__ __launch_bounds__(WG) void lg_inner(LgArgs a, int pub) {
 // maps x -> a x + b across the lanes (six shuffle steps) instead of 64
 // dependent steps; the running entry carries from chunk to chunk.
 __device__ inline void rotate_bt_unit(const LgArgs& a) {
+    // All four waves take chunks at once (CPW each per round): each chunk's
+    // map comes from its own scan, one thread composes the chunk maps in order
+    // to get every chunk's incoming entry, then each lane writes its output.
+    // All loads of a round precede its stores (a chunk reads the first entry
+    // of the next one).
+    constexpr int CPW = 4, NCH = CPW * NW;
+    __shared__ double agA[NCH], agB[NCH], xin[NCH + 1];
     const LgExtra* ex = a.ex;
-    const int nd = ex->ndown, lane = threadIdx.x & 63;
+    const int nd = ex->ndown, lane = threadIdx.x & 63, wv = wave_index();
     double* bt = a.p.bt + ex->first;
     double x0 = bt[0];
-    for (int e0 = 0; e0 < nd; e0 += 64) {
-        const int ne = min(64, nd - e0);
-        double c = 1.0, sn = 0.0, y = 0.0;
-        if (lane < ne) {
-            const int ro = a.roff[e0 + lane];
-            c = a.rotbuf[2 * ro];
-            sn = a.rotbuf[2 * ro + 1];
-            y = bt[e0 + lane + 1];
+    for (int r0 = 0; r0 < nd; r0 += 64 * NCH) {
+        double cc[CPW], ss[CPW], yy[CPW], A[CPW], B[CPW];
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) {
+            const int q = wv * CPW + u, e0 = r0 + 64 * q;
+            const int ne = max(0, min(64, nd - e0));
+            double c = 1.0, sn = 0.0, y = 0.0;
+            if (lane < ne) {
+                const int ro = a.roff[e0 + lane];
+                c = a.rotbuf[2 * ro];
+                sn = a.rotbuf[2 * ro + 1];
+                y = bt[e0 + lane + 1];
+            }
+            cc[u] = c;
+            ss[u] = sn;
+            yy[u] = y;
+            A[u] = (lane < ne) ? -sn : 1.0;
+            B[u] = (lane < ne) ? c * y : 0.0;
         }
-        // map of rotation `lane` (identity past the chunk), then the scan:
-        // (A, B) <- (A, B) after (A', B') of lane - d
-        double A = (lane < ne) ? -sn : 1.0, B = (lane < ne) ? c * y : 0.0;
+        // inclusive scans of the maps x -> A x + B across the lanes
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            const double Ap = __shfl_up(A, d, 64), Bp = __shfl_up(B, d, 64);
-            if (lane >= d) {
-                B = fma(A, Bp, B);
-                A = A * Ap;
+#pragma unroll
+            for (int u = 0; u < CPW; ++u) {
+                const double Ap = __shfl_up(A[u], d, 64), Bp = __shfl_up(B[u], d, 64);
+                if (lane >= d) {
+                    B[u] = fma(A[u], Bp, B[u]);
+                    A[u] = A[u] * Ap;
+                }
             }
         }
-        // x after rotation `lane`; the input of rotation `lane` comes from lane - 1
-        // (the shuffle runs on every lane: a source lane must be active)
-        const double xa = fma(A, x0, B);
-        const double xu = __shfl_up(xa, 1, 64);
-        const double xin = (lane == 0) ? x0 : xu;
-        if (lane < ne) bt[e0 + lane] = c * xin + sn * y;
-        x0 = readlane_d(xa, ne - 1);
+        if (lane == 63) {
+#pragma unroll
+            for (int u = 0; u < CPW; ++u) {
+                agA[wv * CPW + u] = A[u];   // identity past the chunk: lane 63 holds the whole chunk's map
+                agB[wv * CPW + u] = B[u];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double x = x0;
+            for (int q = 0; q < NCH; ++q) {
+                xin[q] = x;
+                x = fma(agA[q], x, agB[q]);
+            }
+            xin[NCH] = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) {
+            const int q = wv * CPW + u, e0 = r0 + 64 * q;
+            const int ne = max(0, min(64, nd - e0));
+            const double xq = xin[q];
+            const double xa = fma(A[u], xq, B[u]);
+            const double xu = __shfl_up(xa, 1, 64);   // every lane takes part: a source lane must be active
+            const double xl = (lane == 0) ? xq : xu;
+            if (lane < ne) bt[e0 + lane] = cc[u] * xl + ss[u] * yy[u];
+        }
+        x0 = xin[NCH];
+        __syncthreads();   // xin and the aggregates are rewritten by the next round
     }
-    if (lane == 0) bt[nd] = x0;
+    if (threadIdx.x == 0) bt[nd] = x0;
 }
 
 // rotbt != 0: also rotate bt (the downdate's columns all carry one rotation;
@@ -1216,7 +1256,7 @@ __global__ __launch_bounds__(WG) void lg_compact(LgArgs a, int rotbt) {
     Wg wg(a.p, a.prm, s);
     wg.compact();
     ctl_store(s, a.ctl);
-    if (rotbt && threadIdx.x < 64) rotate_bt_unit(a);
+    if (rotbt) rotate_bt_unit(a);
 }
 
 __global__ __launch_bounds__(WG) void lg_finalize(LgArgs a) {
