@@ -1248,13 +1248,63 @@ __device__ inline void rotate_bt_unit(const LgArgs& a) {
     if (threadIdx.x == 0) bt[nd] = x0;
 }
 
+// The compaction of P and the slots when every passive position fits in the
+// registers of the workgroup (CLB per thread) and the removal list in LDS:
+// all loads go out before one barrier and the compacted arrays are stored
+// after it, with no staging copy (the same result as Wg::compact, which
+// takes the other cases).  Returns false when the sizes do not fit.
+constexpr int CLB = 16;
+constexpr int RM_LDS = 2048;
+__device__ inline bool compact_onepass(const Prob& p, WgShared& s) {
+    const int q = s.q, nP = s.nP, tid = threadIdx.x;
+    if (q == 0) return true;
+    if (nP > WG * CLB || q > RM_LDS) return false;
+    __shared__ int rms[RM_LDS];
+    int pv[CLB], sv[CLB];
+#pragma unroll
+    for (int u = 0; u < CLB; ++u) {
+        const int c = min(tid + WG * u, nP - 1);
+        pv[u] = p.P[c];
+        sv[u] = p.slot[c];
+    }
+    for (int t = tid; t < q; t += WG) rms[t] = p.rm[t];
+    // every load has returned before any position is overwritten
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < CLB; ++u) {
+        const int c = tid + WG * u;
+        if (c >= nP) continue;
+        int lo = 0, hi = q;   // removals before position c
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rms[mid] < c) lo = mid + 1;
+            else hi = mid;
+        }
+        const int j = pv[u];
+        if (lo < q && rms[lo] == c) {
+            p.pos[j] = -1;
+            p.slot[nP - q + lo] = sv[u];
+        } else {
+            const int w = c - lo;
+            p.P[w] = j;
+            p.slot[w] = sv[u];
+            p.pos[j] = w;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) s.nP = nP - q;
+    __syncthreads();
+    return true;
+}
+
 // rotbt != 0: also rotate bt (the downdate's columns all carry one rotation;
 // the Q rotations then leave bt alone).
 __global__ __launch_bounds__(WG) void lg_compact(LgArgs a, int rotbt) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
-    wg.compact();
+    if (!compact_onepass(a.p, s)) wg.compact();
     ctl_store(s, a.ctl);
     if (rotbt) rotate_bt_unit(a);
 }
