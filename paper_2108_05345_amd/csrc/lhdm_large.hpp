@@ -380,6 +380,88 @@ __global__ __launch_bounds__(WG) void lg_sel_cand(LgArgs a, const double* pv, co
     }
 }
 
+// The first kmax - 1 of cnt (> 256) collected candidates in (w desc, index
+// asc) order without sorting them all: w is mapped to SEL_NBK buckets by a map
+// that is monotone in w (rounding included), a histogram gives the first
+// bucket at which the running count reaches kmax - 1, and only the candidates
+// in that bucket and above are ranked.  Every wanted candidate, and every
+// candidate better than one of them, lies there, so the ranks within that
+// short list are the ranks among all.  Returns false (nothing placed) when
+// the short list would exceed SEL_SL (clustered values) or the map is
+// degenerate; the caller then sorts the whole list.
+constexpr int SEL_NBK = 256;
+constexpr int SEL_SL = 256;
+
+__device__ __forceinline__ int sel_bucket(double w, double bv, double scale) {
+    const double z = (bv - w) * scale;
+    return (z >= (double)(SEL_NBK - 1)) ? SEL_NBK - 1 : ((z > 0.0) ? (int)z : 0);
+}
+
+__device__ bool top_by_histogram(const LgArgs& a, WgShared& s, double* cw, int* ci, int cnt, double bv) {
+    __shared__ int hist[SEL_NBK];
+    __shared__ double lw[SEL_SL];
+    __shared__ int li[SEL_SL];
+    __shared__ int shB, shN;
+    const int K = a.prm.kmax - 1, tid = threadIdx.x;
+    const double scale = SEL_NBK / (bv - a.prm.tau1 * bv);
+    if (!(K < cnt && K <= SEL_SL && scale > 0.0 && scale < INFINITY)) return false;   // uniform
+    for (int e = tid; e < cnt; e += WG) {
+        cw[e] = a.candw[e];
+        ci[e] = a.candi[e];
+    }
+    for (int t = tid; t < SEL_NBK; t += WG) hist[t] = 0;
+    if (tid == 0) shN = 0;
+    __syncthreads();
+    for (int e = tid; e < cnt; e += WG) atomicAdd(&hist[sel_bucket(cw[e], bv, scale)], 1);
+    __syncthreads();
+    if (tid < 64) {
+        constexpr int PL = SEL_NBK / 64;   // buckets per lane
+        int h[PL], sum = 0;
+#pragma unroll
+        for (int u = 0; u < PL; ++u) {
+            h[u] = hist[tid * PL + u];
+            sum += h[u];
+        }
+        int inc = sum;   // inclusive scan of the lane sums (every lane takes part)
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(inc, d, 64);
+            if (tid >= d) inc += o;
+        }
+        int run = inc - sum, bk = SEL_NBK;
+#pragma unroll
+        for (int u = 0; u < PL; ++u) {
+            run += h[u];
+            if (run >= K && bk == SEL_NBK) bk = tid * PL + u;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) bk = min(bk, __shfl_xor(bk, o, 64));
+        if (tid == 0) shB = bk;   // < SEL_NBK: all cnt > K candidates are counted
+    }
+    __syncthreads();
+    const int B = shB;
+    for (int e = tid; e < cnt; e += WG) {
+        if (sel_bucket(cw[e], bv, scale) <= B) {
+            const int sl = atomicAdd(&shN, 1);
+            if (sl < SEL_SL) {
+                lw[sl] = cw[e];
+                li[sl] = ci[e];
+            }
+        }
+    }
+    __syncthreads();
+    const int nl = shN;
+    if (nl > SEL_SL) return false;   // uniform
+    for (int e = tid; e < nl; e += WG) {
+        const double we = lw[e];
+        const int je = li[e];
+        int r = 0;
+        for (int f = 0; f < nl; ++f) r += better(lw[f], li[f], we, je) ? 1 : 0;
+        if (r < K) s.J[1 + r] = je;
+    }
+    return true;
+}
+
 // Selection, pass 3 (one workgroup): termination test (a1) and the first
 // kmax - 1 collected candidates in (w desc, index asc) order, each placed by
 // its rank among the collected ones.  More than CAND_CAP candidates falls back
@@ -441,7 +523,7 @@ __global__ __launch_bounds__(WG) void lg_sel_main(LgArgs a, const double* pv, co
                     for (int f = 0; f < cnt; ++f) r += better(cw[f], ci[f], we, je) ? 1 : 0;
                     if (r < prm.kmax - 1) s.J[1 + r] = je;
                 }
-            } else {
+            } else if (!top_by_histogram(a, s, cw, ci, cnt, bv)) {
                 // bitonic sort of the padded list, best first
                 int nn = 512;
                 while (nn < cnt) nn <<= 1;

@@ -173,6 +173,23 @@ def test_device_engine_multiblock_sizes(lhdm):
         _check(lhdm.solve(A, b, kmax=1, engine="device"), xo, io, same_path=False, tag=f"dev-lh-{m}x{n}")
 
 
+def test_device_engine_many_candidates(lhdm):
+    # uniform entries make almost every column pass the candidate filter of
+    # Deviation Maximization at the first step (w_j >= tau1 max w and
+    # ||a_j|| >= tau2 max ||a||): more than 256 of them, under the collected
+    # list's capacity, so the first kmax - 1 are placed from the histogram's
+    # short list rather than by sorting the whole list
+    m, n = 300, 1800
+    inst = make_small(m, n, 60, 51, kind="uniform", noise_std=1e-2)
+    w = inst.A.T @ inst.b
+    u = np.linalg.norm(inst.A, axis=0)
+    cnt = int(np.count_nonzero((w >= 0.6 * w.max()) & (u >= 0.15 * u.max()))) - 1
+    assert 256 < cnt <= 2048, cnt
+    A, b = _dev(inst.A, inst.b)
+    xo, io = oracle.oracle_lhdm(inst.A, inst.b)
+    _check(lhdm.solve(A, b, engine="device"), xo, io, same_path=False, tag=f"cand-{m}x{n}")
+
+
 def test_device_engine_padded_leading_dimension(lhdm):
     # A given as a column-major view with a padded (even) leading dimension:
     # odd m with even lda takes the 16-byte-load column-block kernel for the
