@@ -632,21 +632,47 @@ __global__ __launch_bounds__(WG) void lg_gram_part(LgArgs a, int which, double* 
         }
 }
 
-// Entry (i, j), i <= j, of the Gram summed over the partial blocks in block order.
-// Loads are issued eight blocks at a time; the additions keep block order.
-__device__ inline double gram_entry(const double* part, int nblk, int i, int j) {
-    const double* q = part + i * 64 + j;
-    double sum = 0.0;
-    int blk = 0;
-    for (; blk + 8 <= nblk; blk += 8) {
-        double v[8];
+// The entries e = tid, tid + WG, ... of an n x n Gram matrix ((i, j) = (e / n,
+// e % n)) for which keep(i, j) holds, each the sum of the nblk partial blocks
+// in block order (from 0.0, block 0 first), handed to put(i, j, value);
+// put(i, j, 0.0) for the other entries.  A thread takes its entries GS_E at a time and keeps
+// the loads of GS_B blocks in flight for all of them together, so the sums
+// cost about nblk / GS_B memory round trips per GS_E entries instead of
+// nblk / 8 per entry.
+constexpr int GS_E = 4, GS_B = 16;
+template <typename Keep, typename Put>
+__device__ inline void gram_entries(const double* part, int nblk, int n, Keep keep, Put put) {
+    const int tid = threadIdx.x, ne = n * n;
+    for (int e0 = tid; e0 < ne; e0 += WG * GS_E) {
+        int off[GS_E];
+        bool use[GS_E];
+        double acc[GS_E];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = q[(size_t)(blk + u) * 64 * 64];
+        for (int u = 0; u < GS_E; ++u) {
+            const int e = e0 + WG * u, i = e / n, j = e % n;
+            use[u] = e < ne && keep(i, j);
+            off[u] = use[u] ? i * 64 + j : 0;
+            acc[u] = 0.0;
+        }
+        for (int b0 = 0; b0 < nblk; b0 += GS_B) {
+            double v[GS_E][GS_B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) sum += v[u];
+            for (int u = 0; u < GS_E; ++u)
+#pragma unroll
+                for (int bb = 0; bb < GS_B; ++bb)
+                    v[u][bb] = (use[u] && b0 + bb < nblk) ? part[(size_t)(b0 + bb) * 64 * 64 + off[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < GS_E; ++u)
+#pragma unroll
+                for (int bb = 0; bb < GS_B; ++bb)
+                    if (b0 + bb < nblk) acc[u] += v[u][bb];
+        }
+#pragma unroll
+        for (int u = 0; u < GS_E; ++u) {
+            const int e = e0 + WG * u;
+            if (e < ne) put(e / n, e % n, use[u] ? acc[u] : 0.0);
+        }
     }
-    for (; blk < nblk; ++blk) sum += q[(size_t)blk * 64 * 64];
-    return sum;
 }
 
 // Deviation maximization's greedy test (Algorithm 2) on the candidates' Gram
@@ -668,10 +694,10 @@ __global__ __launch_bounds__(WG) void lg_greedy(LgArgs a, const double* part) {
     if (c > 1) {
         // the candidates' Gram matrix from the partial blocks (upper part)
         const int nblk = (p.m - s.nP + GRAM_ROWS - 1) / GRAM_ROWS;
-        for (int e = tid; e < c * c; e += WG) {
-            const int ra = e / c, t = e % c;
-            if (ra <= t) Tl[ra][t] = gram_entry(part, nblk, ra, t);
-        }
+        gram_entries(part, nblk, c, [](int ra, int t) { return ra <= t; },
+                     [&](int ra, int t, double v) {
+                         if (ra <= t) Tl[ra][t] = v;
+                     });
         __syncthreads();
         if (tid < c) sq[tid] = sqrt(Tl[tid][tid]);
         __syncthreads();
@@ -1047,10 +1073,8 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, i
     const Prob& p = a.p;
     const int kr = s.kr, kq = p.kq, tid = threadIdx.x;
     // T of the compact WY form, from V^T V (summed from the partial blocks)
-    for (int e = tid; e < kr * kr; e += WG) {
-        const int t = e % kr, i = e / kr;   // consecutive threads: consecutive t (coalesced)
-        Wl[i][t] = (i < t) ? gram_entry(part, nblk, i, t) : 0.0;
-    }
+    gram_entries(part, nblk, kr, [](int i, int t) { return i < t; },   // consecutive threads: consecutive t
+                 [&](int i, int t, double v) { Wl[i][t] = v; });
     __syncthreads();
     if (tid < 64) {
         if (kr <= 32) {
