@@ -100,7 +100,16 @@ struct LgArgs {
 __device__ inline void ctl_load(WgShared& s, const Ctl* g) {
     int* d = reinterpret_cast<int*>(static_cast<Ctl*>(&s));
     const int* src = reinterpret_cast<const int*>(g);
-    for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int)); i += blockDim.x) d[i] = src[i];
+    constexpr int NI = (int)(sizeof(Ctl) / sizeof(int));
+    const int bd = blockDim.x;
+    // two words per thread and step, both loads before either store: one
+    // memory round trip for the whole block at 256 threads
+    for (int i = threadIdx.x; i < NI; i += 2 * bd) {
+        const bool two = i + bd < NI;
+        const int v0 = src[i], v1 = two ? src[i + bd] : 0;
+        d[i] = v0;
+        if (two) d[i + bd] = v1;
+    }
     __syncthreads();
 }
 
@@ -1197,7 +1206,14 @@ __device__ void inner_body(LgArgs& a, WgShared& s) {
         wg.collect_removals();
     } else {
         double mn = INFINITY;
-        for (int c = threadIdx.x; c < s.nP; c += WG) mn = fmin(mn, p.ybuf[c]);
+        const int nP = s.nP;
+        for (int c0 = threadIdx.x; c0 < nP; c0 += WG * 8) {
+            double v[8];   // eight loads in flight per thread
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = (c0 + WG * u < nP) ? p.ybuf[c0 + WG * u] : INFINITY;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) mn = fmin(mn, v[u]);
+        }
         mn = wg.vmin(mn);
         if (mn > 0.0) {
             if (threadIdx.x == 0) ex->inner_done = 1;
