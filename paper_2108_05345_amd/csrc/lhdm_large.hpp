@@ -3250,18 +3250,19 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             if (ex_h()->totrot == ex_h()->ndown) {
                 // one rotation per column: bt is rotated with the compaction, and
-                // the triangular solve runs on the other stream beside the Q rotations
+                // the Q rotations run on the other stream beside the triangular
+                // solve, which is the longer of the two and so follows the
+                // compaction directly (no event wait on its path)
                 hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, cs, a, 1);
                 HIPCHK(hipEventRecord(ev_fork, cs));
                 HIPCHK(hipStreamWaitEvent(os, ev_fork, 0));
                 ++ep_t;
-                hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, os, a, ep_t, 0);
+                hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, cs, a, ep_t, 0);
                 HIPCHK(hipGetLastError());
-                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, cs, a, 1);
+                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, os, a, 1);
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipEventRecord(ev_join, cs));
-                HIPCHK(hipStreamWaitEvent(os, ev_join, 0));
-                std::swap(cs, os);
+                HIPCHK(hipEventRecord(ev_join, os));
+                HIPCHK(hipStreamWaitEvent(cs, ev_join, 0));
             } else {
                 hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, cs, a, 0);
                 hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, cs, a, 0);
