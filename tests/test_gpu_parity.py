@@ -190,6 +190,31 @@ def test_device_engine_many_candidates(lhdm):
     _check(lhdm.solve(A, b, engine="device"), xo, io, same_path=False, tag=f"cand-{m}x{n}")
 
 
+def test_device_engine_long_downdate(lhdm, monkeypatch):
+    # 1200 x 2400 Gaussian, 1100-sparse planted solution: one inner step
+    # removes a single column more than 1024 positions before the end of the
+    # passive set, so the compaction's scan of bt over the downdate's
+    # rotations (16 chunks of 64 per round) takes more than one round.  The
+    # oracle's removal positions are recorded to check that the instance
+    # still has such a step.
+    import oracle.nnls as onn
+    inst = make_small(1200, 2400, 1100, 61, kind="gauss", noise_std=1e-3)
+    seen = []
+    step = onn._inner_step
+
+    def recording_step(st, x, y):
+        nP, P = st.nP, list(st.P)
+        out = step(st, x, y)
+        seen.append((nP, sorted(P.index(j) for j in out[0])))
+        return out
+
+    monkeypatch.setattr(onn, "_inner_step", recording_step)
+    xo, io = oracle.oracle_lhdm(inst.A, inst.b)
+    assert any(len(pos) == 1 and nP - 1 - pos[0] > 1024 for nP, pos in seen)
+    A, b = _dev(inst.A, inst.b)
+    _check(lhdm.solve(A, b, engine="device"), xo, io, unique=False, tag="long-downdate")
+
+
 def test_device_engine_padded_leading_dimension(lhdm):
     # A given as a column-major view with a padded (even) leading dimension:
     # odd m with even lda takes the 16-byte-load column-block kernel for the
