@@ -3203,31 +3203,38 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         }
         hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart, pblk);
         // the triangular solve needs R, bt and the accepted count only: it runs
-        // on the other stream while the Q update and the commit run here
+        // beside the Q update and the commit, on two streams.  The longer of
+        // the two branches follows lg_panel_b on its stream and the other one
+        // waits for the fork event: the Q update while the trailing part of Q
+        // is wide, the solve (a chain over n_P / 64 row blocks) once n_P passes
+        // about two thirds of m, where the two cross on a 4096-row instance.
+        const bool solve_direct = 3 * mir->ctl.nP > 2 * m;
+        hipStream_t qs = solve_direct ? os : cs, ts = solve_direct ? cs : os;
         HIPCHK(hipEventRecord(ev_fork, cs));
         HIPCHK(hipStreamWaitEvent(os, ev_fork, 0));
         ++ep_t;
-        hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, os, a, ep_t, 1);
+        hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, ts, a, ep_t, 1);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, cs, a);
+        hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, qs, a);
         // one or two reflectors (plain LH): the single-kernel pass 2 is cheaper
         // than forming W2 in a launch of its own
         if (mir->ctl.ncol <= 32 && mir->ctl.ncol > 2 && (m & 1) == 0) {
             const int mp = m - mir->ctl.nP, gx = (m + 511) / 512;
             const int cpw = std::min(QV_COLS, std::max(8, (mp * gx / 512) / 8 * 8));
-            hipLaunchKernelGGL(lg_qw2, dim3((m + 15) / 16), dim3(WG), 0, cs, a);
-            hipLaunchKernelGGL(lg_qup2v, dim3(gx, (mp + cpw - 1) / cpw), dim3(WG), 0, cs, a, cpw);
+            hipLaunchKernelGGL(lg_qw2, dim3((m + 15) / 16), dim3(WG), 0, qs, a);
+            hipLaunchKernelGGL(lg_qup2v, dim3(gx, (mp + cpw - 1) / cpw), dim3(WG), 0, qs, a, cpw);
         } else if (mir->ctl.ncol <= 32) {
-            hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, cs, a);
+            hipLaunchKernelGGL(lg_qup2<8>, dim3((m + 15) / 16), dim3(WG), 0, qs, a);
         } else {
-            hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, cs, a);
+            hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, qs, a);
         }
-        hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, cs, a);
-        hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, cs, a);
+        hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, qs, a);
+        hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, qs, a);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipEventRecord(ev_join, cs));
-        HIPCHK(hipStreamWaitEvent(os, ev_join, 0));
-        std::swap(cs, os);
+        // the loop continues on the solve's stream once the other branch is in
+        HIPCHK(hipEventRecord(ev_join, qs));
+        HIPCHK(hipStreamWaitEvent(ts, ev_join, 0));
+        if (!solve_direct) std::swap(cs, os);
         bool restart = false;
         while (true) {
             const int pi = next_pub();
