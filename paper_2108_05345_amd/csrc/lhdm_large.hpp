@@ -1295,10 +1295,10 @@ __global__ __launch_bounds__(WG) void lg_inner(LgArgs a, int pub) {
 // maps x -> a x + b across the lanes (six shuffle steps) instead of 64
 // dependent steps; the running entry carries from chunk to chunk.
 __device__ inline void rotate_bt_unit(const LgArgs& a) {
-    // All four waves take chunks at once (CPW each per round): each chunk's
+    // All four waves take chunks at once (CPW each per sweep of 16 chunks): each chunk's
     // map comes from its own scan, one thread composes the chunk maps in order
     // to get every chunk's incoming entry, then each lane writes its output.
-    // All loads of a round precede its stores (a chunk reads the first entry
+    // All loads of a sweep precede its stores (a chunk reads the first entry
     // of the next one).
     constexpr int CPW = 4, NCH = CPW * NW;
     __shared__ double agA[NCH], agB[NCH], xin[NCH + 1];
@@ -1365,7 +1365,7 @@ __device__ inline void rotate_bt_unit(const LgArgs& a) {
             if (lane < ne) bt[e0 + lane] = cc[u] * xl + ss[u] * yy[u];
         }
         x0 = xin[NCH];
-        __syncthreads();   // xin and the aggregates are rewritten by the next round
+        __syncthreads();   // xin and the aggregates are rewritten by the next sweep
     }
     if (threadIdx.x == 0) bt[nd] = x0;
 }

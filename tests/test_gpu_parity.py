@@ -194,7 +194,7 @@ def test_device_engine_long_downdate(lhdm, monkeypatch):
     # 1200 x 2400 Gaussian, 1100-sparse planted solution: one inner step
     # removes a single column more than 1024 positions before the end of the
     # passive set, so the compaction's scan of bt over the downdate's
-    # rotations (16 chunks of 64 per round) takes more than one round.  The
+    # rotations (16 chunks of 64 per sweep) takes more than one sweep.  The
     # oracle's removal positions are recorded to check that the instance
     # still has such a step.
     import oracle.nnls as onn
