@@ -190,6 +190,30 @@ def test_device_engine_many_candidates(lhdm):
     _check(lhdm.solve(A, b, engine="device"), xo, io, same_path=False, tag=f"cand-{m}x{n}")
 
 
+def test_device_engine_tied_candidates(lhdm):
+    # 600 exact copies of the column with the largest w (uniform entries,
+    # that column scaled by 2): at the first step all of them pass the
+    # candidate filter with equal w, so the histogram's deciding bucket holds
+    # more than 256 candidates and the selection sorts the whole list; ties
+    # are ordered by index, as in the oracle
+    rng = np.random.default_rng(71)
+    m, n, ndup = 128, 900, 600
+    A = rng.uniform(0.0, 1.0, (m, n))
+    A[:, 0] *= 2.0
+    A[:, 1:1 + ndup] = A[:, [0]]
+    xs = np.zeros(n)
+    sup = rng.choice(np.arange(1 + ndup, n), 40, replace=False)
+    xs[sup] = rng.uniform(1.0, 2.0, 40)
+    xs[0] = 1.5
+    b = A @ xs + 1e-2 * rng.standard_normal(m)
+    w = A.T @ b
+    u = np.linalg.norm(A, axis=0)
+    assert int(np.argmax(w)) == 0
+    assert int(np.count_nonzero((w >= 0.6 * w.max()) & (u >= 0.15 * u.max()))) - 1 > 256
+    xo, io = oracle.oracle_lhdm(A, b)
+    _check(lhdm.solve(*_dev(A, b), engine="device"), xo, io, unique=False, tag="tied-candidates")
+
+
 def test_device_engine_long_downdate(lhdm, monkeypatch):
     # 1200 x 2400 Gaussian, 1100-sparse planted solution: one inner step
     # removes a single column more than 1024 positions before the end of the
