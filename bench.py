@@ -72,9 +72,29 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def oracle_full_solve(delta):
+    """Wall time of one complete oracle solve of the same instance, as stored by
+    the script that wrote the oracle's path fixtures (measured on the host that
+    ran it, with its BLAS thread count), or None when that fixture is absent."""
+    path = os.path.join(GOLDEN_DIR, f"c3_seed3000_delta{delta:.1f}.npz")
+    try:
+        import numpy as np
+        z = np.load(path, allow_pickle=False)
+        return {"seconds": float(z["seconds"]), "solves_per_s": 1.0 / float(z["seconds"]),
+                "blas_threads": int(z["threads"]), "host_cpu": str(z["host"]),
+                "outer_iters": int(z["counters"][1]), "source": os.path.relpath(path, ROOT)}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(inst, delta, outer_total, max_outer):
     """The CPU oracle on a bounded sample: the first `max_outer` outer steps of the
-    same LHDM solve, scaled by the fraction of the GPU solve's outer steps."""
+    same LHDM solve, scaled by the fraction of the GPU solve's outer steps (an
+    estimate: the first steps are the costliest, so it understates the oracle's
+    rate; the measured time of a whole oracle solve is reported beside it)."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -87,8 +107,10 @@ def cpu_baseline(inst, delta, outer_total, max_outer):
     done = info["outer_iters"]
     frac = done / max(outer_total, 1)
     return {"value": frac / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {done} of {outer_total} outer steps of the same LHDM solve (delta={delta}) "
-                      f"in {dt:.1f} s on the host, scaled by {done}/{outer_total}"}
+            "estimate": True,
+            "sample": f"estimate: first {done} of {outer_total} outer steps of the same LHDM solve "
+                      f"(delta={delta}) in {dt:.1f} s on the host, scaled by {done}/{outer_total}",
+            "full_solve_measured": oracle_full_solve(delta)}
 
 
 def _pmc_rows(path, counter):
@@ -130,6 +152,14 @@ def write_traffic(fetch_csv, write_csv):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     log("wrote", TRAFFIC_FILE, out)
+
+
+def check_converged(infos, what):
+    """Every timed solve must have converged at KKT tol 1e-9 (the metric's condition)."""
+    bad = [i for i in infos if i["status"] != 0 or not (i["kkt_residual"] <= 1e-9)]
+    if bad:
+        raise SystemExit(f"bench.py: {len(bad)} of {len(infos)} timed {what} solves did not converge: {bad[0]}")
+    return max(i["kkt_residual"] for i in infos)
 
 
 def _summary(infos):
@@ -231,6 +261,8 @@ def main():
     ap.add_argument("--lh-steps", type=int, default=1)
     ap.add_argument("--delta", type=float, default=0.8)
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer steps of the oracle sample (0: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=2,
+                    help="timed solves at each other delta of the sweep, 0.2 and 0.5 (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     ap.add_argument("--max-outer", type=int, default=0,
@@ -300,20 +332,44 @@ def main():
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     value = args.steps / (t1 - t0)
     log("lhdm", infos[-1], f"{ms_per_step:.1f} ms/solve")
+    kkt_worst = check_converged(infos, "LHDM") if args.max_outer == 0 else None
 
     lh_value = lh_ms = None
     lh_info = None
     if args.lh_steps > 0:
         torch.cuda.synchronize()
+        lh_infos = []
         t2 = time.perf_counter()
         for _ in range(args.lh_steps):
             rl = lhdm.lh_solve(A, b)
-            lh_info = rl.info
+            lh_infos.append(rl.info)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        lh_info = lh_infos[-1]
         lh_ms = 1e3 * (t3 - t2) / args.lh_steps
         lh_value = args.lh_steps / (t3 - t2)
         log("lh", lh_info, f"{lh_ms:.1f} ms/solve")
+        lh_info = dict(lh_info, kkt_worst=check_converged(lh_infos, "LH"))
+
+    # the other deviation thresholds of the sweep (same instance, same GPU)
+    sweep = {}
+    if args.sweep_steps > 0 and args.max_outer == 0:
+        for d in (0.2, 0.5):
+            if d == args.delta:
+                continue
+            r = lhdm.solve(A, b, delta=d)   # untimed first call
+            torch.cuda.synchronize()
+            sw_infos = []
+            t4 = time.perf_counter()
+            for _ in range(args.sweep_steps):
+                sw_infos.append(lhdm.solve(A, b, delta=d).info)
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            sweep[f"delta_{d}"] = {"value": args.sweep_steps / (t5 - t4), "unit": "solves/s",
+                                   "ms_per_solve": 1e3 * (t5 - t4) / args.sweep_steps,
+                                   "kkt_worst": check_converged(sw_infos, f"LHDM delta={d}"),
+                                   "info": sw_infos[-1]}
+            log("lhdm delta", d, sweep[f"delta_{d}"])
 
     roof = None
     if kl.value > 0:
@@ -349,7 +405,8 @@ def main():
         "config": {"workload": "gauss-4096x16384-k820-noise1e-3-seed3000", "m": m, "n": n,
                    "method": "lhdm", "tau1": 0.6, "tau2": 0.15, "delta": args.delta, "kmax": 32,
                    "kkt_tol": 1e-9},
-        "lhdm_info": infos[-1],
+        "lhdm_info": dict(infos[-1], kkt_worst=kkt_worst),
+        "delta_sweep": sweep or None,
         "lh": None if lh_value is None else {"value": lh_value, "unit": "solves/s", "ms_per_solve": lh_ms,
                                              "info": lh_info},
         "speedup_vs_lh": None if lh_value is None else value / lh_value,

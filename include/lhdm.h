@@ -20,7 +20,10 @@
  *   - Workspace: `ws` [dev] of at least the size returned by the matching
  *     *_workspace_bytes query, aligned to 256 bytes.  If ws is NULL the library
  *     allocates a workspace itself and keeps it cached per device until
- *     lhdm_release() is called.
+ *     lhdm_release() is called.  A workspace (the caller's or the cached one)
+ *     serves one call at a time: calls that overlap in time (from several host
+ *     threads, or on several streams) must use distinct workspaces, and the
+ *     cached workspace must then not be used by more than one of them.
  *   - Return value: 0 on success, a negative LHDM_E* code if the call itself
  *     failed (nothing was solved; outputs are unspecified).  The per-instance
  *     outcome is reported in lhdm_info.status (LHDM_STATUS_*).
@@ -57,7 +60,7 @@ extern "C" {
  * the values used throughout the paper's experiments (Section 5): tau1 = 0.6,
  * tau2 = 0.15, delta = 0.9, kmax = 32.  kkt_tol scales the outer-loop stopping
  * test: stop when max_{j in Z} w_j <= kkt_tol * max_j ||a_j||_2 * ||b||_2.
- * max_outer / max_inner <= 0 select 3n.  flags: LHDM_FLAG_* (0 = automatic engine:
+ * max_outer / max_inner <= 0 select 3n (per instance in lhdm_solve_batched).  flags: LHDM_FLAG_* (0 = automatic engine:
  * the one-workgroup engine for m <= 2048 and m*n <= 2^18, the whole-device
  * engine otherwise; lhdm_solve_batched always uses the one-workgroup engine). */
 typedef struct lhdm_params {
@@ -142,7 +145,10 @@ size_t lhdm_backward_workspace_bytes(int32_t batch, const int32_t* m, const int3
  * Layout as in lhdm_solve_batched: [host] size/offset arrays, [dev] pools.
  * passive_pool holds each instance's P (as returned by the forward call, -1
  * padded); grad_A_pool is fully overwritten (lda = m[i]); grad_b_pool gets m[i]
- * values at b_off[i]. */
+ * values at b_off[i].  Each instance is handled by one workgroup, which keeps
+ * its QR in the workspace and its multipliers in LDS: a batch holding an
+ * instance with min(m, n) > 2048 returns LHDM_EUNSUPPORTED (nothing is
+ * written). */
 int lhdm_backward(void* stream, int32_t batch, const int32_t* m, const int32_t* n,
                   const int64_t* a_off, const double* A_pool,
                   const int64_t* b_off, const double* b_pool,
@@ -151,9 +157,11 @@ int lhdm_backward(void* stream, int32_t batch, const int32_t* m, const int32_t* 
                   void* ws, size_t ws_bytes);
 
 /* Timing of the dominant kernel: the dual w = A^T r fused with the projected-
- * norm update (lg_colmat_dot in the whole-device engine).  When enabled, every
- * launch of it is bracketed by HIP events on the solve's stream; the elapsed
- * times are collected at the library's own stream synchronisations.
+ * norm update in the whole-device engine (lg_dual_ws for up to 32 update
+ * directions, lg_colmat2 for 33 to 48, lg_colmat_dot when A is not 16-byte
+ * aligned).  When enabled, every launch of it records a start and a stop event
+ * on the solve's stream (the launch records them itself where it can); the
+ * elapsed times are collected at the library's own stream synchronisations.
  * lhdm_profile_enable(1) resets the counters.  lhdm_profile_read reports the
  * summed kernel time [ms], the number of launches and the algorithmic bytes
  * those launches move (8 m n for A plus the vectors read and written). */

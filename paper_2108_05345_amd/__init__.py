@@ -227,7 +227,10 @@ class LHDMFunction(torch.autograd.Function):
     """x = argmin_{x >= 0} ||A x - b||, differentiable through the final passive set.
 
     ``LHDMFunction.apply(A, b)`` for one (m, n) instance; ``A`` and ``b`` are
-    float64 device tensors.  Solver parameters take their defaults."""
+    float64 device tensors.  Solver parameters take their defaults.  The forward
+    runs the one-workgroup engine and the backward one workgroup per instance, so
+    both need m <= 2048 (the backward min(m, n) <= 2048): larger instances raise
+    ``LhdmError`` (LHDM_EUNSUPPORTED)."""
 
     @staticmethod
     def forward(ctx, A, b):

@@ -54,7 +54,11 @@ __global__ __launch_bounds__(WG) void wg_solve_kernel(const ProbIn* __restrict__
         p.passive = in.passive;
         p.info = in.info;
         carve_slot(p, base, in.m, in.n, prm.kmax);
-        Wg wg(p, prm, sh);
+        // iteration limits <= 0 select 3 n of this instance
+        DevParams q = prm;
+        if (q.max_outer <= 0) q.max_outer = 3 * in.n;
+        if (q.max_inner <= 0) q.max_inner = 3 * in.n;
+        Wg wg(p, q, sh);
         wg.run();
         __syncthreads();
     }
@@ -94,14 +98,11 @@ struct WgLayout {
 };
 
 static int wg_slots_for(int batch) {
-    static int cus = -1;
-    if (cus < 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) cus = 256;
-        else cus = prop.multiProcessorCount;
-        if (cus <= 0) cus = 256;
-    }
+    // compute units of the current device (queried per call: a process may use several devices)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_solve_kernel, WG, 0) != hipSuccess || occ < 1)
         occ = 1;
@@ -311,8 +312,9 @@ int lhdm_solve_batched(void* stream, int32_t batch, const int32_t* m, const int3
         ins[i].n = n[i];
     }
     DevParams prm = dev_params(p, nmax, use_lh ? 1 : 0);
-    prm.max_outer = p->max_outer > 0 ? p->max_outer : 3 * nmax;
-    prm.max_inner = p->max_inner > 0 ? p->max_inner : 3 * nmax;
+    // non-positive limits are resolved per instance (3 n_i) by the kernel
+    prm.max_outer = p->max_outer > 0 ? p->max_outer : 0;
+    prm.max_inner = p->max_inner > 0 ? p->max_inner : 0;
     return run_wg_engine((hipStream_t)stream, ins, mm, nn, prm, ws, L.total);
 }
 

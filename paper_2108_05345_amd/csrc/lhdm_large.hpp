@@ -3043,18 +3043,13 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     unsigned long long* anmax_bits = (unsigned long long*)(base + L.misc);
     int* bad = (int*)(base + L.misc + 8);
 
-    // The hand-off buffers are matched by epoch.  Epochs only grow while the same
-    // buffers (same workspace, same kc) are reused; anything else clears them and
-    // restarts the epochs.
-    static thread_local void* last_ws = nullptr;
-    static thread_local int last_kc = -1;
-    static thread_local int ep_t = 0, ep_g = 0, ep_p = 0;
-    if (last_ws != ws || last_kc != p.kc || ep_t > (1 << 30) || ep_g > (1 << 30) || ep_p > (1 << 22)) {
-        HIPCHK(hipMemsetAsync(base + L.flt, 0, L.slot - L.flt, st));
-        ep_t = ep_g = ep_p = 0;
-        last_ws = ws;
-        last_kc = p.kc;
-    }
+    // The hand-off buffers are matched by epoch.  They are cleared at the start of
+    // every solve and the epochs restart from 1, so no word left in the
+    // workspace by an earlier call (of any entry point) can carry a live epoch.
+    // Epochs stay below 2^30 within one solve (at most a few per outer and inner
+    // step, bounded by max_outer and max_inner).
+    HIPCHK(hipMemsetAsync(base + L.flt, 0, L.slot - L.flt, st));
+    int ep_t = 0, ep_g = 0, ep_p = 0;
     // Host mirror in fine-grained (coherent) pinned memory: written by the
     // kernels that end with a host decision, polled here through `seq`.
     static thread_local Mirror* mir = nullptr;
@@ -3131,6 +3126,11 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     const int rgrid = (m + WG - 1) / WG;
     bool stop = mir->ctl.status != LHDM_STATUS_OK;
     while (!stop) {
+        if (ep_t > (1 << 30) || ep_g > (1 << 30) || ep_p > (1 << 22)) {
+            // every earlier launch is ordered before this point on cs
+            HIPCHK(hipMemsetAsync(base + L.flt, 0, L.slot - L.flt, cs));
+            ep_t = ep_g = ep_p = 0;
+        }
         hipLaunchKernelGGL(lg_sel_part, dim3(NSEL), dim3(WG), 0, cs, a, a.selv, a.seli);
         if (!prm.lh && prm.kmax > 1)
             hipLaunchKernelGGL(lg_sel_cand, dim3(NSEL), dim3(WG), 0, cs, a, (const double*)a.selv, (const int*)a.seli);
@@ -3182,11 +3182,15 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             rpw = ((rpw + 63) / 64) * 64;
             const int npw = (mp + rpw - 1) / rpw;
             const size_t lds = sizeof(double) * (size_t)rpw * (mir->ctl.ncol + 1);
-            static thread_local bool attr_set = false;
-            if (!attr_set) {
+            // the attribute is per device: set it once on each device a thread uses
+            static thread_local unsigned long long attr_devs = 0;
+            int cur_dev = 0;
+            HIPCHK(hipGetDevice(&cur_dev));
+            const unsigned long long bit = cur_dev < 64 ? (1ull << cur_dev) : 0ull;
+            if (!(attr_devs & bit) || bit == 0) {
                 HIPCHK(hipFuncSetAttribute((const void*)lg_panel_mw, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            PANEL_LDS_MAX));
-                attr_set = true;
+                attr_devs |= bit;
             }
             ++ep_p;
             if (lds <= (size_t)PANEL_LDS_MAX) {
