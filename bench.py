@@ -247,6 +247,39 @@ def run_config(name, reps):
             ts = sorted(res[meth])
             out[meth] = {"solves_per_s": count / sum(ts), "ms_median": 1e3 * ts[len(ts) // 2],
                          **_summary(infos[meth])}
+    elif name == "signflip":
+        # signed sparse recovery by the positivity trick (Section 3.2): the
+        # sign-flip inner loop (Section 4.2) against the ordinary inner loop,
+        # for LH and LHDM, on the same GPU and instance ([A, -A] never formed)
+        from workloads import make_signed
+        m, n, k = 2048, 4096, 512
+        inst = make_signed(m, n, k, 7000, noise_std=1e-3)
+        A = torch.from_numpy(np.asfortranarray(inst.A)).to(dev)
+        b = torch.from_numpy(inst.b).to(dev)
+        out["workload"] = f"signed-gauss-{m}x{n}-k{k}-noise1e-3-seed7000"
+        for meth, kmax in (("lh", 1), ("lhdm", 32)):
+            for flip in (True, False):
+                t, r = _timed(lambda: lhdm.solve_signed(A, b, sign_flip=flip, kmax=kmax), max(1, reps // 3))
+                key = f"{meth}_{'signflip' if flip else 'innerloop'}"
+                out[key] = {"solves_per_s": 1.0 / t, "ms_per_solve": 1e3 * t, **_summary([r.info])}
+                log(name, key, out[key])
+        out["lh_signflip_over_innerloop"] = out["lh_signflip"]["solves_per_s"] / out["lh_innerloop"]["solves_per_s"]
+        out["lhdm_signflip_over_innerloop"] = (out["lhdm_signflip"]["solves_per_s"] /
+                                               out["lhdm_innerloop"]["solves_per_s"])
+        out["lhdm"], out["lh"] = out["lhdm_signflip"], out["lh_signflip"]
+    elif name == "illcond":
+        # moderately ill-conditioned instance (condition number ~1e6): LHDM against LH
+        from workloads import make_illcond
+        m, n, k = 2048, 8192, 160
+        inst = make_illcond(m, n, k, 1e5, 8000)
+        A = torch.from_numpy(np.asfortranarray(inst.A)).to(dev)
+        b = torch.from_numpy(inst.b).to(dev)
+        out["workload"] = f"illcond-uniform-rowscaled-{m}x{n}-k{k}-rowrange1e5-seed8000"
+        for meth in ("lhdm", "lh"):
+            fn = (lambda: lhdm.solve(A, b)) if meth == "lhdm" else (lambda: lhdm.lh_solve(A, b))
+            t, r = _timed(fn, max(1, reps // 3))
+            out[meth] = {"solves_per_s": 1.0 / t, "ms_per_solve": 1e3 * t, **_summary([r.info])}
+            log(name, meth, out[meth])
     else:
         raise SystemExit(f"unknown config {name}")
     out["lhdm_over_lh"] = out["lhdm"]["solves_per_s"] / out["lh"]["solves_per_s"]
@@ -270,7 +303,7 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic file from two rocprofv3 --pmc counter_collection.csv "
                          "files (FETCH_SIZE, WRITE_SIZE) of a --copy-calibration run, then exit")
-    ap.add_argument("--config", choices=("c1", "c2", "c4", "c5"),
+    ap.add_argument("--config", choices=("c1", "c2", "c4", "c5", "signflip", "illcond"),
                     help="measure another workload instead of the headline one (one JSON line)")
     ap.add_argument("--reps", type=int, default=10, help="timed repeats for --config")
     args = ap.parse_args()

@@ -54,6 +54,15 @@ extern "C" {
 /* lhdm_params.flags: engine selection (default 0 = automatic). */
 #define LHDM_FLAG_ENGINE_WORKGROUP 1  /* one workgroup per instance (m <= 2048) */
 #define LHDM_FLAG_ENGINE_DEVICE    2  /* one instance over the whole GPU */
+/* Theorem 4 (Section 3): with tau1 = 1 and tau2 <= 1/2 (and the selection's
+ * delta <= tau2 / (kmax - 1) of Theorem 2, which makes the block's Gram matrix
+ * diagonally dominant) the least-squares components of every accepted block J
+ * are positive, so the feasibility loop on J is not evaluated (the block is
+ * taken whole).  Requires tau1 == 1, tau2 <= 0.5 and delta <= tau2 / (kmax - 1),
+ * else LHDM_EINVAL.  A violation by rounding (excluded in exact
+ * arithmetic) is left to the inner loop, where a zero iterate entry with a
+ * nonpositive least-squares component gives the step length 0. */
+#define LHDM_FLAG_NO_JLOOP         4
 
 /* Solver parameters [host].  tau1, tau2, delta and kmax are the thresholds of
  * Algorithm 2 (delta is the tau_c of the Algorithm 3 signature); the defaults are
@@ -105,6 +114,46 @@ size_t lhdm_workspace_bytes(int32_t m, int32_t n, const lhdm_params* p);
 int lhdm_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda,
                const double* b, const lhdm_params* p, double* x, double* w,
                int32_t* passive, lhdm_info* info, void* ws, size_t ws_bytes);
+
+/* Signed least squares by the positivity trick (Section 3.2, problem
+ * (positivity trick)): min ||[A, -A] z - b||_2 s.t. z >= 0 with z = (x+, x-),
+ * solved by LHDM (or LH with kmax = 1) on the 2n columns of [A, -A] without
+ * forming -A: column j >= n is the caller's column j - n negated, and its dual
+ * is -w_{j-n}, so each outer step still reads A once.
+ *   sign_flip != 0: the inner loop of the positivity-trick case (Section 4.2):
+ *     each passive column whose least-squares component is negative is
+ *     replaced, at the same position, by its twin, which negates that column
+ *     of R and the component, leaves the residual unchanged and ends the inner
+ *     loop without a downdate; an exactly zero component takes the ordinary
+ *     inner iteration.  sign_flip == 0: the ordinary inner loop (step length
+ *     and Givens downdating) on [A, -A].
+ *   x [dev] n (out): the signed solution x+ - x-.
+ *   z [dev] 2n (out, may be NULL): (x+, x-).
+ *   passive [dev] 2n (out, may be NULL): P over the 2n columns, insertion
+ *     order, -1 padded.
+ *   info: as lhdm_solve (outer, inner iterations over the 2n-column problem;
+ *     a sign flip counts as one inner iteration).
+ * Other arguments, workspace and errors as lhdm_solve (workspace size from
+ * lhdm_signed_workspace_bytes). */
+size_t lhdm_signed_workspace_bytes(int32_t m, int32_t n, const lhdm_params* p);
+int lhdm_solve_signed(void* stream, int32_t m, int32_t n, const double* A, int64_t lda,
+                      const double* b, const lhdm_params* p, int32_t sign_flip, double* x,
+                      double* z, int32_t* passive, lhdm_info* info, void* ws, size_t ws_bytes);
+
+/* l1-NNLS (Section 3.3, problem (l1-NNLS)): the squared-l1 regularised least
+ * squares min ||x||_1^2 + lambda^2 ||A x - b||_2^2 in its NNLS form
+ *     min || [1^T, 1^T; lambda A, -lambda A] z - [0; lambda b] ||_2,  z >= 0,
+ * x = z[:n] - z[n:].  The (m + 1) x 2n matrix and the right-hand side are
+ * assembled in the workspace (8 (m + 1) 2n bytes) and solved by LHDM, or LH
+ * with kmax = 1.  lambda > 0 and finite, else LHDM_EINVAL.
+ *   x [dev] n (out): the signed solution.
+ *   z [dev] 2n (out, may be NULL);  passive [dev] 2n (out, may be NULL).
+ * Other arguments, workspace (lhdm_l1_workspace_bytes) and errors as
+ * lhdm_solve; the engine is chosen for the (m + 1) x 2n problem. */
+size_t lhdm_l1_workspace_bytes(int32_t m, int32_t n, const lhdm_params* p);
+int lhdm_solve_l1(void* stream, int32_t m, int32_t n, const double* A, int64_t lda,
+                  const double* b, double lambda, const lhdm_params* p, double* x, double* z,
+                  int32_t* passive, lhdm_info* info, void* ws, size_t ws_bytes);
 
 /* Plain Lawson-Hanson (Algorithm 1): one column per outer step with a rank-one
  * Householder append.  Same arguments and outputs as lhdm_solve. */

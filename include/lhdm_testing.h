@@ -1,0 +1,51 @@
+/*
+ * lhdm_testing.h -- test-only entry points of liblhdm.so.
+ *
+ * These calls expose single steps of the solvers so that tests can compare
+ * them with a reference implementation on inputs that the whole solve rarely
+ * produces.  They are not part of the solver API: they allocate and free their
+ * own device memory, synchronise the stream and are not tuned for speed.
+ * Conventions as in lhdm.h (float64, column-major, [dev] / [host] pointers,
+ * negative LHDM_E* return codes on failure).
+ */
+#ifndef LHDM_TESTING_H
+#define LHDM_TESTING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Algorithm 5 (Section 4.1, "Downdating"): delete the columns at the ascending
+ * positions rm[0..q) from the triangular factor of a QR factorisation of nP
+ * columns and restore the triangle with Givens rotations -- columns left to
+ * right, each column's subdiagonal entries annihilated bottom-up, every
+ * rotation acting on two adjacent rows -- applying the same rotations to Q^T b
+ * and to the columns of the orthogonal factor, exactly as one inner iteration
+ * of the solvers does.
+ *   engine 1: the one-workgroup engine (one sweep over all q positions);
+ *   engine 2: the whole-device engine (the solver's inner-step kernels, in
+ *             sweeps of at most 64 positions, the rest carried to the next
+ *             sweep as in the solver).
+ *   Q  [dev] m x m, column-major (ld m): the orthogonal factor.
+ *   R  [dev] nP x nP, column-major (ld nP): upper triangular factor (entries
+ *      below the diagonal are ignored).
+ *   bt [dev] m: Q^T b.
+ *   rm [host] q strictly ascending positions in [0, nP), 1 <= q <= nP.
+ *   Q_out [dev] m x m, R_out [dev] (nP-q) x (nP-q) (ld nP-q, zeros below the
+ *   diagonal), bt_out [dev] m: the downdated factors.
+ *   P_out [host, may be NULL] nP-q: the kept positions, in their new order.
+ *   sweeps [host, may be NULL]: downdating sweeps run.
+ * Returns LHDM_EINVAL on bad sizes, pointers or positions, LHDM_EUNSUPPORTED
+ * for nP > m or, with engine 1, m > 2048. */
+int lhdm_test_downdate(void* stream, int32_t engine, int32_t m, int32_t nP, const double* Q,
+                       const double* R, const double* bt, int32_t q, const int32_t* rm,
+                       double* Q_out, double* R_out, double* bt_out, int32_t* P_out,
+                       int32_t* sweeps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LHDM_TESTING_H */

@@ -22,6 +22,9 @@ from .nnls import (  # noqa: F401
     givens,
     oracle_lh,
     oracle_lhdm,
+    oracle_signed,
+    oracle_l1nnls,
+    l1nnls_matrix,
     dm_select_reference,
     downdate_rotations,
     kkt_report,

@@ -297,7 +297,12 @@ def _inner_step(st, x, y):
     P = np.array(st.P, dtype=np.int64)
     xP = x[P]
     neg = np.nonzero(y <= 0.0)[0]
-    ratios = xP[neg] / (xP[neg] - y[neg])
+    # an entry whose iterate is exactly 0 (only a new column of J, in the
+    # variant without the feasibility loop) limits the step to 0
+    xn = xP[neg]
+    ratios = np.zeros(len(neg))
+    nz = xn != 0.0
+    ratios[nz] = xn[nz] / (xn[nz] - y[neg][nz])
     alpha = float(ratios.min())
     xP = xP + alpha * (y - xP)
     xP[neg[ratios == alpha]] = 0.0
@@ -306,6 +311,45 @@ def _inner_step(st, x, y):
     x[P] = xP
     st.remove_positions(rm)
     return [int(P[i]) for i in rm], alpha
+
+
+def _sign_flip(st, x, y):
+    """The inner iteration of the positivity-trick case (Section 4.2) on the
+    matrix [B, -B]: every passive column with y_k < 0 is replaced, at the same
+    position, by its twin (the negated column), so that column of R changes
+    sign and y_k becomes -y_k > 0; the residual is unchanged.  Returns the
+    (old, new) index pairs."""
+    half = st.n // 2
+    out = []
+    for c in np.nonzero(y < 0.0)[0]:
+        j = st.P[c]
+        t = j + half if j < half else j - half
+        st.M[:, t] = -st.M[:, j]          # Q^T (-a_j): the R column at position c, negated
+        st.pos[j] = -1
+        st.pos[t] = c
+        st.P[c] = t
+        x[j] = 0.0
+        out.append((int(j), int(t)))
+    return out
+
+
+def _check_twins(A, sign_flip):
+    if not sign_flip:
+        return
+    n = A.shape[1]
+    if n % 2 or not np.array_equal(A[:, n // 2:], -A[:, :n // 2]):
+        raise ValueError("the sign flip needs the positivity-trick matrix [B, -B]")
+
+
+def _inner_iteration(st, x, y, sign_flip, step):
+    """One pass of the inner loop: the sign flip of Section 4.2 when it applies
+    (every nonpositive component strictly negative), else the step length and
+    removal of Algorithms 1 and 3."""
+    if sign_flip and not (y == 0.0).any():
+        step["flipped"].append(_sign_flip(st, x, y))
+    else:
+        rm, _ = _inner_step(st, x, y)
+        step["removed"].append(rm)
 
 
 def _finish(st, A, b, x, w, status, outer, inner, jdrops, trace, tol_w):
@@ -317,11 +361,28 @@ def _finish(st, A, b, x, w, status, outer, inner, jdrops, trace, tol_w):
 
 
 def oracle_lhdm(A, b, tau1=0.6, tau2=0.15, delta=0.9, kmax=32, kkt_tol=1e-9,
-                max_outer=None, max_inner=None, record=False):
+                max_outer=None, max_inner=None, record=False, jloop=True, sign_flip=False):
     """LHDM (Algorithm 3 with Deviation Maximization, Algorithm 2).
 
+    ``jloop=False``: the variant of Theorem 4 (tau1 = 1 and tau2 <= 1/2, with
+    the selection's delta <= tau2 / (kmax - 1) of Theorem 2 that makes the
+    block's Gram matrix diagonally dominant), in which the least-squares
+    components of every accepted block are positive and the feasibility loop
+    on J is not evaluated; a violation by rounding is left to the inner loop (a
+    zero iterate entry gives the step length 0).
+
+    ``sign_flip=True`` (A must be the positivity-trick matrix [B, -B]): the
+    inner loop of Section 4.2, which replaces each column with a negative
+    least-squares component by its twin instead of stepping and downdating;
+    an exactly zero component (the flip cannot make it positive) takes the
+    ordinary inner iteration.
+
     Returns ``(x, info)``; ``info['passive']`` is the ordered passive set."""
+    if not jloop and not (tau1 == 1.0 and tau2 <= 0.5 and (kmax <= 1 or delta <= tau2 / (kmax - 1))):
+        raise ValueError("the variant without the feasibility loop needs tau1 = 1, tau2 <= 1/2 and "
+                         "delta <= tau2 / (kmax - 1) (Theorems 2 and 4)")
     A, b = _prep(A, b)
+    _check_twins(A, sign_flip)
     m, n = A.shape
     max_outer = 3 * n if max_outer is None else max_outer
     max_inner = 3 * n if max_inner is None else max_inner
@@ -354,7 +415,7 @@ def oracle_lhdm(A, b, tau1=0.6, tau2=0.15, delta=0.9, kmax=32, kkt_tol=1e-9,
             st.append(j)
         y = st.solve()
         drops = 0
-        while len(J) > 0 and float(y[n0:].min()) <= 0.0:   # feasibility loop on J
+        while jloop and len(J) > 0 and float(y[n0:].min()) <= 0.0:   # feasibility loop on J
             st.drop_last()
             J.pop()
             drops += 1
@@ -366,14 +427,13 @@ def oracle_lhdm(A, b, tau1=0.6, tau2=0.15, delta=0.9, kmax=32, kkt_tol=1e-9,
             continue
         outer += 1
         excluded[:] = False
-        step = dict(J=list(J), drops=drops, removed=[])
+        step = dict(J=list(J), drops=drops, removed=[], flipped=[])
         while st.nP > 0 and float(y.min()) <= 0.0:          # inner loop
             if inner >= max_inner:
                 status = STATUS_MAXITER
                 break
             inner += 1
-            rm, _ = _inner_step(st, x, y)
-            step["removed"].append(rm)
+            _inner_iteration(st, x, y, sign_flip, step)
             y = st.solve()
         if status == STATUS_MAXITER:
             x[:] = np.maximum(x, 0.0)
@@ -389,10 +449,13 @@ def oracle_lhdm(A, b, tau1=0.6, tau2=0.15, delta=0.9, kmax=32, kkt_tol=1e-9,
     return _finish(st, A, b, x, w, status, outer, inner, jdrops, trace, tol_w)
 
 
-def oracle_lh(A, b, kkt_tol=1e-9, max_outer=None, max_inner=None, record=False):
+def oracle_lh(A, b, kkt_tol=1e-9, max_outer=None, max_inner=None, record=False, sign_flip=False):
     """Plain Lawson-Hanson (Algorithm 1): one column per outer step, rank-one
-    Householder append, inner loop with step length and Givens removal."""
+    Householder append, inner loop with step length and Givens removal (or,
+    with ``sign_flip`` on a positivity-trick matrix, the sign flip of Section
+    4.2, as in ``oracle_lhdm``)."""
     A, b = _prep(A, b)
+    _check_twins(A, sign_flip)
     m, n = A.shape
     max_outer = 3 * n if max_outer is None else max_outer
     max_inner = 3 * n if max_inner is None else max_inner
@@ -432,14 +495,13 @@ def oracle_lh(A, b, kkt_tol=1e-9, max_outer=None, max_inner=None, record=False):
             continue
         outer += 1
         excluded[:] = False
-        step = dict(J=[j], drops=0, removed=[])
+        step = dict(J=[j], drops=0, removed=[], flipped=[])
         while st.nP > 0 and float(y.min()) <= 0.0:           # inner loop
             if inner >= max_inner:
                 status = STATUS_MAXITER
                 break
             inner += 1
-            rm, _ = _inner_step(st, x, y)
-            step["removed"].append(rm)
+            _inner_iteration(st, x, y, sign_flip, step)
             y = st.solve()
         if status == STATUS_MAXITER:
             x[:] = np.maximum(x, 0.0)
@@ -453,6 +515,54 @@ def oracle_lh(A, b, kkt_tol=1e-9, max_outer=None, max_inner=None, record=False):
             step.update(nP=st.nP, obj=float(r @ r))
             trace.append(step)
     return _finish(st, A, b, x, w, status, outer, inner, jdrops, trace, tol_w)
+
+
+def oracle_signed(A, b, method="lhdm", sign_flip=True, **kw):
+    """Signed least squares by the positivity trick (Section 3.2): the NNLS
+    problem min ||[A, -A] z - b||, z >= 0, solved by LHDM or LH (``method``)
+    with the sign-flip inner loop of Section 4.2 (or the ordinary one);
+    returns ``(x, info)`` with x = z[:n] - z[n:], and z in ``info['z']``."""
+    A, b = _prep(A, b)
+    n = A.shape[1]
+    A2 = np.concatenate([A, -A], axis=1)
+    if method == "lhdm":
+        z, info = oracle_lhdm(A2, b, sign_flip=sign_flip, **kw)
+    elif method == "lh":
+        z, info = oracle_lh(A2, b, sign_flip=sign_flip, **kw)
+    else:
+        raise ValueError(method)
+    info["z"] = z
+    return z[:n] - z[n:], info
+
+
+def l1nnls_matrix(A, b, lam):
+    """The NNLS form of the squared-l1 regularised problem (Section 3.3): the
+    matrix [1^T, 1^T; lam A, -lam A] and right-hand side [0; lam b]."""
+    A, b = _prep(A, b)
+    m, n = A.shape
+    M = np.empty((m + 1, 2 * n))
+    M[0, :] = 1.0
+    M[1:, :n] = lam * A
+    M[1:, n:] = -lam * A
+    rhs = np.concatenate([[0.0], lam * b])
+    return M, rhs
+
+
+def oracle_l1nnls(A, b, lam, method="lhdm", **kw):
+    """l1-NNLS (Section 3.3): min ||x||_1^2 + lam^2 ||A x - b||^2 written as the
+    NNLS problem on [1^T, 1^T; lam A, -lam A], [0; lam b] with x = z+ - z-
+    (the weight of the residual term is lam^2, as that matrix form gives),
+    solved by LHDM or LH; returns ``(x, info)`` with z in ``info['z']``."""
+    M, rhs = l1nnls_matrix(A, b, lam)
+    n = M.shape[1] // 2
+    if method == "lhdm":
+        z, info = oracle_lhdm(M, rhs, **kw)
+    elif method == "lh":
+        z, info = oracle_lh(M, rhs, **kw)
+    else:
+        raise ValueError(method)
+    info["z"] = z
+    return z[:n] - z[n:], info
 
 
 # ---------------------------------------------------------------------------

@@ -20,7 +20,7 @@ from ._lib import (LhdmError, LhdmInfo, LhdmParams, STATUS_MAXITER, STATUS_NONFI
                    STATUS_RANK)
 
 __all__ = [
-    "solve", "lh_solve", "solve_batched", "solve_pooled", "backward_pooled", "LHDMFunction",
+    "solve", "lh_solve", "solve_signed", "solve_l1", "solve_batched", "solve_pooled", "backward_pooled", "LHDMFunction",
     "default_params", "Result", "pack", "LhdmError",
 ]
 
@@ -110,15 +110,85 @@ def _single(A, b, method: str, params: LhdmParams) -> Result:
 ENGINES = {"auto": 0, "workgroup": 1, "device": 2}
 
 
+FLAG_NO_JLOOP = 4
+
+
 def solve(A: torch.Tensor, b: torch.Tensor, *, tau1=0.6, tau2=0.15, delta=0.9, kmax=32, kkt_tol=1e-9,
-          max_outer=0, max_inner=0, engine="auto") -> Result:
+          max_outer=0, max_inner=0, engine="auto", no_jloop=False) -> Result:
     """LHDM solve of min ||A x - b|| s.t. x >= 0 (Algorithm 3 with Algorithm 2).
 
     ``engine``: "auto", "workgroup" (one workgroup per instance, m <= 2048) or
-    "device" (one instance over the whole GPU)."""
+    "device" (one instance over the whole GPU).  ``no_jloop``: the variant of
+    Theorem 4 without the feasibility loop on J (needs tau1 = 1, tau2 <= 1/2)."""
+    flags = ENGINES[engine] | (FLAG_NO_JLOOP if no_jloop else 0)
+    p = default_params(tau1=tau1, tau2=tau2, delta=delta, kmax=kmax, kkt_tol=kkt_tol, max_outer=max_outer,
+                       max_inner=max_inner, flags=flags)
+    return _single(A, b, "lhdm", p)
+
+
+@dataclass
+class SignedResult:
+    x: torch.Tensor            # (n,) float64, signed solution x+ - x-
+    z: torch.Tensor            # (2n,) float64, (x+, x-)
+    passive: torch.Tensor      # (2n,) int32, P over the columns of [A, -A], -1 padded
+    info: dict
+
+
+def solve_signed(A: torch.Tensor, b: torch.Tensor, *, sign_flip=True, tau1=0.6, tau2=0.15, delta=0.9, kmax=32,
+                 kkt_tol=1e-9, max_outer=0, max_inner=0, engine="auto") -> SignedResult:
+    """Signed least squares by the positivity trick (Section 3.2): NNLS on [A, -A]
+    (never formed) by LHDM, or LH with ``kmax=1``; ``sign_flip`` selects the
+    inner loop of Section 4.2."""
+    _check_dev_tensor(A, "A")
+    _check_dev_tensor(b, "b")
+    Acm, lda = _colmajor(A)
+    m, n = A.shape
+    b = b.reshape(-1).contiguous()
+    if b.numel() != m:
+        raise ValueError("b must have m entries")
+    dev = A.device
+    lib = _lib.load()
     p = default_params(tau1=tau1, tau2=tau2, delta=delta, kmax=kmax, kkt_tol=kkt_tol, max_outer=max_outer,
                        max_inner=max_inner, flags=ENGINES[engine])
-    return _single(A, b, "lhdm", p)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    z = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    passive = torch.empty(2 * n, dtype=torch.int32, device=dev)
+    info = torch.empty(_lib.INFO_BYTES, dtype=torch.uint8, device=dev)
+    ws = _Workspace(lib.lhdm_signed_workspace_bytes(m, n, ctypes.byref(p)), dev)
+    with torch.cuda.device(dev):
+        rc = lib.lhdm_solve_signed(_stream(dev), m, n, Acm.data_ptr(), lda, b.data_ptr(), ctypes.byref(p),
+                                   1 if sign_flip else 0, x.data_ptr(), z.data_ptr(), passive.data_ptr(),
+                                   info.data_ptr(), ws.ptr, ws.nbytes)
+    _lib.check(rc)
+    return SignedResult(x, z, passive, _info_dicts(info, 1)[0])
+
+
+def solve_l1(A: torch.Tensor, b: torch.Tensor, lam: float, *, tau1=0.6, tau2=0.15, delta=0.9, kmax=32,
+             kkt_tol=1e-9, max_outer=0, max_inner=0, engine="auto") -> SignedResult:
+    """l1-NNLS (Section 3.3): min ||x||_1^2 + lam^2 ||A x - b||^2 through the NNLS
+    problem on [1^T, 1^T; lam A, -lam A], [0; lam b], solved by LHDM (LH with
+    ``kmax=1``)."""
+    _check_dev_tensor(A, "A")
+    _check_dev_tensor(b, "b")
+    Acm, lda = _colmajor(A)
+    m, n = A.shape
+    b = b.reshape(-1).contiguous()
+    if b.numel() != m:
+        raise ValueError("b must have m entries")
+    dev = A.device
+    lib = _lib.load()
+    p = default_params(tau1=tau1, tau2=tau2, delta=delta, kmax=kmax, kkt_tol=kkt_tol, max_outer=max_outer,
+                       max_inner=max_inner, flags=ENGINES[engine])
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    z = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    passive = torch.empty(2 * n, dtype=torch.int32, device=dev)
+    info = torch.empty(_lib.INFO_BYTES, dtype=torch.uint8, device=dev)
+    ws = _Workspace(lib.lhdm_l1_workspace_bytes(m, n, ctypes.byref(p)), dev)
+    with torch.cuda.device(dev):
+        rc = lib.lhdm_solve_l1(_stream(dev), m, n, Acm.data_ptr(), lda, b.data_ptr(), float(lam), ctypes.byref(p),
+                               x.data_ptr(), z.data_ptr(), passive.data_ptr(), info.data_ptr(), ws.ptr, ws.nbytes)
+    _lib.check(rc)
+    return SignedResult(x, z, passive, _info_dicts(info, 1)[0])
 
 
 def lh_solve(A: torch.Tensor, b: torch.Tensor, *, kkt_tol=1e-9, max_outer=0) -> Result:

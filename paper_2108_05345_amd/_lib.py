@@ -64,6 +64,12 @@ SIGNATURES = {
     "lhdm_solve": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _vp, ctypes.POINTER(LhdmParams),
                                   _vp, _vp, _vp, _vp, _vp, _sz]),
     "lh_solve": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _vp, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _sz]),
+    "lhdm_signed_workspace_bytes": (_sz, [_i32, _i32, ctypes.POINTER(LhdmParams)]),
+    "lhdm_l1_workspace_bytes": (_sz, [_i32, _i32, ctypes.POINTER(LhdmParams)]),
+    "lhdm_solve_l1": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _vp, _dbl, ctypes.POINTER(LhdmParams), _vp, _vp,
+                                     _vp, _vp, _vp, _sz]),
+    "lhdm_solve_signed": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _vp, ctypes.POINTER(LhdmParams), _i32, _vp, _vp,
+                                         _vp, _vp, _vp, _sz]),
     "lhdm_batched_workspace_bytes": (_sz, [_i32, _pi32, _pi32, ctypes.POINTER(LhdmParams)]),
     "lhdm_solve_batched": (ctypes.c_int, [_vp, _i32, _pi32, _pi32, _pi64, _vp, _pi64, _vp, _pi64, _vp, _vp,
                                           ctypes.POINTER(LhdmParams), _i32, _vp, _vp, _sz]),
@@ -76,6 +82,9 @@ SIGNATURES = {
     "lhdm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lhdm_last_hip_error": (ctypes.c_int, []),
     "lhdm_release": (None, []),
+    # test-only entry points (include/lhdm_testing.h)
+    "lhdm_test_downdate": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _pi32, _vp, _vp, _vp, _pi32,
+                                          _pi32]),
 }
 
 _LIB = None

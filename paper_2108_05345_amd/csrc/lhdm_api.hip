@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -13,6 +14,7 @@
 #include "lhdm_wg.hpp"
 #include "lhdm_large.hpp"
 #include "lhdm_backward.hpp"
+#include "lhdm_testing.hpp"
 
 namespace lhdm {
 
@@ -31,10 +33,13 @@ struct ProbIn {
 };
 
 // Persistent batched solve: each workgroup owns one workspace slot and takes
-// instances from the queue `order` (largest first) until it is exhausted.
+// instances from the queue `order` (largest first; NULL: the given order) until
+// it is exhausted.  An instance without a w buffer (in.w == NULL) keeps its
+// dual in its slot at byte offset w_off.
 __global__ __launch_bounds__(WG) void wg_solve_kernel(const ProbIn* __restrict__ ins, int nprob,
                                                       const int* __restrict__ order, int* counter,
-                                                      char* slots, size_t slot_stride, DevParams prm) {
+                                                      char* slots, size_t slot_stride, DevParams prm,
+                                                      size_t w_off) {
     __shared__ WgShared sh;
     __shared__ int sidx;
     char* base = slots + (size_t)blockIdx.x * slot_stride;
@@ -44,16 +49,17 @@ __global__ __launch_bounds__(WG) void wg_solve_kernel(const ProbIn* __restrict__
         const int idx = sidx;
         __syncthreads();
         if (idx >= nprob) break;
-        const ProbIn in = ins[order[idx]];
+        const ProbIn in = ins[order ? order[idx] : idx];
         Prob p;
         p.A = in.A;
         p.lda = in.lda;
         p.b = in.b;
         p.x = in.x;
-        p.w = in.w;
+        p.w = in.w ? in.w : (double*)(base + w_off);
         p.passive = in.passive;
         p.info = in.info;
         carve_slot(p, base, in.m, in.n, prm.kmax);
+        if (prm.twin) p.nph = in.n / 2;   // in.n counts the columns of [A, -A]
         // iteration limits <= 0 select 3 n of this instance
         DevParams q = prm;
         if (q.max_outer <= 0) q.max_outer = 3 * in.n;
@@ -74,11 +80,14 @@ static bool params_ok(const lhdm_params* p) {
     if (!(p->delta > 0.0 && p->delta <= 1.0)) return false;
     if (!(p->kkt_tol >= 0.0)) return false;
     if (p->kmax < 1 || p->kmax > KM) return false;
+    if ((p->flags & LHDM_FLAG_NO_JLOOP) &&
+        !(p->tau1 == 1.0 && p->tau2 <= 0.5 && (p->kmax <= 1 || p->delta <= p->tau2 / (p->kmax - 1))))
+        return false;
     return true;
 }
 
 static DevParams dev_params(const lhdm_params* p, int n, int lh) {
-    DevParams d;
+    DevParams d{};
     d.tau1 = p->tau1;
     d.tau2 = p->tau2;
     d.delta = p->delta;
@@ -87,6 +96,7 @@ static DevParams dev_params(const lhdm_params* p, int n, int lh) {
     d.max_outer = p->max_outer > 0 ? p->max_outer : 3 * n;
     d.max_inner = p->max_inner > 0 ? p->max_inner : 3 * n;
     d.lh = lh;
+    d.nojloop = (p->flags & LHDM_FLAG_NO_JLOOP) ? 1 : 0;
     return d;
 }
 
@@ -150,7 +160,7 @@ static int run_wg_engine(hipStream_t st, const std::vector<ProbIn>& ins, const s
     HIPCHK(hipMemsetAsync(base + L.off_counter, 0, sizeof(int), st));
     hipLaunchKernelGGL(wg_solve_kernel, dim3(L.nslot), dim3(WG), 0, st, (const ProbIn*)(base + L.off_in), batch,
                        (const int*)(base + L.off_order), (int*)(base + L.off_counter), base + L.off_slots,
-                       L.slot_stride, prm);
+                       L.slot_stride, prm, (size_t)0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return 0;
@@ -201,6 +211,61 @@ static int solve_one(void* stream, int32_t m, int32_t n, const double* A, int64_
     return run_wg_engine(st, ins, mm, nn, prm, ws, L.total);
 }
 
+// x = z[:n] - z[n:] (the signed solution of the positivity trick).
+__global__ __launch_bounds__(WG) void signed_combine(const double* __restrict__ z, double* __restrict__ x, int n) {
+    const int j = blockIdx.x * WG + threadIdx.x;
+    if (j < n) x[j] = z[j] - z[j + n];
+}
+
+// The NNLS form of the squared-l1 regularised problem (Section 3.3): M =
+// [1^T, 1^T; lam A, -lam A] ((m + 1) x 2n, column-major, ld m + 1) and
+// rhs = [0; lam b].
+__global__ __launch_bounds__(WG) void l1_assemble(const double* __restrict__ A, long long lda,
+                                                   const double* __restrict__ b, double lam, int m, int n,
+                                                   double* __restrict__ M, double* __restrict__ rhs) {
+    const long long ld = m + 1, tot = ld * 2 * (long long)n;
+    for (long long e = (long long)blockIdx.x * WG + threadIdx.x; e < tot; e += (long long)gridDim.x * WG) {
+        const int j = (int)(e / ld), i = (int)(e % ld);
+        double v = 1.0;
+        if (i > 0) {
+            const double a = A[(size_t)(j < n ? j : j - n) * lda + (i - 1)];
+            v = (j < n) ? lam * a : -(lam * a);
+        }
+        M[e] = v;
+    }
+    for (int i = blockIdx.x * WG + threadIdx.x; i <= m; i += gridDim.x * WG) rhs[i] = (i == 0) ? 0.0 : lam * b[i - 1];
+}
+
+struct L1Layout {
+    size_t M, rhs, z, solver, total;
+};
+
+static L1Layout l1_layout(int m, int n, const lhdm_params* p) {
+    L1Layout L;
+    lhdm_params q = *p;
+    if (q.kmax < 1) q.kmax = 1;
+    size_t o = 0;
+    L.M = o;
+    o += pad256(sizeof(double) * (size_t)(m + 1) * 2 * n);
+    L.rhs = o;
+    o += pad256(sizeof(double) * (size_t)(m + 1));
+    L.z = o;
+    o += pad256(sizeof(double) * 2 * (size_t)n);
+    L.solver = o;
+    o += lhdm_workspace_bytes(m + 1, 2 * n, &q);
+    L.total = o;
+    return L;
+}
+
+static size_t signed_workspace(int m, int n, const lhdm_params* p, size_t* solver_bytes) {
+    const size_t zb = pad256(sizeof(double) * 2 * (size_t)n);
+    lhdm_params q = *p;
+    if (q.kmax < 1) q.kmax = 1;
+    const size_t sb = lhdm_workspace_bytes(m, 2 * n, &q);
+    if (solver_bytes) *solver_bytes = sb;
+    return sb + zb;
+}
+
 }  // namespace lhdm
 
 using namespace lhdm;
@@ -239,6 +304,92 @@ int lhdm_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda,
     }
     if (!params_ok(p)) return LHDM_EINVAL;
     return solve_one(stream, m, n, A, lda, b, dev_params(p, n, 0), p->flags, x, w, passive, info, ws, ws_bytes);
+}
+
+size_t lhdm_signed_workspace_bytes(int32_t m, int32_t n, const lhdm_params* p) {
+    lhdm_params def;
+    if (!p) {
+        lhdm_default_params(&def);
+        p = &def;
+    }
+    if (m < 1 || n < 1 || n > INT_MAX / 2) return 0;
+    return signed_workspace(m, n, p, nullptr);
+}
+
+int lhdm_solve_signed(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                      const lhdm_params* p, int32_t sign_flip, double* x, double* z, int32_t* passive,
+                      lhdm_info* info, void* ws, size_t ws_bytes) {
+    lhdm_params def;
+    if (!p) {
+        lhdm_default_params(&def);
+        p = &def;
+    }
+    if (!params_ok(p)) return LHDM_EINVAL;
+    if (m < 1 || n < 1 || n > INT_MAX / 2 || lda < m || !A || !b || !x) return LHDM_EINVAL;
+    size_t solver_bytes = 0;
+    const size_t need = signed_workspace(m, n, p, &solver_bytes);
+    if (ws == nullptr) {
+        int rc = cached_workspace(need, &ws);
+        if (rc) return rc;
+        ws_bytes = need;
+    }
+    if (ws_bytes < need || ((uintptr_t)ws & 255)) return LHDM_EWORKSPACE;
+    double* zb = z ? z : (double*)((char*)ws + solver_bytes);
+    DevParams prm = dev_params(p, 2 * n, 0);
+    prm.twin = 1;
+    prm.signflip = sign_flip ? 1 : 0;
+    int rc = solve_one(stream, m, 2 * n, A, lda, b, prm, p->flags, zb, nullptr, passive, info, ws, solver_bytes);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(signed_combine, dim3((n + WG - 1) / WG), dim3(WG), 0, st, (const double*)zb, x, n);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+size_t lhdm_l1_workspace_bytes(int32_t m, int32_t n, const lhdm_params* p) {
+    lhdm_params def;
+    if (!p) {
+        lhdm_default_params(&def);
+        p = &def;
+    }
+    if (m < 1 || n < 1 || n > INT_MAX / 2 || m == INT_MAX) return 0;
+    return l1_layout(m, n, p).total;
+}
+
+int lhdm_solve_l1(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, const double* b, double lambda,
+                  const lhdm_params* p, double* x, double* z, int32_t* passive, lhdm_info* info, void* ws,
+                  size_t ws_bytes) {
+    lhdm_params def;
+    if (!p) {
+        lhdm_default_params(&def);
+        p = &def;
+    }
+    if (!params_ok(p)) return LHDM_EINVAL;
+    if (m < 1 || n < 1 || n > INT_MAX / 2 || m == INT_MAX || lda < m || !A || !b || !x) return LHDM_EINVAL;
+    if (!(lambda > 0.0) || !(lambda < INFINITY)) return LHDM_EINVAL;
+    const L1Layout L = l1_layout(m, n, p);
+    if (ws == nullptr) {
+        int rc = cached_workspace(L.total, &ws);
+        if (rc) return rc;
+        ws_bytes = L.total;
+    }
+    if (ws_bytes < L.total || ((uintptr_t)ws & 255)) return LHDM_EWORKSPACE;
+    char* base = (char*)ws;
+    double* M = (double*)(base + L.M);
+    double* rhs = (double*)(base + L.rhs);
+    double* zb = z ? z : (double*)(base + L.z);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(l1_assemble, dim3(1024), dim3(WG), 0, st, A, (long long)lda, b, lambda, m, n, M, rhs);
+    HIPCHK(hipGetLastError());
+    const int lh = p->kmax == 1;
+    int rc = solve_one(stream, m + 1, 2 * n, M, m + 1, rhs, dev_params(p, 2 * n, lh), p->flags, zb, nullptr,
+                       passive, info, base + L.solver, L.total - L.solver);
+    if (rc) return rc;
+    hipLaunchKernelGGL(signed_combine, dim3((n + WG - 1) / WG), dim3(WG), 0, st, (const double*)zb, x, n);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
 }
 
 int lh_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, const double* b, double kkt_tol,

@@ -32,6 +32,9 @@ constexpr int MMAX_WG = 2048;        // largest m of the workgroup engine
 struct DevParams {
     double tau1, tau2, delta, kkt_tol;
     int kmax, max_outer, max_inner, lh;
+    int nojloop;   // feasibility loop on J not evaluated (Theorem 4 regime)
+    int twin;      // positivity trick: the matrix is [A, -A], -A never formed
+    int signflip;  // inner loop by the sign flip of the positivity-trick case
 };
 
 // One instance: caller buffers plus its workspace slice.
@@ -44,6 +47,8 @@ struct Prob {
     int* passive;      // may be null
     lhdm_info* info;   // may be null
     int m, n, kc, kq;  // kc = min(m, n); kq = columns of the panel buffers (>= 2)
+    int nph;           // columns of the caller's A: n, or n / 2 for the positivity trick
+                       // (column j >= nph is the negated caller column j - nph)
     double* Q;         // m * m
     double* R;         // kc * kc
     double* bt;        // m
@@ -118,6 +123,28 @@ __host__ __device__ inline void carve_slot(Prob& p, char* base, int m, int n, in
     p.excl = (int*)take(sizeof(int) * n);
     p.ybuf = nullptr;
     p.Vt = nullptr;
+    p.nph = n;
+}
+
+// Column j of the instance's matrix: the caller's column j or, in the
+// positivity-trick mode (n = 2 nph, Section 3.2), the caller's column j - nph
+// negated (sign -1) for j >= nph.
+__host__ __device__ inline const double* col_ptr(const Prob& p, int j, double& sign) {
+    if (j >= p.nph) {
+        sign = -1.0;
+        return p.A + (size_t)(j - p.nph) * p.lda;
+    }
+    sign = 1.0;
+    return p.A + (size_t)j * p.lda;
+}
+
+// The twin of column j in the positivity-trick mode (its negation).
+__host__ __device__ inline int twin_of(const Prob& p, int j) { return j >= p.nph ? j - p.nph : j + p.nph; }
+
+// A column whose twin is passive lies in range(A_P): its projected norm is 0
+// in exact arithmetic, so it is not eligible (positivity-trick mode only).
+__device__ __forceinline__ bool twin_passive(const Prob& p, int j) {
+    return p.n != p.nph && p.pos[twin_of(p, j)] >= 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -187,6 +214,13 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     const int lo = __builtin_amdgcn_readlane((int)bits, l);
     const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Step-length ratio x_i / (x_i - y_i) of an inner iteration for a passive
+// entry with y_i <= 0; an entry whose iterate is exactly 0 gives 0 (it can only
+// arise in the variant without the feasibility loop on J).
+__device__ __forceinline__ double step_ratio(double xc, double yc) {
+    return (xc == 0.0) ? 0.0 : xc / (xc - yc);
 }
 
 // Rotation G = [[c, s], [-s, c]] with G [a, b]^T = [r, 0]^T (Algorithm 5's givens).

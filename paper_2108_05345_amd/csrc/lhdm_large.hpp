@@ -213,12 +213,13 @@ __device__ inline void ll_wait_word(const u64* word, int epoch, int* err) {
 // --------------------------------------------------------------------------
 // initialisation
 // --------------------------------------------------------------------------
-// w = A^T b, ||a_j||^2, and the per-column state; one wave per column.
+// w = A^T b, ||a_j||^2, and the per-column state; one wave per column of the
+// caller's A (with its twin -a_j in the positivity-trick mode).
 __global__ __launch_bounds__(WG) void lg_init_cols(LgArgs a, unsigned long long* anmax_bits, int* bad) {
     const Prob& p = a.p;
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * NW + wave_index();
-    if (j >= p.n) return;
+    if (j >= p.nph) return;
     const double* col = p.A + (size_t)j * p.lda;
     double ab = 0.0, aa = 0.0;
     for (int i = lane; i < p.m; i += 64) {
@@ -235,6 +236,15 @@ __global__ __launch_bounds__(WG) void lg_init_cols(LgArgs a, unsigned long long*
         p.pos[j] = -1;
         p.excl[j] = 0;
         p.x[j] = 0.0;
+        if (p.nph != p.n) {
+            const int t = j + p.nph;
+            p.w[t] = -ab;
+            p.an2[t] = aa;
+            p.u2[t] = aa;
+            p.pos[t] = -1;
+            p.excl[t] = 0;
+            p.x[t] = 0.0;
+        }
         if (!isfinite(ab) || !isfinite(aa)) atomicOr(bad, 1);
         else atomicMax(anmax_bits, (unsigned long long)__double_as_longlong(aa));
     }
@@ -300,7 +310,7 @@ __global__ __launch_bounds__(WG) void lg_sel_part(LgArgs a, double* pv, int* pi)
         const double u = sqrt(fmax(p.u2[j], 0.0));
         mwz = fmax(mwz, wj);
         mu = fmax(mu, u);
-        if (!p.excl[j] && u > DEP_TOL * sqrt(p.an2[j]) && better(wj, j, bv, bi)) {
+        if (!p.excl[j] && u > DEP_TOL * sqrt(p.an2[j]) && !twin_passive(p, j) && better(wj, j, bv, bi)) {
             bv = wj;
             bi = j;
         }
@@ -380,7 +390,7 @@ __global__ __launch_bounds__(WG) void lg_sel_cand(LgArgs a, const double* pv, co
         const double wj = p.w[j], u2 = p.u2[j], an2 = p.an2[j];
         if (ps >= 0 || ex || j == bi || !(wj >= tw)) continue;
         const double u = sqrt(fmax(u2, 0.0));
-        if (!(u >= tu) || !(u > DEP_TOL * sqrt(an2))) continue;
+        if (!(u >= tu) || !(u > DEP_TOL * sqrt(an2)) || twin_passive(p, j)) continue;
         const int slot = atomicAdd(&a.ex->ccount, 1);
         if (slot < CAND_CAP) {
             a.candw[slot] = wj;
@@ -591,7 +601,13 @@ __global__ __launch_bounds__(WG) void lg_gather_cand(LgArgs a, int pair) {
     for (size_t e = (size_t)blockIdx.x * WG + threadIdx.x; e < tot; e += (size_t)gridDim.x * WG) {
         int row, t;
         dt_coords(e, pair, row, t);
-        a.Dt[e] = (t < nc && row < m) ? p.A[(size_t)a.ctl->J[t] * p.lda + row] : 0.0;
+        double v = 0.0;
+        if (t < nc && row < m) {
+            double sg;
+            const double* col = col_ptr(p, a.ctl->J[t], sg);
+            v = sg * col[row];
+        }
+        a.Dt[e] = v;
     }
 }
 
@@ -1125,7 +1141,7 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, i
         for (int j = 0; j < KM; ++j) rrow[j] = (lk && j > lane && j < kr) ? Wl[lane][j] * rinv : 0.0;
         const double bl = lk ? p.bt[r0 + lane] * rinv : 0.0;
         int k = kr;
-        while (k > 0) {
+        while (k > 0 && !a.prm.nojloop) {   // not evaluated in the Theorem 4 regime
             double v = (lane < k) ? bl : 0.0;
             double mn = INFINITY;
 #pragma unroll
@@ -1228,6 +1244,12 @@ __device__ void inner_body(LgArgs& a, WgShared& s) {
         }
         __syncthreads();
         if (threadIdx.x == 0) s.inner += 1;
+        if (a.prm.signflip && wg.sign_flip()) {
+            // y > 0 after the flip (Section 4.2): the inner loop ends, with no downdate
+            if (threadIdx.x == 0) ex->inner_done = 1;
+            ctl_store(s, a.ctl);
+            return;
+        }
         wg.inner_step();
     }
     if (threadIdx.x == 0) {
@@ -1431,6 +1453,13 @@ __global__ __launch_bounds__(WG) void lg_compact(LgArgs a, int rotbt) {
     if (rotbt) rotate_bt_unit(a);
 }
 
+// w of the twins -a_j from w of the caller's columns (positivity-trick mode).
+__global__ __launch_bounds__(WG) void lg_twin_w(LgArgs a) {
+    const Prob& p = a.p;
+    const int j = blockIdx.x * WG + threadIdx.x;
+    if (j < p.nph) p.w[j + p.nph] = -p.w[j];
+}
+
 __global__ __launch_bounds__(WG) void lg_finalize(LgArgs a) {
     __shared__ WgShared s;
     ctl_load(s, a.ctl);
@@ -1569,10 +1598,12 @@ __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
     }
     // MODE_DUAL: w_j and the projected-norm update
     const Prob& p = a.p;
+    const bool tw = p.nph != p.n;
     int t0 = 0;
     double u2;
     if (a.v0 == 0) {
         p.w[j] = c[0];
+        if (tw) p.w[j + p.nph] = -c[0];
         t0 = 1;
         u2 = a.exact ? 0.0 : p.u2[j];
     } else {
@@ -1586,12 +1617,13 @@ __global__ __launch_bounds__(WG) void lg_colmat_dot(ColmatArgs a) {
     }
     if (a.v0 + a.nvec >= a.vtot) {
         u2 = fmax(u2, 0.0);
-        if (!a.exact && p.pos[j] < 0 && u2 < RECOMP_FRAC * p.an2[j]) {
+        if (!a.exact && p.pos[j] < 0 && !twin_passive(p, j) && u2 < RECOMP_FRAC * p.an2[j]) {
             const int slotn = atomicAdd(a.nrecomp, 1);
             a.recomp[slotn] = j;
         }
     }
     p.u2[j] = u2;
+    if (tw) p.u2[j + p.nph] = u2;
 }
 
 // Column block times vector block on FP64 MFMA 16x16x4, X column-major.
@@ -1776,6 +1808,7 @@ __global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
     const double rsum = ((Rs[0][c][jc] + Rs[1][c][jc]) + Rs[2][c][jc]) + Rs[3][c][jc];
     const Prob& p = a.p;
     p.w[j] = rsum;
+    if (p.nph != p.n) p.w[j + p.nph] = -rsum;
     double u2 = a.exact ? 0.0 : p.u2[j];
     for (int q = 0; q + 1 < a.nvec; ++q) {
         // vector 1 + q: tile q / 16, lane (jc % 4) * 16 + q % 16, register v
@@ -1785,11 +1818,12 @@ __global__ __launch_bounds__(WG) void lg_colmat2(ColmatArgs a) {
         else u2 += d * d;
     }
     u2 = fmax(u2, 0.0);
-    if (!a.exact && p.pos[j] < 0 && u2 < RECOMP_FRAC * p.an2[j]) {
+    if (!a.exact && p.pos[j] < 0 && !twin_passive(p, j) && u2 < RECOMP_FRAC * p.an2[j]) {
         const int slotn = atomicAdd(a.nrecomp, 1);
         a.recomp[slotn] = j;
     }
     p.u2[j] = u2;
+    if (p.nph != p.n) p.u2[j + p.nph] = u2;
 }
 
 // Dual pass with producer and consumer waves, for up to 32 MFMA vectors.
@@ -1958,6 +1992,7 @@ __global__ __launch_bounds__(DW_WG) void lg_dual_ws(ColmatArgs a) {
     const double rsum = ((rpart(0) + rpart(1)) + rpart(2)) + rpart(3);
     const Prob& p = a.p;
     p.w[j] = rsum;
+    if (p.nph != p.n) p.w[j + p.nph] = -rsum;
     double u2 = a.exact ? 0.0 : p.u2[j];
     for (int qv = 0; qv + 1 < a.nvec; ++qv) {
         // vector 1 + qv: tile qv / 16, lane (jc % 4) * 16 + qv % 16, register v
@@ -1967,11 +2002,12 @@ __global__ __launch_bounds__(DW_WG) void lg_dual_ws(ColmatArgs a) {
         else u2 += d * d;
     }
     u2 = fmax(u2, 0.0);
-    if (!a.exact && p.pos[j] < 0 && u2 < RECOMP_FRAC * p.an2[j]) {
+    if (!a.exact && p.pos[j] < 0 && !twin_passive(p, j) && u2 < RECOMP_FRAC * p.an2[j]) {
         const int slotn = atomicAdd(a.nrecomp, 1);
         a.recomp[slotn] = j;
     }
     p.u2[j] = u2;
+    if (p.nph != p.n) p.u2[j + p.nph] = u2;
 }
 
 __global__ __launch_bounds__(WG) void lg_gather_dual(LgArgs a, int v0, int pair) {
@@ -2064,7 +2100,10 @@ __global__ __launch_bounds__(WG) void lg_recompute(LgArgs a) {
             d = wave_sum(d);
             u2 += d * d;
         }
-        if (lane == 0) p.u2[j] = u2;
+        if (lane == 0) {
+            p.u2[j] = u2;
+            if (p.nph != p.n) p.u2[j + p.nph] = u2;
+        }
     }
 }
 
@@ -2097,7 +2136,9 @@ __global__ __launch_bounds__(WG) void lg_residual_part(LgArgs a) {
         double av[RB], xv[RB];
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
-            av[u] = p.A[(size_t)j[u] * p.lda + row];
+            double sg;
+            const double* col = col_ptr(p, j[u], sg);
+            av[u] = sg * col[row];
             xv[u] = accept ? p.ybuf[min(cb + u, c1 - 1)] : p.x[j[u]];
         }
 #pragma unroll
@@ -2992,38 +3033,16 @@ static void colmat2_launch(hipStream_t st, ColmatArgs ca, hipEvent_t ev0 = nullp
     else hipLaunchKernelGGL((lg_colmat2<3, 1, 2, false>), g, dim3(WG), 0, st, ca);
 }
 
-// Host copy of the control words read at each decision point.
-// Host copy of the control block and the leading int fields of LgExtra, laid
-// out as in the workspace (LgExtra starts at the next 256-byte boundary after
-// Ctl) so that one transfer brings both.
-
-static int large_solve(hipStream_t st, int m, int n, const double* A, long long lda, const double* b,
-                       const DevParams& prm, double* x, double* w, int* passive, lhdm_info* info, void* ws,
-                       size_t ws_bytes) {
-    const LargeLayout L = large_layout(m, n, prm.kmax);
-    if (ws == nullptr) {
-        int rc = cached_workspace(L.total, &ws);
-        if (rc) return rc;
-        ws_bytes = L.total;
-    }
-    if (ws_bytes < L.total || ((uintptr_t)ws & 255)) return LHDM_EWORKSPACE;
-    char* base = (char*)ws;
-    LgArgs a;
+// The instance's state and the engine's buffers carved from a workspace laid
+// out by large_layout (the caller's A, b and outputs are set by the caller).
+static void large_bind(LgArgs& a, const LargeLayout& L, char* base, int m, int n, const DevParams& prm) {
     Prob& p = a.p;
-    p.A = A;
-    p.lda = lda;
-    p.b = b;
-    p.x = x;
-    p.w = w ? w : (double*)(base + L.wfall);
-    p.passive = passive;
-    p.info = info;
     carve_slot(p, base + L.slot, m, n, prm.kmax);
     p.ybuf = (double*)(base + L.ybuf);
     p.Vt = (double*)(base + L.Vt);
     a.prm = prm;
     a.ctl = (Ctl*)(base + L.ctl);
     a.ex = (LgExtra*)(base + L.ex);
-    if (L.ex - L.ctl != CTL_SPAN) return LHDM_EINVAL;   // Mirror assumes this spacing
     a.Dt = (double*)(base + L.Dt);
     a.rotbuf = (double*)(base + L.rot);
     a.ocol = (int*)(base + L.ocol);
@@ -3040,6 +3059,32 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
     a.candw = (double*)(base + L.candw);
     a.candi = (int*)(base + L.candi);
     a.pll = (u64*)(base + L.ppart);
+    a.hmir = nullptr;
+}
+
+static int large_solve(hipStream_t st, int m, int n, const double* A, long long lda, const double* b,
+                       const DevParams& prm, double* x, double* w, int* passive, lhdm_info* info, void* ws,
+                       size_t ws_bytes) {
+    const LargeLayout L = large_layout(m, n, prm.kmax);
+    if (ws == nullptr) {
+        int rc = cached_workspace(L.total, &ws);
+        if (rc) return rc;
+        ws_bytes = L.total;
+    }
+    if (ws_bytes < L.total || ((uintptr_t)ws & 255)) return LHDM_EWORKSPACE;
+    if (L.ex - L.ctl != CTL_SPAN) return LHDM_EINVAL;   // Mirror assumes this spacing
+    char* base = (char*)ws;
+    LgArgs a;
+    Prob& p = a.p;
+    large_bind(a, L, base, m, n, prm);
+    if (prm.twin) p.nph = n / 2;   // n counts the columns of [A, -A]
+    p.A = A;
+    p.lda = lda;
+    p.b = b;
+    p.x = x;
+    p.w = w ? w : (double*)(base + L.wfall);
+    p.passive = passive;
+    p.info = info;
     unsigned long long* anmax_bits = (unsigned long long*)(base + L.misc);
     int* bad = (int*)(base + L.misc + 8);
 
@@ -3098,7 +3143,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
 
     HIPCHK(hipMemsetAsync(base + L.misc, 0, 256, st));
     HIPCHK(hipMemsetAsync(a.ex, 0, sizeof(LgExtra), st));
-    hipLaunchKernelGGL(lg_init_cols, dim3((n + NW - 1) / NW), dim3(WG), 0, st, a, anmax_bits, bad);
+    hipLaunchKernelGGL(lg_init_cols, dim3((p.nph + NW - 1) / NW), dim3(WG), 0, st, a, anmax_bits, bad);
     hipLaunchKernelGGL(lg_fill_identity, dim3(1024), dim3(WG), 0, st, p.Q, m);
     hipLaunchKernelGGL(lg_init_ctl, dim3(1), dim3(WG), 0, st, a, (const unsigned long long*)anmax_bits,
                        (const int*)bad);
@@ -3299,7 +3344,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             ca.X = A;
             ca.ldx = lda;
             ca.m = m;
-            ca.ncols = n;
+            ca.ncols = p.nph;   // the caller's columns (their twins are written beside them)
             ca.Dt = a.Dt;
             ca.ldd = 64;
             ca.mode = MODE_DUAL;
@@ -3312,7 +3357,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             ca.recomp = a.recomp;
             ca.nrecomp = &a.ex->nrecomp;
             // algorithmic bytes: A once, the vector block, w written, u2 read and written
-            const double bytes = 8.0 * ((double)m * n + (double)m * 64 + 3.0 * n);
+            const double bytes = 8.0 * ((double)m * p.nph + (double)m * 64 + 3.0 * n);
             const bool pair = colmat2_fits(ca);
             // the first block also forms r and the sizes of the update
             if (v0 == 0) hipLaunchKernelGGL(lg_dual_prep, dim3(ggrid), dim3(WG), 0, cs, a, (int)pair);
@@ -3340,7 +3385,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         ca.X = A;
         ca.ldx = lda;
         ca.m = m;
-        ca.ncols = n;
+        ca.ncols = p.nph;
         ca.Dt = a.Dt;
         ca.ldd = 64;
         ca.mode = MODE_PROJ;
@@ -3349,6 +3394,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         ca.nvec = 1;
         ca.p = p;
         if ((rc = colmat_launch(cs, ca))) return rc;
+        if (p.nph != n) hipLaunchKernelGGL(lg_twin_w, dim3((p.nph + WG - 1) / WG), dim3(WG), 0, cs, a);
     }
     hipLaunchKernelGGL(lg_finalize, dim3(1), dim3(WG), 0, cs, a);
     if (cs != st) {

@@ -1,0 +1,167 @@
+// Test-only entry points (declared in lhdm_testing.h): single solver steps on
+// caller-given state.  They run the solvers' own device code; only the set-up
+// and the read-back here are specific to the tests.
+#pragma once
+
+#include <vector>
+
+#include "lhdm_testing.h"
+#include "lhdm_large.hpp"
+
+namespace lhdm {
+
+// One-workgroup engine: the removal set is read from x (x <= 0 marks a
+// removed position) and deleted in one sweep, compaction included.
+__global__ __launch_bounds__(WG) void wg_test_downdate_kernel(Prob p, DevParams prm, int nP) {
+    __shared__ WgShared s;
+    Wg wg(p, prm, s);
+    if (threadIdx.x == 0) {
+        s.nP = nP;
+        s.q = 0;
+    }
+    __syncthreads();
+    wg.collect_removals();
+    wg.downdate();
+}
+
+struct DeviceBuffer {
+    void* ptr = nullptr;
+    ~DeviceBuffer() {
+        if (ptr) (void)hipFree(ptr);
+    }
+};
+
+static int test_downdate(hipStream_t st, int engine, int m, int nP, const double* Q, const double* R,
+                         const double* bt, int q, const int* rm, double* Qo, double* Ro, double* bto, int* Po,
+                         int* sweeps) {
+    if (m < 1 || nP < 1 || q < 1 || q > nP || !Q || !R || !bt || !rm || !Qo || !Ro || !bto) return LHDM_EINVAL;
+    if (engine != 1 && engine != 2) return LHDM_EINVAL;
+    for (int t = 0; t < q; ++t)
+        if (rm[t] < 0 || rm[t] >= nP || (t > 0 && rm[t] <= rm[t - 1])) return LHDM_EINVAL;
+    if (nP > m || (engine == 1 && m > MMAX_WG)) return LHDM_EUNSUPPORTED;
+    DevParams prm{};
+    prm.tau1 = 0.6;
+    prm.tau2 = 0.15;
+    prm.delta = 0.9;
+    prm.kkt_tol = 1e-9;
+    prm.kmax = 2;
+    prm.max_outer = 1 << 30;
+    prm.max_inner = 1 << 30;
+    prm.lh = 0;
+    const int n = nP;   // position c holds column c
+    // host copies of the integer state: P = pos = slot = identity, x marks the removals
+    std::vector<int> ident(nP);
+    std::vector<double> xs(nP, 1.0);
+    for (int c = 0; c < nP; ++c) ident[c] = c;
+    for (int t = 0; t < q; ++t) xs[rm[t]] = 0.0;
+    DeviceBuffer buf;
+    Prob* pp = nullptr;
+    LgArgs a;
+    size_t base_total = 0;
+    if (engine == 2) {
+        const LargeLayout L = large_layout(m, n, prm.kmax);
+        base_total = L.total + pad256(sizeof(double) * n) + pad256(sizeof(Mirror));
+        HIPCHK(hipMalloc(&buf.ptr, base_total));
+        char* base = (char*)buf.ptr;
+        large_bind(a, L, base, m, n, prm);
+        a.p.x = (double*)(base + L.total);
+        a.p.w = (double*)(base + L.wfall);
+        a.hmir = (Mirror*)(base + L.total + pad256(sizeof(double) * n));
+        HIPCHK(hipMemsetAsync(base + L.flt, 0, L.slot - L.flt, st));
+        pp = &a.p;
+    } else {
+        base_total = slot_bytes(m, n, prm.kmax) + pad256(sizeof(double) * n);
+        HIPCHK(hipMalloc(&buf.ptr, base_total));
+        carve_slot(a.p, (char*)buf.ptr, m, n, prm.kmax);
+        a.p.x = (double*)((char*)buf.ptr + slot_bytes(m, n, prm.kmax));
+        a.p.ybuf = nullptr;
+        a.p.Vt = nullptr;
+        pp = &a.p;
+    }
+    Prob& p = *pp;
+    p.A = nullptr;
+    p.b = nullptr;
+    p.lda = m;
+    p.passive = nullptr;
+    p.info = nullptr;
+    // kc = min(m, nP) = nP: R's leading dimension is nP, as the caller's
+    HIPCHK(hipMemcpyAsync(p.Q, Q, sizeof(double) * (size_t)m * m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.R, R, sizeof(double) * (size_t)nP * nP, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.bt, bt, sizeof(double) * (size_t)m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.P, ident.data(), sizeof(int) * nP, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.pos, ident.data(), sizeof(int) * nP, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.slot, ident.data(), sizeof(int) * nP, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.x, xs.data(), sizeof(double) * nP, hipMemcpyHostToDevice, st));
+    int nsweep = 0;
+    if (engine == 1) {
+        hipLaunchKernelGGL(wg_test_downdate_kernel, dim3(1), dim3(WG), 0, st, p, prm, nP);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        nsweep = 1;
+    } else {
+        // control block: nP positions, one accepted column (an inner step follows
+        // an append), the removal set pending (read from x by the next inner call)
+        Ctl c{};
+        c.nP = nP;
+        c.nP0 = nP;
+        c.nPa = nP;
+        c.k = 1;
+        c.kr = 1;
+        c.status = LHDM_STATUS_OK;
+        LgExtra ex{};
+        ex.pending = 1;
+        HIPCHK(hipMemcpyAsync(a.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(a.ex, &ex, sizeof(LgExtra), hipMemcpyHostToDevice, st));
+        int left = q, ep_g = 0, pub = 0;
+        while (left > 0) {
+            hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, st, a, ++pub);
+            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ++ep_g);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&ex, a.ex, sizeof(LgExtra), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (ex.err || ex.inner_done || c.q < 1 || c.q > left) return LHDM_EHIP;
+            if (ex.totrot == ex.ndown) {
+                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a, 1);
+                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a, 1);
+            } else {
+                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, st, a, 0);
+                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, st, a, 0);
+            }
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(&ex, a.ex, sizeof(LgExtra), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (ex.err) return LHDM_EHIP;
+            left -= c.q;
+            ++nsweep;
+            if ((left > 0) != (ex.pending != 0)) return LHDM_EHIP;
+        }
+    }
+    // read back: the kept columns of R through their slots, Q and bt
+    const int nk = nP - q;
+    std::vector<double> Rh((size_t)nP * nP), Rk((size_t)nk * nk, 0.0);
+    std::vector<int> sl(nP), Ph(nP);
+    HIPCHK(hipMemcpyAsync(Rh.data(), p.R, sizeof(double) * Rh.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sl.data(), p.slot, sizeof(int) * nP, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(Ph.data(), p.P, sizeof(int) * nP, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int cc = 0; cc < nk; ++cc)
+        for (int i = 0; i <= cc; ++i) Rk[(size_t)cc * nk + i] = Rh[(size_t)sl[cc] * nP + i];
+    if (nk > 0) HIPCHK(hipMemcpyAsync(Ro, Rk.data(), sizeof(double) * Rk.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(Qo, p.Q, sizeof(double) * (size_t)m * m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(bto, p.bt, sizeof(double) * (size_t)m, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (Po)
+        for (int cc = 0; cc < nk; ++cc) Po[cc] = Ph[cc];
+    if (sweeps) *sweeps = nsweep;
+    return 0;
+}
+
+}  // namespace lhdm
+
+extern "C" int lhdm_test_downdate(void* stream, int32_t engine, int32_t m, int32_t nP, const double* Q,
+                                  const double* R, const double* bt, int32_t q, const int32_t* rm, double* Q_out,
+                                  double* R_out, double* bt_out, int32_t* P_out, int32_t* sweeps) {
+    return lhdm::test_downdate((hipStream_t)stream, engine, m, nP, Q, R, bt, q, rm, Q_out, R_out, bt_out, P_out,
+                               sweeps);
+}

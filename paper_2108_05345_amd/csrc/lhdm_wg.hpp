@@ -126,10 +126,10 @@ struct Wg {
 
     // ---------------- a0: initialisation (Algorithm 3, first lines) ----------------
     __device__ void init() {
-        const int m = p.m, n = p.n;
+        const int m = p.m, nph = p.nph;
         double anmax = 0.0;
         int bad = 0;
-        for (int j = wid; j < n; j += NW) {
+        for (int j = wid; j < nph; j += NW) {
             const double* a = Acol(j);
             double ab = 0.0, aa = 0.0;
             for (int i = lane; i < m; i += 64) {
@@ -146,6 +146,15 @@ struct Wg {
                 p.pos[j] = -1;
                 p.excl[j] = 0;
                 p.x[j] = 0.0;
+                if (nph != p.n) {     // the twin -a_j of the positivity trick
+                    const int t = j + nph;
+                    p.w[t] = -ab;
+                    p.an2[t] = aa;
+                    p.u2[t] = aa;
+                    p.pos[t] = -1;
+                    p.excl[t] = 0;
+                    p.x[t] = 0.0;
+                }
             }
             if (!isfinite(ab) || !isfinite(aa)) bad = 1;
             anmax = fmax(anmax, aa);
@@ -188,7 +197,7 @@ struct Wg {
             const double u = sqrt(fmax(p.u2[j], 0.0));
             mwz = fmax(mwz, wj);
             mu = fmax(mu, u);
-            if (!p.excl[j] && u > DEP_TOL * sqrt(p.an2[j]) && better(wj, j, bv, bi)) {
+            if (!p.excl[j] && u > DEP_TOL * sqrt(p.an2[j]) && !twin_passive(p, j) && better(wj, j, bv, bi)) {
                 bv = wj;
                 bi = j;
             }
@@ -226,7 +235,7 @@ struct Wg {
                 const double wj = p.w[j];
                 if (!(wj >= tw)) continue;
                 const double u = sqrt(fmax(p.u2[j], 0.0));
-                if (!(u >= tu) || !(u > DEP_TOL * sqrt(p.an2[j]))) continue;
+                if (!(u >= tu) || !(u > DEP_TOL * sqrt(p.an2[j])) || twin_passive(p, j)) continue;
                 if (!(wj < pv || (wj == pv && j > pi))) continue;   // strictly after the previous pick
                 if (better(wj, j, cv, ci)) {
                     cv = wj;
@@ -252,10 +261,11 @@ struct Wg {
         for (int i = tid; i < m; i += WG) {
             const double* q = &Qat(0, i);
             for (int t = 0; t < cnt; ++t) {
-                const double* a = Acol(s.J[t]);
+                double sg;
+                const double* a = col_ptr(p, s.J[t], sg);
                 double acc = 0.0;
                 for (int l = 0; l < m; ++l) acc += q[l] * a[l];
-                p.G[(size_t)t * m + i] = acc;
+                p.G[(size_t)t * m + i] = sg * acc;
             }
         }
         __syncthreads();
@@ -507,6 +517,11 @@ struct Wg {
     // a5: feasibility loop on J (Algorithm 3): keep the longest prefix of J whose
     // own least-squares components are all positive.
     __device__ void jloop() {
+        if (prm.nojloop) {   // Theorem 4: the block is taken whole
+            if (tid == 0) s.k = s.kr;
+            __syncthreads();
+            return;
+        }
         if (tid == 0) {
             const int r0 = s.nP;
             int k = s.kr;
@@ -552,7 +567,7 @@ struct Wg {
             const double yc = yv[c];
             if (yc <= 0.0) {
                 const double xc = p.x[p.P[c]];
-                al = fmin(al, xc / (xc - yc));
+                al = fmin(al, step_ratio(xc, yc));
             }
         }
         al = vmin(al);
@@ -576,7 +591,7 @@ struct Wg {
             for (int u = 0; u < LB; ++u) {
                 if (cb + u < c1) {
                     double xn = xc[u] + al * (yc[u] - xc[u]);
-                    if (yc[u] <= 0.0 && xc[u] / (xc[u] - yc[u]) == al) xn = 0.0;
+                    if (yc[u] <= 0.0 && step_ratio(xc[u], yc[u]) == al) xn = 0.0;
                     if (xn <= 0.0) xn = 0.0;
                     p.x[j[u]] = xn;
                 }
@@ -587,6 +602,13 @@ struct Wg {
 
     // p.rm[0..s.q) = ascending passive positions whose x is <= 0.
     __device__ void collect_removals() {
+        collect_positions([&](int c, int j) { return p.x[j] <= 0.0; });
+    }
+
+    // p.rm[0..s.q) = ascending passive positions c (column j = P[c]) for which
+    // pick(c, j) holds.
+    template <typename Pick>
+    __device__ void collect_positions(Pick pick) {
         const int nP = s.nP;
         const int chunk = (nP + WG - 1) / WG;
         const int c0 = tid * chunk, c1 = min(nP, c0 + chunk);
@@ -598,12 +620,12 @@ struct Wg {
             int j[LB];
 #pragma unroll
             for (int u = 0; u < LB; ++u) j[u] = p.P[min(cb + u, c1 - 1)];
-            double xv[LB];
+            bool hit[LB];
 #pragma unroll
-            for (int u = 0; u < LB; ++u) xv[u] = p.x[j[u]];
+            for (int u = 0; u < LB; ++u) hit[u] = pick(min(cb + u, c1 - 1), j[u]);
 #pragma unroll
             for (int u = 0; u < LB; ++u)
-                if (cb + u < c1 && xv[u] <= 0.0) {
+                if (cb + u < c1 && hit[u]) {
                     ++mine;
                     if (cb + u - c0 < 64) mask |= 1ull << (cb + u - c0);
                 }
@@ -629,9 +651,39 @@ struct Wg {
             }
         } else {
             for (int c = c0; c < c1; ++c)
-                if (p.x[p.P[c]] <= 0.0) p.rm[o++] = c;
+                if (pick(c, p.P[c])) p.rm[o++] = c;
         }
         __syncthreads();
+    }
+
+    // The inner iteration of the positivity-trick case (Section 4.2): every
+    // passive position with y < 0 takes the twin of its column (the negated
+    // column), whose R column is the negated one and whose least-squares
+    // component is -y > 0; the residual is unchanged, so the inner loop ends.
+    // Returns false, changing nothing, when a component is exactly 0 (the
+    // ordinary inner iteration then runs).
+    __device__ bool sign_flip() {
+        const int nP = s.nP;
+        int zero = 0;
+        for (int c = tid; c < nP; c += WG) zero |= (yv[c] == 0.0) ? 1 : 0;
+        if (imax(zero)) return false;
+        collect_positions([&](int c, int j) { return yv[c] < 0.0; });
+        const int q = s.q;
+        for (int t = 0; t < q; ++t) {
+            const int c = p.rm[t];
+            double* col = p.R + (size_t)p.slot[c] * p.kc;
+            for (int i = tid; i <= c; i += WG) col[i] = -col[i];
+        }
+        for (int t = tid; t < q; t += WG) {
+            const int c = p.rm[t], j = p.P[c], tw = twin_of(p, j);
+            p.P[c] = tw;
+            p.pos[j] = -1;
+            p.pos[tw] = c;
+            p.x[j] = 0.0;
+            yv[c] = -yv[c];
+        }
+        __syncthreads();
+        return true;
     }
 
     // Algorithm 5: delete the passive positions p.rm[0..q) from R and restore the
@@ -771,7 +823,11 @@ struct Wg {
         const int m = p.m, nP = s.nP;
         for (int i = tid; i < m; i += WG) {
             double acc = p.b[i];
-            for (int c = 0; c < nP; ++c) acc -= p.A[(size_t)p.P[c] * p.lda + i] * yv[c];
+            for (int c = 0; c < nP; ++c) {
+                double sg;
+                const double* a = col_ptr(p, p.P[c], sg);
+                acc -= (sg * a[i]) * yv[c];
+            }
             p.r[i] = acc;
         }
         __syncthreads();
@@ -781,10 +837,11 @@ struct Wg {
     //   u2 <- u2 - sum_added (q^T a)^2 + sum_dropped (q^T a)^2,
     // or exactly from the trailing columns of Q when they are fewer.
     __device__ void dual_and_norms(int kadd) {
-        const int m = p.m, n = p.n, nP = s.nP, nPa = s.nPa;
+        const int m = p.m, nph = p.nph, nP = s.nP, nPa = s.nPa;
         const int ndrop = nPa - nP;
         const bool exact = (m - nP) <= kadd + ndrop;
-        for (int j = wid; j < n; j += NW) {
+        const bool tw = nph != p.n;
+        for (int j = wid; j < nph; j += NW) {
             const double* a = Acol(j);
             double acc = 0.0;
             for (int i = lane; i < m; i += 64) acc += a[i] * p.r[i];
@@ -814,7 +871,7 @@ struct Wg {
                     u2 += d * d;
                 }
                 u2 = fmax(u2, 0.0);
-                if (p.pos[j] < 0 && u2 < RECOMP_FRAC * p.an2[j]) {
+                if (p.pos[j] < 0 && !twin_passive(p, j) && u2 < RECOMP_FRAC * p.an2[j]) {
                     u2 = 0.0;
                     for (int t = nP; t < m; ++t) {
                         double d = 0.0;
@@ -827,6 +884,10 @@ struct Wg {
             if (lane == 0) {
                 p.w[j] = wj;
                 p.u2[j] = u2;
+                if (tw) {
+                    p.w[j + nph] = -wj;
+                    p.u2[j + nph] = u2;
+                }
             }
         }
         __syncthreads();
@@ -834,22 +895,27 @@ struct Wg {
 
     // r and w for the current x (used when the loop stops inside an inner loop)
     __device__ void refresh_dual() {
-        const int m = p.m, n = p.n;
+        const int m = p.m, nph = p.nph;
         for (int i = tid; i < m; i += WG) {
             double acc = p.b[i];
             for (int c = 0; c < s.nP; ++c) {
                 const int j = p.P[c];
-                acc -= p.A[(size_t)j * p.lda + i] * p.x[j];
+                double sg;
+                const double* a = col_ptr(p, j, sg);
+                acc -= (sg * a[i]) * p.x[j];
             }
             p.r[i] = acc;
         }
         __syncthreads();
-        for (int j = wid; j < n; j += NW) {
+        for (int j = wid; j < nph; j += NW) {
             const double* a = Acol(j);
             double acc = 0.0;
             for (int i = lane; i < m; i += 64) acc += a[i] * p.r[i];
             acc = wave_sum(acc);
-            if (lane == 0) p.w[j] = acc;
+            if (lane == 0) {
+                p.w[j] = acc;
+                if (nph != p.n) p.w[j + nph] = -acc;
+            }
         }
         __syncthreads();
     }
@@ -959,6 +1025,7 @@ struct Wg {
                 }
                 __syncthreads();
                 if (tid == 0) s.inner += 1;
+                if (prm.signflip && sign_flip()) break;   // y > 0 now: the inner loop ends
                 inner_step();
                 downdate();
                 trsv();

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "lhdm.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "\n".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
     return sorted(set(n for n in names if n.startswith(("lhdm_", "lh_"))))
@@ -100,3 +101,21 @@ def test_workspace_queries(lib):
     nn = (ctypes.c_int32 * 2)(80, 130)
     assert lib.lhdm_batched_workspace_bytes(2, mm, nn, ctypes.byref(p)) > 0
     assert lib.lhdm_backward_workspace_bytes(2, mm, nn) >= 8 * (32 * 32 + 64 * 64)
+
+
+def test_signed_entry_rejects_bad_sizes_before_device_work(lib):
+    from paper_2108_05345_amd import _lib
+    p = _lib.LhdmParams()
+    lib.lhdm_default_params(ctypes.byref(p))
+    assert lib.lhdm_solve_signed(None, 0, 5, None, 1, None, ctypes.byref(p), 1, None, None, None, None, None,
+                                 0) == _lib.LHDM_EINVAL
+    assert lib.lhdm_signed_workspace_bytes(0, 5, ctypes.byref(p)) == 0
+
+
+def test_theorem4_flag_is_checked_on_the_host(lib):
+    from paper_2108_05345_amd import _lib
+    p = _lib.LhdmParams()
+    lib.lhdm_default_params(ctypes.byref(p))
+    p.flags = 4   # LHDM_FLAG_NO_JLOOP with tau1 = 0.6: invalid
+    assert lib.lhdm_solve(None, 4, 4, None, 4, None, ctypes.byref(p), None, None, None, None, None,
+                          0) == _lib.LHDM_EINVAL

@@ -1,0 +1,45 @@
+"""The stored oracle paths of the 4096 x 16384 instance (tests/golden/c3_*.npz)
+checked against what the mathematics fixes, without a GPU: the step lists
+rebuild the final passive set, the stored x satisfies the KKT conditions of
+Theorem 1 at 1e-9 on the regenerated instance, and it is nonzero exactly on
+the passive set."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import oracle_passive_after
+from workloads import make_c3
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DELTAS = (0.2, 0.5, 0.8)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return make_c3(3000)
+
+
+@pytest.mark.parametrize("delta", DELTAS)
+def test_golden_path_rebuilds_the_passive_set(delta):
+    z = np.load(os.path.join(GOLDEN, f"c3_seed3000_delta{delta:.1f}.npz"), allow_pickle=False)
+    st, outer, inner, jdrops, nP = (int(v) for v in z["counters"])
+    assert st == 0 and float(z["delta"]) == delta and int(z["seed"]) == 3000
+    assert len(z["J_len"]) == outer and int(z["rm_count"].sum()) == inner
+    assert int(z["drops"].sum()) <= jdrops
+    P = oracle_passive_after(z, outer)
+    assert P == [int(j) for j in z["passive"]] and len(P) == nP
+    # every step appends at least one column (Theorem 3: no empty step)
+    assert (z["J_len"] >= 1).all() and (z["J_len"] <= 32).all()
+
+
+@pytest.mark.parametrize("delta", DELTAS)
+def test_golden_solution_satisfies_kkt(c3, delta):
+    z = np.load(os.path.join(GOLDEN, f"c3_seed3000_delta{delta:.1f}.npz"), allow_pickle=False)
+    x = z["x"]
+    P = [int(j) for j in z["passive"]]
+    assert (x >= 0).all() and np.count_nonzero(x) == len(P) and (x[P] > 0).all()
+    rep = oracle.kkt_report(c3.A, c3.b, x)
+    assert rep["kkt"] <= 1e-9 and rep["feasible"]
+    assert abs(rep["kkt"] - float(z["kkt"])) <= 1e-12

@@ -10,12 +10,10 @@ import pytest
 import torch
 
 import oracle
+from parity_util import KKT, XTOL, _check, _dev, _passive, _rel, _supp  # noqa: F401
 from workloads import make_c1, make_c3, make_c4_batch, make_c5_batch, make_small
 
 pytestmark = pytest.mark.gpu
-
-XTOL = 1e-10
-KKT = 1e-9
 
 
 @pytest.fixture(scope="module")
@@ -26,62 +24,6 @@ def lhdm():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return mod
-
-
-def _dev(A, b):
-    d = torch.device("cuda:0")
-    return (torch.from_numpy(np.asfortranarray(A)).to(d), torch.from_numpy(np.ascontiguousarray(b)).to(d))
-
-
-def _rel(x, xo):
-    return float(np.abs(x - xo).max() / max(np.abs(xo).max(), 1e-300))
-
-
-def _passive(res):
-    P = res.passive.cpu().numpy()
-    return [int(j) for j in P if j >= 0]
-
-
-SUPP_THR = 1e-12   # support = entries above this fraction of max|x| (rounding-level entries excluded)
-SEP = 1e-8         # a solution is well separated when every passive entry exceeds SEP * max|x|
-
-
-def _supp(x):
-    return sorted(int(j) for j in np.nonzero(x > SUPP_THR * np.abs(x).max(initial=0.0))[0])
-
-
-def _check(res, x_o, info_o, *, same_path=True, unique=True, tag=""):
-    """Compare one GPU result with the oracle's.
-
-    In zero-residual instances an appended column can have an exactly-zero
-    least-squares coefficient; its sign, and so the decisions of the feasibility
-    loops, is then set by rounding and legitimately differs between summation
-    orders.  Path identity (ordered P, iteration counters) is therefore required
-    only when both solutions are well separated from zero."""
-    x = res.x.cpu().numpy()
-    print(f"[{tag}] gpu info {res.info} | oracle outer={info_o['outer_iters']} inner={info_o['inner_iters']} "
-          f"jd={info_o['jloop_drops']} nP={info_o['n_passive']}", flush=True)
-    assert res.info["status"] == info_o["status"] == 0
-    assert (x >= 0).all()
-    assert res.info["kkt_residual"] <= KKT
-    P = _passive(res)
-    assert res.info["n_passive"] == len(P)
-    assert all(x[j] > 0 for j in P)
-    assert np.count_nonzero(x) == len(P)
-    if unique:
-        assert _supp(x) == _supp(x_o), tag
-        assert _rel(x, x_o) <= XTOL, (tag, _rel(x, x_o))
-    Po = info_o["passive"]
-
-    def sep(xx, PP):
-        return len(PP) == 0 or float(np.min(xx[PP])) > SEP * float(np.abs(xx).max())
-
-    separated = sep(x_o, Po) and sep(x, P)
-    if same_path and separated:
-        assert P == Po, tag
-        for key in ("outer_iters", "inner_iters", "jloop_drops"):
-            assert res.info[key] == info_o[key], (tag, key)
-    return separated
 
 
 ENGINES = ["workgroup", "device"]
@@ -100,9 +42,9 @@ def test_c1_lhdm_and_lh(lhdm, seed, engine):
     inst = make_c1(seed)
     A, b = _dev(inst.A, inst.b)
     xo, io = oracle.oracle_lhdm(inst.A, inst.b)
-    _check(lhdm.solve(A, b, engine=engine), xo, io, tag=f"c1-lhdm-{seed}-{engine}")
+    assert _check(lhdm.solve(A, b, engine=engine), xo, io, tag=f"c1-lhdm-{seed}-{engine}") in ("path", "order")
     xo, io = oracle.oracle_lh(inst.A, inst.b)
-    _check(_lh(lhdm, A, b, engine), xo, io, tag=f"c1-lh-{seed}-{engine}")
+    assert _check(_lh(lhdm, A, b, engine), xo, io, tag=f"c1-lh-{seed}-{engine}") == "path"
     # planted recovery
     np.testing.assert_allclose(lhdm.solve(A, b, engine=engine).x.cpu().numpy(), inst.x_true, atol=1e-12)
 
@@ -148,8 +90,10 @@ def test_scaled_c3_delta_sweep(lhdm, delta, engine):
     inst = make_c3(3000, m=160, n=640, k=32)
     A, b = _dev(inst.A, inst.b)
     xo, io = oracle.oracle_lhdm(inst.A, inst.b, delta=delta)
-    _check(lhdm.solve(A, b, delta=delta, engine=engine), xo, io, unique=False, same_path=True,
-           tag=f"c3s-d{delta}-{engine}")
+    # the oracle's solution is separated here (min x_P > 1e-8 max x), so the
+    # whole path must be compared, not only its significant columns
+    assert _check(lhdm.solve(A, b, delta=delta, engine=engine), xo, io, unique=False, same_path=True,
+                  tag=f"c3s-d{delta}-{engine}") == "path"
 
 
 @pytest.mark.parametrize("engine", ENGINES)
@@ -265,10 +209,10 @@ def test_c2_full_size(lhdm):
     A, b = _dev(inst.A, inst.b)
     xo, io = oracle.oracle_lhdm(inst.A, inst.b)
     r = lhdm.solve(A, b)
-    _check(r, xo, io, tag="c2-lhdm")
+    assert _check(r, xo, io, tag="c2-lhdm") == "path"
     np.testing.assert_allclose(r.x.cpu().numpy(), inst.x_true, atol=1e-10)
     xo, io = oracle.oracle_lh(inst.A, inst.b)
-    _check(lhdm.lh_solve(A, b), xo, io, tag="c2-lh")
+    assert _check(lhdm.lh_solve(A, b), xo, io, tag="c2-lh") == "path"
 
 
 @pytest.mark.parametrize("delta", [0.8])

@@ -160,3 +160,66 @@ def test_every_inner_iteration_removes_the_step_length_index(case):
             assert len(rm) >= 1
             n_inner += 1
     assert n_inner == info["inner_iters"] and n_inner > 0
+
+
+# ---------------------------------------------------------------------------
+# Theorem 4: tau1 = 1 and tau2 <= 1/2 make the feasibility loop on J idle
+# ---------------------------------------------------------------------------
+def tie_instance(seed, m=30, ntie=6, nweak=12):
+    """Six columns with disjoint 3-row supports of ones (mutually orthogonal,
+    norm sqrt(3)) and weak columns of U[0, 0.15] entries; b = ones.  The first
+    dual vector is exactly 3 on the six (an exact tie; the weak columns' duals
+    are smaller), so with tau1 = 1 the first block holds all six; later duals
+    are continuous, so the rest of the path has no rounding-level ties."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((m, ntie + nweak))
+    rows = rng.permutation(m)
+    for i in range(ntie):
+        A[rows[3 * i:3 * i + 3], i] = 1.0
+    A[:, ntie:] = rng.uniform(0.0, 0.15, size=(m, nweak))
+    assert (A[:, ntie:].sum(axis=0) < 3.0).all()
+    return A, np.ones(m)
+
+
+T4 = dict(tau1=1.0, tau2=0.5, kmax=8, delta=0.5 / 7)   # delta <= tau2 / (kmax - 1)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14, 15])
+def test_theorem4_variant_takes_the_same_path(seed):
+    # with tau1 = 1, tau2 <= 1/2 and delta <= tau2 / (kmax - 1), Theorem 4 says
+    # the feasibility loop never drops a column, so skipping it must leave the
+    # whole path unchanged
+    A, b = tie_instance(seed)
+    x1, i1 = oracle.oracle_lhdm(A, b, record=True, **T4)
+    x2, i2 = oracle.oracle_lhdm(A, b, record=True, jloop=False, **T4)
+    assert i1["jloop_drops"] == 0 and i2["jloop_drops"] == 0
+    assert [s["J"] for s in i1["trace"]] == [s["J"] for s in i2["trace"]]
+    assert i1["passive"] == i2["passive"]
+    np.testing.assert_array_equal(x1, x2)
+    assert len(i2["trace"][0]["J"]) == 6          # the tied orthogonal columns, in index order
+    assert i2["trace"][0]["J"] == [0, 1, 2, 3, 4, 5]
+    assert oracle.kkt_report(A, b, x2)["kkt"] <= 1e-9
+
+
+def test_theorem4_variant_needs_its_thresholds():
+    A, b = tie_instance(11)
+    with pytest.raises(ValueError):
+        oracle.oracle_lhdm(A, b, tau1=0.6, tau2=0.15, jloop=False)
+    with pytest.raises(ValueError):
+        oracle.oracle_lhdm(A, b, tau1=1.0, tau2=0.6, jloop=False)
+    with pytest.raises(ValueError):
+        oracle.oracle_lhdm(A, b, tau1=1.0, tau2=0.5, kmax=8, delta=0.9, jloop=False)
+
+
+def test_zero_iterate_entry_limits_the_step_to_zero():
+    # without the feasibility loop a new column can enter the inner loop with
+    # x_j = 0 and y_j <= 0: its ratio is 0, so the step is 0 and it leaves P
+    from oracle.nnls import _QRState, _inner_step
+    A = np.array([[1.0, 0.0], [0.0, 1.0], [0.0, 0.0]])
+    st = _QRState(A, np.array([1.0, -1.0, 0.0]))
+    st.append(0)
+    st.append(1)
+    x = np.array([0.5, 0.0])
+    y = st.solve()                       # (1, -1): column 1 has y <= 0 and x = 0
+    rm, alpha = _inner_step(st, x, y)
+    assert alpha == 0.0 and rm == [1] and st.P == [0] and x[0] == 0.5

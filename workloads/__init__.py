@@ -13,5 +13,7 @@ from .generators import (  # noqa: F401
     make_c4_batch,
     make_c5_batch,
     make_small,
+    make_illcond,
+    make_signed,
     CONFIGS,
 )

@@ -136,6 +136,42 @@ def make_c5_batch(seed: int = 5000, count: int = 256, m: int = 256, n: int = 512
     return out
 
 
+def make_illcond(m, n, k, row_range, seed, *, vals=(1.0, 2.0), noise_std=0.0, name="illcond"):
+    """A = diag(d) U with U ~ U[0, 1]^(m x n) and row scales d log-spaced from 1
+    down to 1 / row_range; x_true k-sparse with U[vals] entries; b = A x + noise.
+
+    Row scaling leaves the set {x >= 0 : A x = b} unchanged (it is the set of
+    the unscaled system), so a sparse planted solution of the nonnegative
+    matrix U stays the unique one, while the condition number of A grows to
+    about 10 * row_range (1e4 -> ~5e5, 1e5 -> ~5e6).  Stands in for the
+    moderately ill-conditioned matrices (condition number 1e5 to 1e6) of the
+    paper's experiments, whose dataset is not available here."""
+    rng = _rng(seed)
+    U = rng.uniform(0.0, 1.0, (m, n))
+    d = np.logspace(0.0, -np.log10(row_range), m)
+    A = d[:, None] * U
+    lo, hi = vals
+    return _planted(rng, A, k, lambda r, kk: r.uniform(lo, hi, kk), noise_std, name, seed,
+                    {"m": m, "n": n, "k": k, "row_range": row_range, "noise_std": noise_std})
+
+
+def make_signed(m, n, k, seed, *, noise_std=0.0, name="signed"):
+    """Signed sparse recovery (the positivity-trick problem): A ~ N(0, 1/m),
+    x_true k-sparse with random signs and magnitudes U[1, 2]; b = A x + noise.
+    ``x_true`` is signed here (the nonnegative variable of the trick is
+    (x+, x-))."""
+    rng = _rng(seed)
+    A = rng.standard_normal((m, n)) / np.sqrt(m)
+    S = np.sort(rng.choice(n, size=k, replace=False))
+    x = np.zeros(n)
+    x[S] = rng.uniform(1.0, 2.0, k) * rng.choice([-1.0, 1.0], size=k)
+    b = A @ x
+    if noise_std > 0.0:
+        b = b + noise_std * rng.standard_normal(m)
+    return Instance(name=name, seed=seed, A=np.asfortranarray(A), b=np.ascontiguousarray(b), x_true=x,
+                    support=S, meta={"m": m, "n": n, "k": k, "noise_std": noise_std})
+
+
 CONFIGS = {
     "c1": make_c1,
     "c2": make_c2,
