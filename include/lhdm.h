@@ -181,6 +181,32 @@ int lhdm_solve_batched(void* stream, int32_t batch, const int32_t* m, const int3
                        const lhdm_params* p, int32_t use_lh, lhdm_info* infos,
                        void* ws, size_t ws_bytes);
 
+/* Size of the fixed device scratch of lhdm_solve_batched_noalloc (per device). */
+#define LHDM_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
+ * solve of lhdm_solve_batched without a workspace argument and without any
+ * allocation.  Arguments and results as in lhdm_solve_batched.  Every buffer
+ * beyond the caller's inputs and outputs lives in a fixed scratch array of
+ * LHDM_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends.  The scratch keeps the bookkeeping of the batch
+ * (about 90 bytes per instance) and as many instance slots as fit (a slot is
+ * the state of one instance of the largest m and n: about 8 (m^2 + min(m,n)^2
+ * + 4 m kmax) bytes plus a few vectors of length m and n), so fewer instances
+ * may be in flight at once than
+ * with lhdm_solve_batched; instances are taken in the given order (no
+ * largest-first reordering).  Returns LHDM_EUNSUPPORTED, before any device
+ * work, when the bookkeeping plus one slot exceeds the scratch, and for m > 2048.
+ * All calls on one device share its scratch and every call overwrites it (what
+ * must start at zero is cleared by the call itself): calls that overlap in time
+ * on one device race, so serialise them (one host thread, one stream). */
+int lhdm_solve_batched_noalloc(void* stream, int32_t batch, const int32_t* m, const int32_t* n,
+                               const int64_t* a_off, const double* A_pool,
+                               const int64_t* b_off, const double* b_pool,
+                               const int64_t* x_off, double* x_pool, int32_t* passive_pool,
+                               const lhdm_params* p, int32_t use_lh, lhdm_info* infos);
+
 /* Bytes of workspace for lhdm_backward. */
 size_t lhdm_backward_workspace_bytes(int32_t batch, const int32_t* m, const int32_t* n);
 

@@ -73,6 +73,8 @@ SIGNATURES = {
     "lhdm_batched_workspace_bytes": (_sz, [_i32, _pi32, _pi32, ctypes.POINTER(LhdmParams)]),
     "lhdm_solve_batched": (ctypes.c_int, [_vp, _i32, _pi32, _pi32, _pi64, _vp, _pi64, _vp, _pi64, _vp, _vp,
                                           ctypes.POINTER(LhdmParams), _i32, _vp, _vp, _sz]),
+    "lhdm_solve_batched_noalloc": (ctypes.c_int, [_vp, _i32, _pi32, _pi32, _pi64, _vp, _pi64, _vp, _pi64, _vp,
+                                                  _vp, ctypes.POINTER(LhdmParams), _i32, _vp]),
     "lhdm_backward_workspace_bytes": (_sz, [_i32, _pi32, _pi32]),
     "lhdm_backward": (ctypes.c_int, [_vp, _i32, _pi32, _pi32, _pi64, _vp, _pi64, _vp, _pi64, _vp, _vp, _vp,
                                      _vp, _vp, _vp, _sz]),

@@ -211,6 +211,138 @@ static int solve_one(void* stream, int32_t m, int32_t n, const double* A, int64_
     return run_wg_engine(st, ins, mm, nn, prm, ws, L.total);
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free batched solve (lhdm_solve_batched_noalloc)
+// ---------------------------------------------------------------------------
+// Every buffer of the call beyond the caller's inputs and outputs lives in this
+// fixed array: the batch's size and offset arrays, the instance descriptors,
+// the queue counter and the workgroups' slots (each slot also holds its
+// instance's dual).  Each device the library runs on holds its own copy until
+// the process ends.  Host code never passes `scratch` itself to a kernel or a
+// copy: in host code the name is a host-side stand-in, not the device address;
+// noalloc_scratch() returns the address on the current device.
+static __device__ __align__(256) char scratch[LHDM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// Device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept.
+static int noalloc_scratch(char** out) {
+    static std::mutex mu;
+    static char* ptrs[NOALLOC_MAX_DEVICES] = {};
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return LHDM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return LHDM_EHIP;
+        ptrs[dev] = (char*)ptr;
+    }
+    *out = ptrs[dev];
+    return 0;
+}
+
+// Layout of the scratch for one call: [m | n | a_off | b_off | x_off | ProbIn
+// x batch | counter | slots].  A slot is the instance state of slot_bytes()
+// followed by the dual (nmax doubles).
+struct NoallocLayout {
+    size_t off_m, off_n, off_a, off_b, off_x, off_in, off_counter, off_slots, slot_stride, w_off, head;
+};
+
+static NoallocLayout noalloc_layout(int batch, int mmax, int nmax, int kmax) {
+    NoallocLayout L;
+    size_t o = 0;
+    L.off_m = o;
+    o += pad256(sizeof(int32_t) * (size_t)batch);
+    L.off_n = o;
+    o += pad256(sizeof(int32_t) * (size_t)batch);
+    L.off_a = o;
+    o += pad256(sizeof(int64_t) * (size_t)batch);
+    L.off_b = o;
+    o += pad256(sizeof(int64_t) * (size_t)batch);
+    L.off_x = o;
+    o += pad256(sizeof(int64_t) * (size_t)batch);
+    L.off_in = o;
+    o += pad256(sizeof(ProbIn) * (size_t)batch);
+    L.off_counter = o;
+    o += 256;
+    L.off_slots = o;
+    L.head = o;
+    L.w_off = slot_bytes(mmax, nmax, kmax);
+    L.slot_stride = L.w_off + pad256(sizeof(double) * (size_t)nmax);
+    return L;
+}
+
+// Instance descriptors from the size and offset arrays (one thread each); the
+// queue counter starts at 0 (a kernel store: no memset node on the stream).
+__global__ __launch_bounds__(WG) void noalloc_describe(int batch, const int32_t* m, const int32_t* n,
+                                                        const int64_t* ao, const double* Ap, const int64_t* bo,
+                                                        const double* bp, const int64_t* xo, double* xp,
+                                                        int32_t* pp, lhdm_info* infos, ProbIn* out, int* counter) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i == 0) *counter = 0;
+    if (i >= batch) return;
+    ProbIn in;
+    in.A = Ap + ao[i];
+    in.lda = m[i];
+    in.b = bp + bo[i];
+    in.x = xp + xo[i];
+    in.w = nullptr;   // the dual stays in the slot
+    in.passive = pp ? pp + xo[i] : nullptr;
+    in.info = infos ? infos + i : nullptr;
+    in.m = m[i];
+    in.n = n[i];
+    out[i] = in;
+}
+
+static int solve_batched_noalloc(hipStream_t st, int batch, const int32_t* m, const int32_t* n,
+                                 const int64_t* a_off, const double* A_pool, const int64_t* b_off,
+                                 const double* b_pool, const int64_t* x_off, double* x_pool, int32_t* passive_pool,
+                                 const lhdm_params* p, int use_lh, lhdm_info* infos) {
+    if (batch < 1 || !m || !n || !a_off || !b_off || !x_off || !A_pool || !b_pool || !x_pool) return LHDM_EINVAL;
+    if (!params_ok(p)) return LHDM_EINVAL;
+    int mmax = 1, nmax = 1;
+    for (int i = 0; i < batch; ++i) {
+        if (m[i] < 1 || n[i] < 1) return LHDM_EINVAL;
+        if (m[i] > MMAX_WG) return LHDM_EUNSUPPORTED;
+        mmax = std::max(mmax, (int)m[i]);
+        nmax = std::max(nmax, (int)n[i]);
+    }
+    const int kmax = use_lh ? 1 : p->kmax;
+    const NoallocLayout L = noalloc_layout(batch, mmax, nmax, kmax);
+    // the bookkeeping and at least one slot must fit the fixed scratch
+    if (L.head > (size_t)LHDM_NOALLOC_SCRATCH_BYTES ||
+        L.slot_stride > (size_t)LHDM_NOALLOC_SCRATCH_BYTES - L.head)
+        return LHDM_EUNSUPPORTED;
+    char* base = nullptr;
+    int rc = noalloc_scratch(&base);
+    if (rc) return rc;
+    const int fit = (int)std::min<size_t>((size_t)INT_MAX, ((size_t)LHDM_NOALLOC_SCRATCH_BYTES - L.head) / L.slot_stride);
+    const int nslot = std::max(1, std::min(wg_slots_for(batch), fit));
+    HIPCHK(hipMemcpyAsync(base + L.off_m, m, sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + L.off_n, n, sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + L.off_a, a_off, sizeof(int64_t) * batch, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + L.off_b, b_off, sizeof(int64_t) * batch, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + L.off_x, x_off, sizeof(int64_t) * batch, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(noalloc_describe, dim3((batch + WG - 1) / WG), dim3(WG), 0, st, batch,
+                       (const int32_t*)(base + L.off_m), (const int32_t*)(base + L.off_n),
+                       (const int64_t*)(base + L.off_a), A_pool, (const int64_t*)(base + L.off_b), b_pool,
+                       (const int64_t*)(base + L.off_x), x_pool, passive_pool, infos, (ProbIn*)(base + L.off_in),
+                       (int*)(base + L.off_counter));
+    HIPCHK(hipGetLastError());
+    DevParams prm = dev_params(p, nmax, use_lh ? 1 : 0);
+    prm.max_outer = p->max_outer > 0 ? p->max_outer : 0;   // <= 0: 3 n per instance
+    prm.max_inner = p->max_inner > 0 ? p->max_inner : 0;
+    hipLaunchKernelGGL(wg_solve_kernel, dim3(nslot), dim3(WG), 0, st, (const ProbIn*)(base + L.off_in), batch,
+                       (const int*)nullptr, (int*)(base + L.off_counter), base + L.off_slots, L.slot_stride, prm,
+                       L.w_off);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
 // x = z[:n] - z[n:] (the signed solution of the positivity trick).
 __global__ __launch_bounds__(WG) void signed_combine(const double* __restrict__ z, double* __restrict__ x, int n) {
     const int j = blockIdx.x * WG + threadIdx.x;
@@ -467,6 +599,19 @@ int lhdm_solve_batched(void* stream, int32_t batch, const int32_t* m, const int3
     prm.max_outer = p->max_outer > 0 ? p->max_outer : 0;
     prm.max_inner = p->max_inner > 0 ? p->max_inner : 0;
     return run_wg_engine((hipStream_t)stream, ins, mm, nn, prm, ws, L.total);
+}
+
+int lhdm_solve_batched_noalloc(void* stream, int32_t batch, const int32_t* m, const int32_t* n,
+                               const int64_t* a_off, const double* A_pool, const int64_t* b_off,
+                               const double* b_pool, const int64_t* x_off, double* x_pool, int32_t* passive_pool,
+                               const lhdm_params* p, int32_t use_lh, lhdm_info* infos) {
+    lhdm_params def;
+    if (!p) {
+        lhdm_default_params(&def);
+        p = &def;
+    }
+    return solve_batched_noalloc((hipStream_t)stream, batch, m, n, a_off, A_pool, b_off, b_pool, x_off, x_pool,
+                                 passive_pool, p, use_lh, infos);
 }
 
 size_t lhdm_backward_workspace_bytes(int32_t batch, const int32_t* m, const int32_t* n) {
