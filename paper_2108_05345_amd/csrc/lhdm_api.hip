@@ -40,8 +40,9 @@ __global__ __launch_bounds__(WG) void wg_solve_kernel(const ProbIn* __restrict__
                                                       const int* __restrict__ order, int* counter,
                                                       char* slots, size_t slot_stride, DevParams prm,
                                                       size_t w_off) {
-    __shared__ WgShared sh;
-    __shared__ int sidx;
+    __shared__ WgLds lds;
+    WgShared& sh = lds.sh;
+    int& sidx = lds.sidx;
     char* base = slots + (size_t)blockIdx.x * slot_stride;
     while (true) {
         if (threadIdx.x == 0) sidx = atomicAdd(counter, 1);
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(WG) void wg_solve_kernel(const ProbIn* __restrict__
         DevParams q = prm;
         if (q.max_outer <= 0) q.max_outer = 3 * in.n;
         if (q.max_inner <= 0) q.max_inner = 3 * in.n;
-        Wg wg(p, q, sh);
+        Wg wg(p, q, sh, (lds_double*)lds.x);
         wg.run();
         __syncthreads();
     }

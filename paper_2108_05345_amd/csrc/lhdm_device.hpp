@@ -28,6 +28,7 @@ constexpr double DEP_TOL = 1e-12;    // projected norm <= DEP_TOL ||a_j||: numer
 constexpr double RECOMP_FRAC = 1e-4; // u2 below this fraction of ||a_j||^2: recompute exactly
 constexpr int YMAX = 2048;           // largest min(m, n) of the workgroup engine
 constexpr int MMAX_WG = 2048;        // largest m of the workgroup engine
+constexpr int DVL = 64;              // vectors per row of the workgroup engine's vector block
 
 struct DevParams {
     double tau1, tau2, delta, kkt_tol;
@@ -70,6 +71,7 @@ struct Prob {
     double* ybuf;      // kc : least-squares solution by position (large-instance engine)
     double* Vt;        // m * kq : V stored row-major (large-instance engine)
     int* itmp;         // 2 * kc : scratch of the passive-set compaction
+    double* Dv;        // m * DVL, row-major: vector block of the workgroup engine's products
 };
 
 // Bytes of one instance's workspace slice (each array padded to 256 bytes).
@@ -91,6 +93,7 @@ __host__ __device__ inline size_t slot_bytes(int m, int n, int kmax) {
     s += 3 * pad256(sizeof(int) * kc);                 // P, rm, slot
     s += pad256(sizeof(int) * 2 * kc);                 // itmp
     s += 2 * pad256(sizeof(int) * (size_t)n);          // pos, excl
+    s += pad256(sizeof(double) * (size_t)m * DVL);     // Dv
     return s;
 }
 
@@ -121,6 +124,7 @@ __host__ __device__ inline void carve_slot(Prob& p, char* base, int m, int n, in
     p.itmp = (int*)take(sizeof(int) * 2 * kc);
     p.pos = (int*)take(sizeof(int) * n);
     p.excl = (int*)take(sizeof(int) * n);
+    p.Dv = (double*)take(sizeof(double) * (size_t)m * DVL);
     p.ybuf = nullptr;
     p.Vt = nullptr;
     p.nph = n;

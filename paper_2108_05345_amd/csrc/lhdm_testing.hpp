@@ -13,8 +13,9 @@ namespace lhdm {
 // One-workgroup engine: the removal set is read from x (x <= 0 marks a
 // removed position) and deleted in one sweep, compaction included.
 __global__ __launch_bounds__(WG) void wg_test_downdate_kernel(Prob p, DevParams prm, int nP) {
-    __shared__ WgShared s;
-    Wg wg(p, prm, s);
+    __shared__ WgLds lds;
+    WgShared& s = lds.sh;
+    Wg wg(p, prm, s, (lds_double*)lds.x);
     if (threadIdx.x == 0) {
         s.nP = nP;
         s.q = 0;

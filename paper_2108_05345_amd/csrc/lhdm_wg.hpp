@@ -33,6 +33,30 @@ struct WgShared : Ctl {
     int cnt[WG];             // prefix counts for compaction
 };
 
+typedef double wd4 __attribute__((ext_vector_type(4)));
+
+// LDS work area of the phases that stage tiles (triangular solve, downdate,
+// matrix-core products); the phases are separated by barriers, so one area
+// serves them all.  It is reached only through LDS-typed pointers (ds_*
+// instructions).  The control block WgShared, which the step functions reach
+// through a generic reference (flat instructions), must lie in the first
+// 64 KiB of the workgroup's LDS: flat accesses above that offset are not
+// routed to LDS.  Kernels therefore declare both in one WgLds, the control
+// block first.
+typedef __attribute__((address_space(3))) double lds_double;
+typedef __attribute__((address_space(3))) int lds_int;
+constexpr int WG_TS = 64;                          // triangular-solve block
+constexpr int WG_DB = 64;                          // downdate window
+constexpr int WG_LX = (WG_DB + 1) * WG_DB + 2 * YMAX;
+static_assert(WG_LX >= NW * 16 * 65, "colmat tile staging");
+static_assert(WG_LX >= WG_TS * (WG_TS + 1) + WG_TS, "triangular-solve block");
+struct WgLds {
+    WgShared sh;
+    double x[WG_LX];
+    int sidx;
+};
+static_assert(sizeof(WgShared) <= 65536, "flat accesses to the control block stay below 64 KiB");
+
 struct Wg {
     static constexpr int LB = 8;   // gathered loads issued together per thread
     Prob& p;
@@ -40,10 +64,11 @@ struct Wg {
     WgShared& s;
     int tid, lane, wid;
     double* yv;   // least-squares solution by position: LDS (workgroup engine) or global
+    lds_double* lx;   // LDS work area of trsv, downdate and colmat (WG_LX doubles)
 
-    __device__ Wg(Prob& p_, const DevParams& prm_, WgShared& s_)
+    __device__ Wg(Prob& p_, const DevParams& prm_, WgShared& s_, lds_double* x_ = nullptr)
         : p(p_), prm(prm_), s(s_), tid(threadIdx.x), lane(threadIdx.x & 63), wid(wave_index()),
-          yv(p_.ybuf ? p_.ybuf : s_.y) {}
+          yv(p_.ybuf ? p_.ybuf : s_.y), lx(x_) {}
 
     // ---------------- workgroup reductions ----------------
     __device__ double sum(double v) {
@@ -254,21 +279,90 @@ struct Wg {
         __syncthreads();
     }
 
-    // G[:, t] = Q^T a_{J[t]} for t < cnt (full projection: rows < n_P are Q_P^T a,
-    // rows >= n_P the coordinates of the projected column in the trailing basis).
-    __device__ void project(int cnt) {
+    // out(j, t) = X[:, j] . Dv[:, t] for j < ncols, t < nv <= 16 NT, on the FP64
+    // matrix cores (v_mfma_f64_16x16x4f64).  X is column-major (ld ldx, rows
+    // [0, m)); Dv is the slot's row-major vector block (ld DVL).  Each wave
+    // takes 16-column tiles in turn and walks down them in 32-row steps: lane
+    // (c, g) feeds column c of the tile with rows 8 g .. 8 g + 7 of the step
+    // (16-byte loads where X allows them), the s-th product of a step taking
+    // row 8 g + s.  A finished tile goes through LDS: lane c < 16 then calls
+    // put(j0 + c, vals, nv) with vals[t] = out(j0 + c, t) (an LDS row).
+    template <int NT, typename Put>
+    __device__ void colmat(const double* X, long long ldx, int ncols, int nv, Put put) {
+        lds_double(*ct)[16][16 * 4 + 1] = reinterpret_cast<lds_double(*)[16][16 * 4 + 1]>(lx);
         const int m = p.m;
-        for (int i = tid; i < m; i += WG) {
-            const double* q = &Qat(0, i);
-            for (int t = 0; t < cnt; ++t) {
-                double sg;
-                const double* a = col_ptr(p, s.J[t], sg);
-                double acc = 0.0;
-                for (int l = 0; l < m; ++l) acc += q[l] * a[l];
-                p.G[(size_t)t * m + i] = sg * acc;
+        const double* __restrict__ D = p.Dv;
+        const bool al16 = ((((uintptr_t)X) & 15) == 0) && ((ldx & 1) == 0);
+        const int ntile = (ncols + 15) / 16, g = lane >> 4, cl = lane & 15;
+        for (int tile = wid; tile < ntile; tile += NW) {
+            const int j0 = tile * 16;
+            const double* xc = X + (size_t)min(j0 + cl, ncols - 1) * ldx;
+            wd4 acc[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = wd4{0.0, 0.0, 0.0, 0.0};
+            for (int r0 = 0; r0 < m; r0 += 32) {
+                const int rb = r0 + 8 * g;
+                double av[8];
+                if (r0 + 32 <= m && al16) {
+                    const double2* s2 = reinterpret_cast<const double2*>(xc + rb);
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const double2 x = s2[h];
+                        av[2 * h] = x.x;
+                        av[2 * h + 1] = x.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) av[u] = (rb + u < m) ? xc[rb + u] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    double bv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) bv[u] = (rb + u < m) ? D[(size_t)(rb + u) * DVL + 16 * t + cl] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc[t], 0, 0, 0);
+                }
             }
+            // lane l, register v: column 4 v + l / 16 of the tile, vector 16 t + l % 16
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ct[wid][4 * v + g][16 * t + cl] = acc[t][v];
+            wave_lds_sync();
+            if (lane < 16 && j0 + lane < ncols) put(j0 + lane, ct[wid][lane], nv);
+            wave_lds_sync();
         }
         __syncthreads();
+    }
+
+    template <typename Put>
+    __device__ void colmat_any(const double* X, long long ldx, int ncols, int nv, Put put) {
+        if (nv <= 16) colmat<1>(X, ldx, ncols, nv, put);
+        else if (nv <= 32) colmat<2>(X, ldx, ncols, nv, put);
+        else if (nv <= 48) colmat<3>(X, ldx, ncols, nv, put);
+        else colmat<4>(X, ldx, ncols, nv, put);
+    }
+
+    // G[:, t] = Q^T a_{J[t]} for t < cnt (full projection: rows < n_P are Q_P^T a,
+    // rows >= n_P the coordinates of the projected column in the trailing basis),
+    // as one product of the columns of Q with the gathered candidate columns.
+    __device__ void project(int cnt) {
+        const int m = p.m, nvp = (cnt + 15) & ~15;   // columns colmat reads
+        for (int e = tid; e < m * nvp; e += WG) {
+            const int i = e / nvp, t = e % nvp;
+            double v = 0.0;
+            if (t < cnt) {
+                double sg;
+                const double* a = col_ptr(p, s.J[t], sg);
+                v = sg * a[i];
+            }
+            p.Dv[(size_t)i * DVL + t] = v;
+        }
+        __syncthreads();
+        colmat_any(p.Q, m, m, cnt, [&](int i, const lds_double* c, int nv) {
+            for (int t = 0; t < nv; ++t) p.G[(size_t)t * m + i] = c[t];
+        });
     }
 
     // Gram matrix of the projected candidates G[n_P:m, 0:ncol] into T (ld kq).
@@ -544,15 +638,66 @@ struct Wg {
         __syncthreads();
     }
 
-    // a4: y = R^{-1} bt[0:n_P] (column-oriented back substitution).
+    // a4: y = R^{-1} bt[0:n_P], by blocks of TS rows from the bottom.  The
+    // diagonal block is staged in LDS with coalesced loads and scaled by its
+    // inverse diagonal; wave 0 back-substitutes it (lane i holds row i, entry
+    // j is broadcast from lane j through the scalar unit when step j reaches
+    // it); then every thread subtracts the block's contribution from its rows
+    // above, with the loads of all its rows for eight columns in flight.
+    static constexpr int TS = WG_TS;
+    static constexpr int TRPT = (YMAX + WG - 1) / WG;   // rows per thread above a block
     __device__ void trsv() {
+        lds_double(*Rd)[TS + 1] = reinterpret_cast<lds_double(*)[TS + 1]>(lx);
+        lds_int* sl = reinterpret_cast<lds_int*>(lx + TS * (TS + 1));
         const int nP = s.nP;
         for (int i = tid; i < nP; i += WG) s.c[i] = p.bt[i];
-        for (int j = nP - 1; j >= 0; --j) {
+        for (int r0 = ((nP - 1) / TS) * TS; r0 >= 0 && nP > 0; r0 -= TS) {
+            const int nr = min(nP, r0 + TS) - r0;
+            __syncthreads();   // rows >= r0 of c are final; Rd and sl are free
+            if (tid < TS) sl[tid] = p.slot[r0 + min(tid, nr - 1)];
             __syncthreads();
-            const double yj = s.c[j] / Rat(j, j);
-            if (tid == 0) yv[j] = yj;
-            for (int i = tid; i < j; i += WG) s.c[i] -= yj * Rat(i, j);
+            for (int e = tid; e < TS * TS; e += WG) {
+                const int j = e / TS, i = e % TS;   // consecutive threads: consecutive rows of a column
+                Rd[i][j] = (j < nr && i <= j) ? p.R[(size_t)sl[j] * p.kc + r0 + i] : 0.0;
+            }
+            __syncthreads();
+            if (wid == 0) {
+                const bool ok = lane < nr;
+                const double rinv = ok ? 1.0 / Rd[lane][lane] : 0.0;
+                for (int j = lane + 1; j < TS; ++j) Rd[lane][j] *= rinv;   // own row only
+                double v = ok ? s.c[r0 + lane] * rinv : 0.0;
+                wave_lds_sync();
+#pragma unroll 16
+                for (int j = TS - 1; j >= 0; --j) {
+                    const double yj = readlane_d(v, j);
+                    v = (lane < j) ? fma(-Rd[lane][j], yj, v) : v;
+                }
+                if (ok) yv[r0 + lane] = v;
+            }
+            __syncthreads();
+            double acc[TRPT];
+#pragma unroll
+            for (int u = 0; u < TRPT; ++u) acc[u] = 0.0;
+            for (int j0 = 0; j0 < nr; j0 += 8) {
+                double rv[TRPT][8];
+#pragma unroll
+                for (int u = 0; u < TRPT; ++u) {
+                    const int i = tid + u * WG;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        rv[u][k] = (i < r0 && j0 + k < nr) ? p.R[(size_t)sl[j0 + k] * p.kc + i] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < TRPT; ++u)
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (j0 + k < nr) acc[u] = fma(rv[u][k], yv[r0 + j0 + k], acc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < TRPT; ++u) {
+                const int i = tid + u * WG;
+                if (i < r0) s.c[i] -= acc[u];
+            }
         }
         __syncthreads();
     }
@@ -686,10 +831,109 @@ struct Wg {
         return true;
     }
 
+    // Algorithm 5 for a single removal (position first = rm[0]): every kept
+    // column after it carries one rotation, on the rows of its new and old
+    // positions, so rotation e acts on rows (first + e, first + e + 1).  Wave 0
+    // takes the kept columns in blocks of 64 (lane t: kept column 64 b + t).
+    // For each earlier block it applies that block's 64 rotations to the 65
+    // rows they touch, staged in an LDS window (one column per lane), with the
+    // running entry in a register; then it generates the block's own
+    // rotations in a chain along the lanes: rotation t is computed by lane t
+    // from its two entries and broadcast through the scalar unit, and every
+    // lane applies it (for the columns left of t those rows are below the
+    // diagonal, and the entry each lane's own rotation zeroes is stored as 0
+    // afterwards).  The rotations then go to bt and to the columns of Q (one
+    // thread per row, loads sixteen columns ahead).  Same rotations, in the
+    // same order, as the general sweep.
+    static constexpr int DB = WG_DB;
+    __device__ void downdate_unit() {
+        lds_double(*win)[DB] = reinterpret_cast<lds_double(*)[DB]>(lx);
+        lds_double* rot = lx + (DB + 1) * DB;   // (c, s) of rotation e at 2 e, 2 e + 1
+        const int nP = s.nP, first = p.rm[0], m = p.m;
+        const int nd = nP - 1 - first;
+        if (wid == 0 && nd > 0) {
+            const int nb = (nd + DB - 1) / DB;
+            for (int b = 0; b < nb; ++b) {
+                const int e = b * DB + lane;
+                const bool valid = e < nd;
+                double* col = p.R + (size_t)p.slot[first + 1 + (valid ? e : nd - 1)] * p.kc;
+                double run = 0.0;   // entry carried from one window to the next
+                for (int bb = 0; bb <= b; ++bb) {
+                    const int rlo = first + DB * bb;
+                    const int nw = min(DB, nd - DB * bb);   // rotations of block bb
+                    // the window's rows 1 .. nw (row 0 is the carried entry)
+                    for (int r = 1; r <= nw; ++r) win[r][lane] = col[rlo + r];
+                    if (bb == 0) run = col[rlo];
+                    wave_lds_sync();
+                    if (bb < b) {
+                        for (int k = 0; k < nw; ++k) {
+                            const double cs = rot[2 * (DB * bb + k)], sn = rot[2 * (DB * bb + k) + 1];
+                            const double y = win[k + 1][lane];
+                            win[k][lane] = cs * run + sn * y;
+                            run = -sn * run + cs * y;
+                        }
+                    } else {
+                        for (int k = 0; k < nw; ++k) {
+                            const double y = win[k + 1][lane];
+                            double cs, sn, rr;
+                            givens(run, y, cs, sn, rr);
+                            cs = readlane_d(cs, k);
+                            sn = readlane_d(sn, k);
+                            if (lane == 0) {
+                                rot[2 * (DB * bb + k)] = cs;
+                                rot[2 * (DB * bb + k) + 1] = sn;
+                            }
+                            wave_lds_sync();
+                            win[k][lane] = cs * run + sn * y;
+                            run = -sn * run + cs * y;
+                        }
+                    }
+                    win[nw][lane] = run;
+                    wave_lds_sync();
+                    if (valid) {
+                        const int top = (bb < b) ? nw - 1 : nw;   // the carried row goes to the next window
+                        for (int r = 0; r <= top; ++r) col[rlo + r] = win[r][lane];
+                        if (bb == b) col[rlo + lane + 1] = 0.0;   // the entry this lane's rotation zeroed
+                    }
+                    wave_lds_sync();
+                }
+            }
+        }
+        __syncthreads();   // rotations in rot, R updated
+        if (nd > 0) {
+            // bt and the columns of Q: row `row` of [Q; bt^T], running entry in a register
+            for (int row = tid; row <= m; row += WG) {
+                double* base = (row < m) ? p.Q + row : p.bt;
+                const size_t stride = (row < m) ? (size_t)m : 1;
+                double x = base[(size_t)first * stride];
+                for (int e0 = 0; e0 < nd; e0 += 16) {
+                    double y[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) y[u] = (e0 + u < nd) ? base[(size_t)(first + e0 + u + 1) * stride] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        if (e0 + u < nd) {
+                            const double cs = rot[2 * (e0 + u)], sn = rot[2 * (e0 + u) + 1];
+                            base[(size_t)(first + e0 + u) * stride] = cs * x + sn * y[u];
+                            x = -sn * x + cs * y[u];
+                        }
+                    }
+                }
+                base[(size_t)(first + nd) * stride] = x;
+            }
+        }
+        __syncthreads();
+        compact();
+    }
+
     // Algorithm 5: delete the passive positions p.rm[0..q) from R and restore the
     // triangle with Givens rotations, column by column, bottom-up within a
     // column; rotations are applied to R, bt and the columns of Q.
     __device__ void downdate() {
+        if (s.q == 1) {
+            downdate_unit();
+            return;
+        }
         const int q = s.q, nP = s.nP, m = p.m;
         const int first = p.rm[0];
         int ri = 0;
@@ -835,58 +1079,81 @@ struct Wg {
 
     // a7: w = A^T r and the update of u2 = ||Q_perp^T a_j||^2:
     //   u2 <- u2 - sum_added (q^T a)^2 + sum_dropped (q^T a)^2,
-    // or exactly from the trailing columns of Q when they are fewer.
+    // or exactly from the trailing columns of Q when they are fewer.  The vectors
+    // (r, then the added and dropped columns of Q, or the trailing ones) go
+    // through the matrix-core product DVL at a time, so A is read once per
+    // chunk instead of once per vector.
     __device__ void dual_and_norms(int kadd) {
         const int m = p.m, nph = p.nph, nP = s.nP, nPa = s.nPa;
         const int ndrop = nPa - nP;
         const bool exact = (m - nP) <= kadd + ndrop;
         const bool tw = nph != p.n;
-        for (int j = wid; j < nph; j += NW) {
-            const double* a = Acol(j);
-            double acc = 0.0;
-            for (int i = lane; i < m; i += 64) acc += a[i] * p.r[i];
-            const double wj = wave_sum(acc);
-            double u2;
-            if (exact) {
-                u2 = 0.0;
+        const int nvec = 1 + (exact ? m - nP : kadd + ndrop);
+        for (int c0 = 0; c0 < nvec; c0 += DVL) {
+            const int nv = min(DVL, nvec - c0), nvp = (nv + 15) & ~15;
+            for (int e = tid; e < m * nvp; e += WG) {
+                const int i = e / nvp, t = e % nvp, v = c0 + t;
+                double val = 0.0;
+                if (t < nv) {
+                    if (v == 0) val = p.r[i];
+                    else if (exact) val = Qat(i, nP + v - 1);
+                    else if (v <= kadd) val = p.Qadd[(size_t)(v - 1) * m + i];
+                    else val = Qat(i, nP + v - 1 - kadd);
+                }
+                p.Dv[(size_t)i * DVL + t] = val;
+            }
+            __syncthreads();
+            colmat_any(p.A, p.lda, nph, nv, [&](int j, const lds_double* c, int nvv) {
+                double u2;
+                int t = 0;
+                if (c0 == 0) {
+                    p.w[j] = c[0];
+                    if (tw) p.w[j + nph] = -c[0];
+                    u2 = exact ? 0.0 : p.u2[j];
+                    t = 1;
+                } else {
+                    u2 = p.u2[j];
+                }
+                for (; t < nvv; ++t) {
+                    const double d = c[t];
+                    if (exact || c0 + t > kadd) u2 += d * d;
+                    else u2 -= d * d;
+                }
+                p.u2[j] = u2;
+            });
+        }
+        // clamp; columns whose updated norm lost most of its digits are
+        // recomputed from the trailing columns of Q, one wave per column
+        for (int base = wid * 64; base < nph; base += WG) {
+            const int j = base + lane;
+            bool flag = false;
+            double u2 = 0.0;
+            if (j < nph) {
+                u2 = p.u2[j];
+                if (!exact) {
+                    u2 = fmax(u2, 0.0);
+                    flag = p.pos[j] < 0 && !twin_passive(p, j) && u2 < RECOMP_FRAC * p.an2[j];
+                }
+                if (!flag) {
+                    p.u2[j] = u2;
+                    if (tw) p.u2[j + nph] = u2;
+                }
+            }
+            unsigned long long mask = __ballot(flag);
+            while (mask) {
+                const int jj = base + __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                const double* a = Acol(jj);
+                double r2 = 0.0;
                 for (int t = nP; t < m; ++t) {
                     double d = 0.0;
                     for (int i = lane; i < m; i += 64) d += a[i] * Qat(i, t);
                     d = wave_sum(d);
-                    u2 += d * d;
+                    r2 += d * d;
                 }
-            } else {
-                u2 = p.u2[j];
-                for (int t = 0; t < kadd; ++t) {
-                    double d = 0.0;
-                    const double* qa = p.Qadd + (size_t)t * m;
-                    for (int i = lane; i < m; i += 64) d += a[i] * qa[i];
-                    d = wave_sum(d);
-                    u2 -= d * d;
-                }
-                for (int t = nP; t < nPa; ++t) {
-                    double d = 0.0;
-                    for (int i = lane; i < m; i += 64) d += a[i] * Qat(i, t);
-                    d = wave_sum(d);
-                    u2 += d * d;
-                }
-                u2 = fmax(u2, 0.0);
-                if (p.pos[j] < 0 && !twin_passive(p, j) && u2 < RECOMP_FRAC * p.an2[j]) {
-                    u2 = 0.0;
-                    for (int t = nP; t < m; ++t) {
-                        double d = 0.0;
-                        for (int i = lane; i < m; i += 64) d += a[i] * Qat(i, t);
-                        d = wave_sum(d);
-                        u2 += d * d;
-                    }
-                }
-            }
-            if (lane == 0) {
-                p.w[j] = wj;
-                p.u2[j] = u2;
-                if (tw) {
-                    p.w[j + nph] = -wj;
-                    p.u2[j + nph] = u2;
+                if (lane == 0) {
+                    p.u2[jj] = r2;
+                    if (tw) p.u2[jj + nph] = r2;
                 }
             }
         }
