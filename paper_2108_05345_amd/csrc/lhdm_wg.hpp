@@ -49,7 +49,8 @@ constexpr int WG_TS = 64;                          // triangular-solve block
 constexpr int WG_DB = 64;                          // downdate window
 constexpr int WG_LX = (WG_DB + 1) * WG_DB + 2 * YMAX;
 static_assert(WG_LX >= NW * 16 * 65, "colmat tile staging");
-static_assert(WG_LX >= WG_TS * (WG_TS + 1) + WG_TS, "triangular-solve block");
+static_assert(WG_LX >= WG_TS * (WG_TS + 1) + YMAX / 2, "triangular-solve block and slot indices");
+static_assert(WG_LX >= NW * KM * 17, "Q-update tiles");
 struct WgLds {
     WgShared sh;
     double x[WG_LX];
@@ -287,61 +288,80 @@ struct Wg {
     // (16-byte loads where X allows them), the s-th product of a step taking
     // row 8 g + s.  A finished tile goes through LDS: lane c < 16 then calls
     // put(j0 + c, vals, nv) with vals[t] = out(j0 + c, t) (an LDS row).
-    template <int NT, typename Put>
+    template <int NT, int TB, typename Put>
     __device__ void colmat(const double* X, long long ldx, int ncols, int nv, Put put) {
         lds_double(*ct)[16][16 * 4 + 1] = reinterpret_cast<lds_double(*)[16][16 * 4 + 1]>(lx);
         const int m = p.m;
         const double* __restrict__ D = p.Dv;
         const bool al16 = ((((uintptr_t)X) & 15) == 0) && ((ldx & 1) == 0);
         const int ntile = (ncols + 15) / 16, g = lane >> 4, cl = lane & 15;
-        for (int tile = wid; tile < ntile; tile += NW) {
-            const int j0 = tile * 16;
-            const double* xc = X + (size_t)min(j0 + cl, ncols - 1) * ldx;
-            wd4 acc[NT];
+        // TB tiles per wave at a time: they share the vector-block loads, and
+        // their column loads are in flight together
+        for (int tile = wid * TB; tile < ntile; tile += NW * TB) {
+            const double* xc[TB];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = wd4{0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < TB; ++b) xc[b] = X + (size_t)min((tile + b) * 16 + cl, ncols - 1) * ldx;
+            wd4 acc[TB][NT];
+#pragma unroll
+            for (int b = 0; b < TB; ++b)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[b][t] = wd4{0.0, 0.0, 0.0, 0.0};
             for (int r0 = 0; r0 < m; r0 += 32) {
                 const int rb = r0 + 8 * g;
-                double av[8];
+                double av[TB][8];
                 if (r0 + 32 <= m && al16) {
-                    const double2* s2 = reinterpret_cast<const double2*>(xc + rb);
 #pragma unroll
-                    for (int h = 0; h < 4; ++h) {
-                        const double2 x = s2[h];
-                        av[2 * h] = x.x;
-                        av[2 * h + 1] = x.y;
+                    for (int b = 0; b < TB; ++b) {
+                        const double2* s2 = reinterpret_cast<const double2*>(xc[b] + rb);
+#pragma unroll
+                        for (int h = 0; h < 4; ++h) {
+                            const double2 x = s2[h];
+                            av[b][2 * h] = x.x;
+                            av[b][2 * h + 1] = x.y;
+                        }
                     }
                 } else {
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) av[u] = (rb + u < m) ? xc[rb + u] : 0.0;
+                    for (int b = 0; b < TB; ++b)
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) av[b][u] = (rb + u < m) ? xc[b][rb + u] : 0.0;
                 }
+                double bv[NT][8];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    double bv[8];
+                for (int t = 0; t < NT; ++t)
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) bv[u] = (rb + u < m) ? D[(size_t)(rb + u) * DVL + 16 * t + cl] : 0.0;
+                    for (int u = 0; u < 8; ++u) bv[t][u] = (rb + u < m) ? D[(size_t)(rb + u) * DVL + 16 * t + cl] : 0.0;
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc[t], 0, 0, 0);
-                }
+                for (int b = 0; b < TB; ++b)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            acc[b][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[b][u], bv[t][u], acc[b][t], 0, 0, 0);
             }
-            // lane l, register v: column 4 v + l / 16 of the tile, vector 16 t + l % 16
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int b = 0; b < TB; ++b) {
+                const int j0 = (tile + b) * 16;
+                if (j0 >= ncols) break;
+                // lane l, register v: column 4 v + l / 16 of the tile, vector 16 t + l % 16
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ct[wid][4 * v + g][16 * t + cl] = acc[t][v];
-            wave_lds_sync();
-            if (lane < 16 && j0 + lane < ncols) put(j0 + lane, ct[wid][lane], nv);
-            wave_lds_sync();
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) ct[wid][4 * v + g][16 * t + cl] = acc[b][t][v];
+                wave_lds_sync();
+                if (lane < 16 && j0 + lane < ncols) put(j0 + lane, ct[wid][lane], nv);
+                wave_lds_sync();
+            }
         }
         __syncthreads();
     }
 
     template <typename Put>
     __device__ void colmat_any(const double* X, long long ldx, int ncols, int nv, Put put) {
-        if (nv <= 16) colmat<1>(X, ldx, ncols, nv, put);
-        else if (nv <= 32) colmat<2>(X, ldx, ncols, nv, put);
-        else if (nv <= 48) colmat<3>(X, ldx, ncols, nv, put);
-        else colmat<4>(X, ldx, ncols, nv, put);
+        if (nv <= 16) colmat<1, 4>(X, ldx, ncols, nv, put);
+        else if (nv <= 32) colmat<2, 2>(X, ldx, ncols, nv, put);
+        else if (nv <= 48) colmat<3, 2>(X, ldx, ncols, nv, put);
+        else colmat<4, 1>(X, ldx, ncols, nv, put);
     }
 
     // G[:, t] = Q^T a_{J[t]} for t < cnt (full projection: rows < n_P are Q_P^T a,
@@ -349,15 +369,24 @@ struct Wg {
     // as one product of the columns of Q with the gathered candidate columns.
     __device__ void project(int cnt) {
         const int m = p.m, nvp = (cnt + 15) & ~15;   // columns colmat reads
-        for (int e = tid; e < m * nvp; e += WG) {
-            const int i = e / nvp, t = e % nvp;
-            double v = 0.0;
-            if (t < cnt) {
-                double sg;
-                const double* a = col_ptr(p, s.J[t], sg);
-                v = sg * a[i];
+        // consecutive threads take consecutive rows of a column; eight loads in flight
+        for (int e0 = tid; e0 < m * nvp; e0 += WG * LB) {
+            double v[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int e = e0 + WG * u, t = e / m, i = e - t * m;
+                v[u] = 0.0;
+                if (e < m * nvp && t < cnt) {
+                    double sg;
+                    const double* a = col_ptr(p, s.J[t], sg);
+                    v[u] = sg * a[i];
+                }
             }
-            p.Dv[(size_t)i * DVL + t] = v;
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int e = e0 + WG * u, t = e / m, i = e - t * m;
+                if (e < m * nvp) p.Dv[(size_t)i * DVL + t] = v[u];
+            }
         }
         __syncthreads();
         colmat_any(p.Q, m, m, cnt, [&](int i, const lds_double* c, int nv) {
@@ -576,36 +605,144 @@ struct Wg {
         __syncthreads();
     }
 
-    // Q[:, n_P:m] <- Q[:, n_P:m] (I - V T V^T)  (rows of Q are independent).
-    __device__ void update_q() {
+    // Q[:, n_P:m] <- Q[:, n_P:m] (I - V T V^T) on the FP64 matrix cores.  Rows
+    // of Q are independent, so each wave owns 16-row tiles of Q in turn:
+    //   W^T  = V^T Q_t^T   (k x 16, K = the trailing columns, 32 at a time),
+    //   W2^T = T^T W^T     (T upper triangular),
+    //   Q_t^T -= V W2^T    (16 trailing columns of Q per product, K = k),
+    // with W^T and then W2^T in the wave's part of the LDS work area.
+    template <int NT>
+    __device__ void update_q_tiles() {
         const int m = p.m, k = s.kr, r0 = s.nP, kq = p.kq;
-        for (int i = tid; i < m; i += WG) {
-            double wrow[KM];
+        const int g = lane >> 4, cl = lane & 15;
+        lds_double* wt = lx + wid * (KM * 17);   // [KM][17]: row t = column t of W (16 rows of Q)
+        const int ntile = (m + 15) / 16;
+        for (int tile = wid; tile < ntile; tile += NW) {
+            const int i0 = tile * 16;
+            const int ic = min(i0 + cl, m - 1);
+            wd4 acc[NT];
 #pragma unroll
-            for (int t = 0; t < KM; ++t) wrow[t] = 0.0;
-            for (int l = r0; l < m; ++l) {
-                const double q = Qat(i, l);
+            for (int t = 0; t < NT; ++t) acc[t] = wd4{0.0, 0.0, 0.0, 0.0};
+            // W^T(t, i) = sum_l V(l, t) Q(i, l): lane (c, g) feeds V column 16 t + c and
+            // Q row i0 + c at rows l0 + 8 g .. l0 + 8 g + 7
+            // two 32-row steps per trip, all their loads before their products
+            for (int l0 = r0; l0 < m; l0 += 64) {
+                double bq[2][8], av[2][NT][8];
 #pragma unroll
-                for (int t = 0; t < KM; ++t)
-                    if (t < k) wrow[t] += q * p.V[(size_t)t * m + l];
+                for (int h = 0; h < 2; ++h) {
+                    const int lb = l0 + 32 * h + 8 * g;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) bq[h][u] = (lb + u < m) ? Qat(ic, lb + u) : 0.0;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const int tc = 16 * t + cl;
+                        const double* vc = p.V + (size_t)min(tc, k - 1) * m;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) av[h][t][u] = (tc < k && lb + u < m) ? vc[lb + u] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][t][u], bq[h][u], acc[t], 0, 0, 0);
             }
-            double w2[KM];
+            // result lane l, register v: W^T(16 t + 4 v + l / 16, i0 + l % 16)
 #pragma unroll
-            for (int t = 0; t < KM; ++t) {
-                double acc = 0.0;
-                if (t < k)
-                    for (int l = 0; l <= t; ++l) acc += wrow[l] * p.T[(size_t)t * kq + l];
-                w2[t] = acc;
-            }
-            for (int l = r0; l < m; ++l) {
-                double acc = 0.0;
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-                for (int t = 0; t < KM; ++t)
-                    if (t < k) acc += w2[t] * p.V[(size_t)t * m + l];
-                Qat(i, l) -= acc;
+                for (int v = 0; v < 4; ++v) wt[(16 * t + 4 * v + g) * 17 + cl] = acc[t][v];
+            wave_lds_sync();
+            // W2^T(t', i) = sum_{t <= t'} T(t, t') W^T(t, i); all operands loaded first
+            wd4 acc2[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc2[t] = wd4{0.0, 0.0, 0.0, 0.0};
+            {
+                double at[4 * NT][NT], bw[4 * NT];
+#pragma unroll
+                for (int ks = 0; ks < 4 * NT; ++ks) {
+                    const int kk = 4 * ks + g;
+                    bw[ks] = (kk < k) ? wt[kk * 17 + cl] : 0.0;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const int tc = 16 * t + cl;
+                        at[ks][t] = (kk < k && tc < k) ? p.T[(size_t)tc * kq + kk] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int ks = 0; ks < 4 * NT; ++ks)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(at[ks][t], bw[ks], acc2[t], 0, 0, 0);
             }
+            wave_lds_sync();
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) wt[(16 * t + 4 * v + g) * 17 + cl] = acc2[t][v];
+            wave_lds_sync();
+            // Q(i, l) -= sum_t V(l, t) W2^T(t, i), HQ 16-column tiles of Q at a time,
+            // every operand of a group loaded before its products
+            double bw[4 * NT];
+#pragma unroll
+            for (int ks = 0; ks < 4 * NT; ++ks) {
+                const int kk = 4 * ks + g;
+                bw[ks] = (kk < k) ? wt[kk * 17 + cl] : 0.0;
+            }
+            constexpr int HQ = NT <= 2 ? 4 : 2;
+            for (int l0 = r0; l0 < m; l0 += 16 * HQ) {
+                wd4 d[HQ];
+#pragma unroll
+                for (int h = 0; h < HQ; ++h) d[h] = wd4{0.0, 0.0, 0.0, 0.0};
+                // Q entries of the group first: lane l, register v of tile h holds
+                // (Q column l0 + 16 h + 4 v + l / 16, row i0 + l % 16)
+                double qv[HQ][4];
+#pragma unroll
+                for (int h = 0; h < HQ; ++h)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int l = l0 + 16 * h + 4 * v + g;
+                        qv[h][v] = (l < m && i0 + cl < m) ? Qat(i0 + cl, l) : 0.0;
+                    }
+                double av[4 * NT][HQ];
+#pragma unroll
+                for (int ks = 0; ks < 4 * NT; ++ks) {
+                    const int kk = 4 * ks + g;
+                    const double* vk = p.V + (size_t)min(kk, k - 1) * m;
+#pragma unroll
+                    for (int h = 0; h < HQ; ++h) {
+                        const int lc = l0 + 16 * h + cl;
+                        av[ks][h] = (kk < k && lc < m) ? vk[lc] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int ks = 0; ks < 4 * NT; ++ks)
+#pragma unroll
+                    for (int h = 0; h < HQ; ++h) d[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][h], bw[ks], d[h], 0, 0, 0);
+                // result lane l, register v: the same Q entry as qv[h][v]
+                if (i0 + cl < m) {
+#pragma unroll
+                    for (int h = 0; h < HQ; ++h)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int l = l0 + 16 * h + 4 * v + g;
+                            if (l < m) Qat(i0 + cl, l) = qv[h][v] - d[h][v];
+                        }
+                }
+            }
+            wave_lds_sync();   // wt is rewritten by the next tile
         }
         __syncthreads();
+    }
+
+    __device__ void update_q() {
+        const int k = s.kr;
+        if (k <= 16) update_q_tiles<1>();
+        else if (k <= 32) update_q_tiles<2>();
+        else if (k <= 48) update_q_tiles<3>();
+        else update_q_tiles<4>();
     }
 
     // a5: feasibility loop on J (Algorithm 3): keep the longest prefix of J whose
@@ -638,65 +775,57 @@ struct Wg {
         __syncthreads();
     }
 
-    // a4: y = R^{-1} bt[0:n_P], by blocks of TS rows from the bottom.  The
-    // diagonal block is staged in LDS with coalesced loads and scaled by its
-    // inverse diagonal; wave 0 back-substitutes it (lane i holds row i, entry
-    // j is broadcast from lane j through the scalar unit when step j reaches
-    // it); then every thread subtracts the block's contribution from its rows
-    // above, with the loads of all its rows for eight columns in flight.
+    // a4: y = R^{-1} bt[0:n_P], by blocks of TS rows from the bottom.  The slot
+    // indices of all passive positions are staged in LDS once.  The diagonal
+    // block is staged in LDS with coalesced loads; wave 0 takes its row,
+    // scaled by the inverse diagonal, into registers and back-substitutes
+    // (lane i holds row i, entry j is broadcast from lane j through the scalar
+    // unit when step j reaches it); then every thread subtracts the block's
+    // contribution from its rows above, with 32 columns' loads in flight.
     static constexpr int TS = WG_TS;
-    static constexpr int TRPT = (YMAX + WG - 1) / WG;   // rows per thread above a block
     __device__ void trsv() {
         lds_double(*Rd)[TS + 1] = reinterpret_cast<lds_double(*)[TS + 1]>(lx);
-        lds_int* sl = reinterpret_cast<lds_int*>(lx + TS * (TS + 1));
+        lds_int* sl = reinterpret_cast<lds_int*>(lx + TS * (TS + 1));   // slot of every position
         const int nP = s.nP;
-        for (int i = tid; i < nP; i += WG) s.c[i] = p.bt[i];
+        for (int i = tid; i < nP; i += WG) {
+            s.c[i] = p.bt[i];
+            sl[i] = p.slot[i];
+        }
         for (int r0 = ((nP - 1) / TS) * TS; r0 >= 0 && nP > 0; r0 -= TS) {
             const int nr = min(nP, r0 + TS) - r0;
-            __syncthreads();   // rows >= r0 of c are final; Rd and sl are free
-            if (tid < TS) sl[tid] = p.slot[r0 + min(tid, nr - 1)];
-            __syncthreads();
+            __syncthreads();   // rows >= r0 of c are final; Rd is free
             for (int e = tid; e < TS * TS; e += WG) {
                 const int j = e / TS, i = e % TS;   // consecutive threads: consecutive rows of a column
-                Rd[i][j] = (j < nr && i <= j) ? p.R[(size_t)sl[j] * p.kc + r0 + i] : 0.0;
+                Rd[i][j] = (j < nr && i <= j) ? p.R[(size_t)sl[r0 + j] * p.kc + r0 + i] : 0.0;
             }
             __syncthreads();
             if (wid == 0) {
                 const bool ok = lane < nr;
                 const double rinv = ok ? 1.0 / Rd[lane][lane] : 0.0;
-                for (int j = lane + 1; j < TS; ++j) Rd[lane][j] *= rinv;   // own row only
+                double row[TS];
+#pragma unroll
+                for (int j = 0; j < TS; ++j) row[j] = Rd[lane][j] * rinv;
                 double v = ok ? s.c[r0 + lane] * rinv : 0.0;
-                wave_lds_sync();
-#pragma unroll 16
+#pragma unroll
                 for (int j = TS - 1; j >= 0; --j) {
                     const double yj = readlane_d(v, j);
-                    v = (lane < j) ? fma(-Rd[lane][j], yj, v) : v;
+                    v = (lane < j) ? fma(-row[j], yj, v) : v;
                 }
                 if (ok) yv[r0 + lane] = v;
             }
             __syncthreads();
-            double acc[TRPT];
+            for (int i = tid; i < r0; i += WG) {
+                double acc = 0.0;
+                for (int j0 = 0; j0 < nr; j0 += 32) {
+                    double rv[32];
 #pragma unroll
-            for (int u = 0; u < TRPT; ++u) acc[u] = 0.0;
-            for (int j0 = 0; j0 < nr; j0 += 8) {
-                double rv[TRPT][8];
+                    for (int k = 0; k < 32; ++k)
+                        rv[k] = (j0 + k < nr) ? p.R[(size_t)sl[r0 + j0 + k] * p.kc + i] : 0.0;
 #pragma unroll
-                for (int u = 0; u < TRPT; ++u) {
-                    const int i = tid + u * WG;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        rv[u][k] = (i < r0 && j0 + k < nr) ? p.R[(size_t)sl[j0 + k] * p.kc + i] : 0.0;
+                    for (int k = 0; k < 32; ++k)
+                        if (j0 + k < nr) acc = fma(rv[k], yv[r0 + j0 + k], acc);
                 }
-#pragma unroll
-                for (int u = 0; u < TRPT; ++u)
-#pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        if (j0 + k < nr) acc[u] = fma(rv[u][k], yv[r0 + j0 + k], acc[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < TRPT; ++u) {
-                const int i = tid + u * WG;
-                if (i < r0) s.c[i] -= acc[u];
+                s.c[i] -= acc;
             }
         }
         __syncthreads();
@@ -861,8 +990,16 @@ struct Wg {
                 for (int bb = 0; bb <= b; ++bb) {
                     const int rlo = first + DB * bb;
                     const int nw = min(DB, nd - DB * bb);   // rotations of block bb
-                    // the window's rows 1 .. nw (row 0 is the carried entry)
-                    for (int r = 1; r <= nw; ++r) win[r][lane] = col[rlo + r];
+                    // the window's rows 1 .. nw (row 0 is the carried entry), sixteen
+                    // loads in flight per lane
+                    for (int r1 = 1; r1 <= nw; r1 += 16) {
+                        double t16[16];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) t16[u] = (r1 + u <= nw) ? col[rlo + r1 + u] : 0.0;
+#pragma unroll
+                        for (int u = 0; u < 16; ++u)
+                            if (r1 + u <= nw) win[r1 + u][lane] = t16[u];
+                    }
                     if (bb == 0) run = col[rlo];
                     wave_lds_sync();
                     if (bb < b) {
@@ -1062,15 +1199,26 @@ struct Wg {
         __syncthreads();
     }
 
-    // a7: r = b - A_P x_P
+    // a7: r = b - A_P x_P.  P is staged in LDS and each thread keeps sixteen
+    // columns' loads in flight; the sum still runs over the positions in order.
     __device__ void residual() {
         const int m = p.m, nP = s.nP;
+        lds_int* Pl = reinterpret_cast<lds_int*>(lx);
+        for (int c = tid; c < nP; c += WG) Pl[c] = p.P[c];
+        __syncthreads();
         for (int i = tid; i < m; i += WG) {
             double acc = p.b[i];
-            for (int c = 0; c < nP; ++c) {
-                double sg;
-                const double* a = col_ptr(p, p.P[c], sg);
-                acc -= (sg * a[i]) * yv[c];
+            for (int c0 = 0; c0 < nP; c0 += 16) {
+                double av[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    double sg;
+                    const double* a = col_ptr(p, Pl[min(c0 + u, nP - 1)], sg);
+                    av[u] = sg * a[i];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (c0 + u < nP) acc -= av[u] * yv[c0 + u];
             }
             p.r[i] = acc;
         }
@@ -1091,16 +1239,25 @@ struct Wg {
         const int nvec = 1 + (exact ? m - nP : kadd + ndrop);
         for (int c0 = 0; c0 < nvec; c0 += DVL) {
             const int nv = min(DVL, nvec - c0), nvp = (nv + 15) & ~15;
-            for (int e = tid; e < m * nvp; e += WG) {
-                const int i = e / nvp, t = e % nvp, v = c0 + t;
-                double val = 0.0;
-                if (t < nv) {
-                    if (v == 0) val = p.r[i];
-                    else if (exact) val = Qat(i, nP + v - 1);
-                    else if (v <= kadd) val = p.Qadd[(size_t)(v - 1) * m + i];
-                    else val = Qat(i, nP + v - 1 - kadd);
+            // consecutive threads take consecutive rows of a vector; eight loads in flight
+            for (int e0 = tid; e0 < m * nvp; e0 += WG * LB) {
+                double val[LB];
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const int e = e0 + WG * u, t = e / m, i = e - t * m, v = c0 + t;
+                    val[u] = 0.0;
+                    if (e < m * nvp && t < nv) {
+                        if (v == 0) val[u] = p.r[i];
+                        else if (exact) val[u] = Qat(i, nP + v - 1);
+                        else if (v <= kadd) val[u] = p.Qadd[(size_t)(v - 1) * m + i];
+                        else val[u] = Qat(i, nP + v - 1 - kadd);
+                    }
                 }
-                p.Dv[(size_t)i * DVL + t] = val;
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const int e = e0 + WG * u, t = e / m, i = e - t * m;
+                    if (e < m * nvp) p.Dv[(size_t)i * DVL + t] = val[u];
+                }
             }
             __syncthreads();
             colmat_any(p.A, p.lda, nph, nv, [&](int j, const lds_double* c, int nvv) {
