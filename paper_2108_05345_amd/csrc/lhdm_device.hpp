@@ -130,6 +130,55 @@ __host__ __device__ inline void carve_slot(Prob& p, char* base, int m, int n, in
     p.nph = n;
 }
 
+// Global-memory view of a buffer.  Loads and stores through it are global_*
+// instructions: the compiler tracks their completion one by one (a flat
+// instruction may also address LDS, so flat loads are waited for all at once)
+// and knows they cannot alias private copies of the instance descriptor, so
+// the hot loops hoist those fields and keep many loads in flight.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* x) {
+    return (__attribute__((address_space(1))) T*)x;
+}
+
+// The instance's buffers as global-memory views (see gmem).
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) int gint;
+struct GProb {
+    const gdouble* A;
+    const gdouble* b;
+    gdouble *x, *w, *Q, *R, *bt, *r, *u2, *an2, *G, *V, *W, *Qadd, *T, *rot, *Dv;
+    gint *passive, *P, *pos, *excl, *rm, *slot, *itmp;
+};
+
+__device__ inline GProb gview(const Prob& p) {
+    GProb g;
+    g.A = gmem(p.A);
+    g.b = gmem(p.b);
+    g.x = gmem(p.x);
+    g.w = gmem(p.w);
+    g.Q = gmem(p.Q);
+    g.R = gmem(p.R);
+    g.bt = gmem(p.bt);
+    g.r = gmem(p.r);
+    g.u2 = gmem(p.u2);
+    g.an2 = gmem(p.an2);
+    g.G = gmem(p.G);
+    g.V = gmem(p.V);
+    g.W = gmem(p.W);
+    g.Qadd = gmem(p.Qadd);
+    g.T = gmem(p.T);
+    g.rot = gmem(p.rot);
+    g.Dv = gmem(p.Dv);
+    g.passive = gmem(p.passive);
+    g.P = gmem(p.P);
+    g.pos = gmem(p.pos);
+    g.excl = gmem(p.excl);
+    g.rm = gmem(p.rm);
+    g.slot = gmem(p.slot);
+    g.itmp = gmem(p.itmp);
+    return g;
+}
+
 // Column j of the instance's matrix: the caller's column j or, in the
 // positivity-trick mode (n = 2 nph, Section 3.2), the caller's column j - nph
 // negated (sign -1) for j >= nph.

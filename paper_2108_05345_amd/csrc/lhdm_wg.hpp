@@ -34,6 +34,7 @@ struct WgShared : Ctl {
 };
 
 typedef double wd4 __attribute__((ext_vector_type(4)));
+typedef double wd2 __attribute__((ext_vector_type(2)));
 
 // LDS work area of the phases that stage tiles (triangular solve, downdate,
 // matrix-core products); the phases are separated by barriers, so one area
@@ -62,17 +63,18 @@ struct Wg {
     static constexpr int LB = 8;   // gathered loads issued together per thread
     Prob& p;
     const DevParams& prm;
-    WgShared& s;
+    __attribute__((address_space(3))) WgShared& s;   // LDS: ds_* instructions
     int tid, lane, wid;
     double* yv;   // least-squares solution by position: LDS (workgroup engine) or global
     lds_double* lx;   // LDS work area of trsv, downdate and colmat (WG_LX doubles)
+    GProb gp;         // the instance's buffers as global-memory views
 
     __device__ Wg(Prob& p_, const DevParams& prm_, WgShared& s_, lds_double* x_ = nullptr)
-        : p(p_), prm(prm_), s(s_), tid(threadIdx.x), lane(threadIdx.x & 63), wid(wave_index()),
-          yv(p_.ybuf ? p_.ybuf : s_.y), lx(x_) {}
+        : p(p_), prm(prm_), s(*(__attribute__((address_space(3))) WgShared*)&s_), tid(threadIdx.x), lane(threadIdx.x & 63), wid(wave_index()),
+          yv(p_.ybuf ? p_.ybuf : s_.y), lx(x_), gp(gview(p_)) {}
 
     // ---------------- workgroup reductions ----------------
-    __device__ double sum(double v) {
+    __device__ __forceinline__ double sum(double v) {
         v = wave_sum(v);
         __syncthreads();
         if (lane == 0) s.rd[wid] = v;
@@ -82,7 +84,7 @@ struct Wg {
         for (int i = 1; i < NW; ++i) t += s.rd[i];
         return t;
     }
-    __device__ double vmax(double v) {
+    __device__ __forceinline__ double vmax(double v) {
         v = wave_max(v);
         __syncthreads();
         if (lane == 0) s.rd[wid] = v;
@@ -92,7 +94,7 @@ struct Wg {
         for (int i = 1; i < NW; ++i) t = fmax(t, s.rd[i]);
         return t;
     }
-    __device__ double vmin(double v) {
+    __device__ __forceinline__ double vmin(double v) {
         v = wave_min(v);
         __syncthreads();
         if (lane == 0) s.rd[wid] = v;
@@ -102,7 +104,7 @@ struct Wg {
         for (int i = 1; i < NW; ++i) t = fmin(t, s.rd[i]);
         return t;
     }
-    __device__ int imax(int v) {
+    __device__ __forceinline__ int imax(int v) {
         v = wave_max_int(v);
         __syncthreads();
         if (lane == 0) s.ri[wid] = v;
@@ -112,7 +114,7 @@ struct Wg {
         for (int i = 1; i < NW; ++i) t = max(t, s.ri[i]);
         return t;
     }
-    __device__ void argmax(double& v, int& i) {
+    __device__ __forceinline__ void argmax(double& v, int& i) {
         wave_argmax(v, i);
         __syncthreads();
         if (lane == 0) {
@@ -131,11 +133,11 @@ struct Wg {
     }
     // Per-thread partial of dot product t is written by the caller into
     // s.mr via push(); finish(cnt) leaves the sums in s.vec[0..cnt).
-    __device__ void push(int t, double part) {
+    __device__ __forceinline__ void push(int t, double part) {
         part = wave_sum(part);
         if (lane == 0) s.mr[t][wid] = part;
     }
-    __device__ void finish(int cnt) {
+    __device__ __forceinline__ void finish(int cnt) {
         __syncthreads();
         if (tid < cnt) {
             double a = s.mr[tid][0];
@@ -146,40 +148,51 @@ struct Wg {
         __syncthreads();
     }
 
-    __device__ double& Qat(int i, int j) { return p.Q[(size_t)j * p.m + i]; }
-    __device__ double& Rat(int i, int j) { return p.R[(size_t)p.slot[j] * p.kc + i]; }
-    __device__ const double* Acol(int j) { return p.A + (size_t)j * p.lda; }
+    __device__ __forceinline__ gdouble& Qat(int i, int j) { return gp.Q[(size_t)j * p.m + i]; }
+    __device__ __forceinline__ gdouble& Rat(int i, int j) { return gp.R[(size_t)gp.slot[j] * p.kc + i]; }
+    __device__ __forceinline__ const gdouble* Acol(int j) { return gp.A + (size_t)j * p.lda; }
+    // column j of the instance's matrix and its sign (as col_ptr)
+    __device__ __forceinline__ const gdouble* gcol(int j, double& sign) {
+        if (j >= p.nph) {
+            sign = -1.0;
+            return gp.A + (size_t)(j - p.nph) * p.lda;
+        }
+        sign = 1.0;
+        return gp.A + (size_t)j * p.lda;
+    }
+    // twin of column j passive (positivity-trick mode only, as twin_passive)
+    __device__ __forceinline__ bool gtwin_passive(int j) { return p.n != p.nph && gp.pos[twin_of(p, j)] >= 0; }
 
     // ---------------- a0: initialisation (Algorithm 3, first lines) ----------------
-    __device__ void init() {
+    __device__ __forceinline__ void init() {
         const int m = p.m, nph = p.nph;
         double anmax = 0.0;
         int bad = 0;
         for (int j = wid; j < nph; j += NW) {
-            const double* a = Acol(j);
+            const gdouble* a = Acol(j);
             double ab = 0.0, aa = 0.0;
             for (int i = lane; i < m; i += 64) {
                 const double v = a[i];
-                ab += v * p.b[i];
+                ab += v * gp.b[i];
                 aa += v * v;
             }
             ab = wave_sum(ab);
             aa = wave_sum(aa);
             if (lane == 0) {
-                p.w[j] = ab;          // w^(0) = A^T b
-                p.an2[j] = aa;
-                p.u2[j] = aa;         // u^(0) = column norms of A
-                p.pos[j] = -1;
-                p.excl[j] = 0;
-                p.x[j] = 0.0;
+                gp.w[j] = ab;          // w^(0) = A^T b
+                gp.an2[j] = aa;
+                gp.u2[j] = aa;         // u^(0) = column norms of A
+                gp.pos[j] = -1;
+                gp.excl[j] = 0;
+                gp.x[j] = 0.0;
                 if (nph != p.n) {     // the twin -a_j of the positivity trick
                     const int t = j + nph;
-                    p.w[t] = -ab;
-                    p.an2[t] = aa;
-                    p.u2[t] = aa;
-                    p.pos[t] = -1;
-                    p.excl[t] = 0;
-                    p.x[t] = 0.0;
+                    gp.w[t] = -ab;
+                    gp.an2[t] = aa;
+                    gp.u2[t] = aa;
+                    gp.pos[t] = -1;
+                    gp.excl[t] = 0;
+                    gp.x[t] = 0.0;
                 }
             }
             if (!isfinite(ab) || !isfinite(aa)) bad = 1;
@@ -187,17 +200,17 @@ struct Wg {
         }
         double bb = 0.0;
         for (int i = tid; i < m; i += WG) {
-            const double v = p.b[i];
+            const double v = gp.b[i];
             bb += v * v;
-            p.bt[i] = v;
-            p.r[i] = v;
+            gp.bt[i] = v;
+            gp.r[i] = v;
         }
         bb = sum(bb);
         anmax = vmax(anmax);
         bad = imax(bad);
         const size_t mm = (size_t)m * m;
-        for (size_t e = tid; e < mm; e += WG) p.Q[e] = ((e % m) == (e / m)) ? 1.0 : 0.0;
-        for (int c = tid; c < p.kc; c += WG) p.slot[c] = c;
+        for (size_t e = tid; e < mm; e += WG) gp.Q[e] = ((e % m) == (e / m)) ? 1.0 : 0.0;
+        for (int c = tid; c < p.kc; c += WG) gp.slot[c] = c;
         if (tid == 0) {
             s.anmax = sqrt(anmax);
             s.bnorm = sqrt(bb);
@@ -213,17 +226,17 @@ struct Wg {
 
     // ---------------- a1 + a2: termination test and Deviation Maximization ----------------
     // Leaves s.done = 1 to stop (status set), else s.J[0..s.ncol) = [j1, candidates...].
-    __device__ void select() {
+    __device__ __forceinline__ void select() {
         const int n = p.n;
         double mwz = -INFINITY, mu = 0.0, bv = -INFINITY;
         int bi = INT_MAX;
         for (int j = tid; j < n; j += WG) {
-            if (p.pos[j] >= 0) continue;
-            const double wj = p.w[j];
-            const double u = sqrt(fmax(p.u2[j], 0.0));
+            if (gp.pos[j] >= 0) continue;
+            const double wj = gp.w[j];
+            const double u = sqrt(fmax(gp.u2[j], 0.0));
             mwz = fmax(mwz, wj);
             mu = fmax(mu, u);
-            if (!p.excl[j] && u > DEP_TOL * sqrt(p.an2[j]) && !twin_passive(p, j) && better(wj, j, bv, bi)) {
+            if (!gp.excl[j] && u > DEP_TOL * sqrt(gp.an2[j]) && !gtwin_passive(j) && better(wj, j, bv, bi)) {
                 bv = wj;
                 bi = j;
             }
@@ -257,11 +270,11 @@ struct Wg {
             double cv = -INFINITY;
             int ci = INT_MAX;
             for (int j = tid; j < n; j += WG) {
-                if (p.pos[j] >= 0 || p.excl[j] || j == bi) continue;
-                const double wj = p.w[j];
+                if (gp.pos[j] >= 0 || gp.excl[j] || j == bi) continue;
+                const double wj = gp.w[j];
                 if (!(wj >= tw)) continue;
-                const double u = sqrt(fmax(p.u2[j], 0.0));
-                if (!(u >= tu) || !(u > DEP_TOL * sqrt(p.an2[j])) || twin_passive(p, j)) continue;
+                const double u = sqrt(fmax(gp.u2[j], 0.0));
+                if (!(u >= tu) || !(u > DEP_TOL * sqrt(gp.an2[j])) || gtwin_passive(j)) continue;
                 if (!(wj < pv || (wj == pv && j > pi))) continue;   // strictly after the previous pick
                 if (better(wj, j, cv, ci)) {
                     cv = wj;
@@ -289,16 +302,16 @@ struct Wg {
     // row 8 g + s.  A finished tile goes through LDS: lane c < 16 then calls
     // put(j0 + c, vals, nv) with vals[t] = out(j0 + c, t) (an LDS row).
     template <int NT, int TB, typename Put>
-    __device__ void colmat(const double* X, long long ldx, int ncols, int nv, Put put) {
+    __device__ __forceinline__ void colmat(const gdouble* X, long long ldx, int ncols, int nv, Put put) {
         lds_double(*ct)[16][16 * 4 + 1] = reinterpret_cast<lds_double(*)[16][16 * 4 + 1]>(lx);
         const int m = p.m;
-        const double* __restrict__ D = p.Dv;
+        const gdouble* __restrict__ D = gp.Dv;
         const bool al16 = ((((uintptr_t)X) & 15) == 0) && ((ldx & 1) == 0);
         const int ntile = (ncols + 15) / 16, g = lane >> 4, cl = lane & 15;
         // TB tiles per wave at a time: they share the vector-block loads, and
         // their column loads are in flight together
         for (int tile = wid * TB; tile < ntile; tile += NW * TB) {
-            const double* xc[TB];
+            const gdouble* xc[TB];
 #pragma unroll
             for (int b = 0; b < TB; ++b) xc[b] = X + (size_t)min((tile + b) * 16 + cl, ncols - 1) * ldx;
             wd4 acc[TB][NT];
@@ -312,12 +325,13 @@ struct Wg {
                 if (r0 + 32 <= m && al16) {
 #pragma unroll
                     for (int b = 0; b < TB; ++b) {
-                        const double2* s2 = reinterpret_cast<const double2*>(xc[b] + rb);
+                        const __attribute__((address_space(1))) wd2* s2 =
+                            reinterpret_cast<const __attribute__((address_space(1))) wd2*>(xc[b] + rb);
 #pragma unroll
                         for (int h = 0; h < 4; ++h) {
-                            const double2 x = s2[h];
-                            av[b][2 * h] = x.x;
-                            av[b][2 * h + 1] = x.y;
+                            const wd2 x = s2[h];
+                            av[b][2 * h] = x[0];
+                            av[b][2 * h + 1] = x[1];
                         }
                     }
                 } else {
@@ -357,7 +371,7 @@ struct Wg {
     }
 
     template <typename Put>
-    __device__ void colmat_any(const double* X, long long ldx, int ncols, int nv, Put put) {
+    __device__ __forceinline__ void colmat_any(const gdouble* X, long long ldx, int ncols, int nv, Put put) {
         if (nv <= 16) colmat<1, 4>(X, ldx, ncols, nv, put);
         else if (nv <= 32) colmat<2, 2>(X, ldx, ncols, nv, put);
         else if (nv <= 48) colmat<3, 2>(X, ldx, ncols, nv, put);
@@ -367,7 +381,7 @@ struct Wg {
     // G[:, t] = Q^T a_{J[t]} for t < cnt (full projection: rows < n_P are Q_P^T a,
     // rows >= n_P the coordinates of the projected column in the trailing basis),
     // as one product of the columns of Q with the gathered candidate columns.
-    __device__ void project(int cnt) {
+    __device__ __forceinline__ void project(int cnt) {
         const int m = p.m, nvp = (cnt + 15) & ~15;   // columns colmat reads
         // consecutive threads take consecutive rows of a column; eight loads in flight
         for (int e0 = tid; e0 < m * nvp; e0 += WG * LB) {
@@ -378,24 +392,24 @@ struct Wg {
                 v[u] = 0.0;
                 if (e < m * nvp && t < cnt) {
                     double sg;
-                    const double* a = col_ptr(p, s.J[t], sg);
+                    const gdouble* a = gcol(s.J[t], sg);
                     v[u] = sg * a[i];
                 }
             }
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
                 const int e = e0 + WG * u, t = e / m, i = e - t * m;
-                if (e < m * nvp) p.Dv[(size_t)i * DVL + t] = v[u];
+                if (e < m * nvp) gp.Dv[(size_t)i * DVL + t] = v[u];
             }
         }
         __syncthreads();
-        colmat_any(p.Q, m, m, cnt, [&](int i, const lds_double* c, int nv) {
-            for (int t = 0; t < nv; ++t) p.G[(size_t)t * m + i] = c[t];
+        colmat_any(gp.Q, m, m, cnt, [&](int i, const lds_double* c, int nv) {
+            for (int t = 0; t < nv; ++t) gp.G[(size_t)t * m + i] = c[t];
         });
     }
 
     // Gram matrix of the projected candidates G[n_P:m, 0:ncol] into T (ld kq).
-    __device__ void candidate_gram() {
+    __device__ __forceinline__ void candidate_gram() {
         const int m = p.m, c = s.ncol, r0 = s.nP, kq = p.kq;
         const int npair = c * (c + 1) / 2;
         for (int pr = wid; pr < npair; pr += NW) {
@@ -405,14 +419,14 @@ struct Wg {
                 ++a;
             }
             const int bcol = rem;   // pair (a, bcol), bcol <= a
-            const double* ga = p.G + (size_t)a * m;
-            const double* gb = p.G + (size_t)bcol * m;
+            const gdouble* ga = gp.G + (size_t)a * m;
+            const gdouble* gb = gp.G + (size_t)bcol * m;
             double acc = 0.0;
             for (int i = r0 + lane; i < m; i += 64) acc += ga[i] * gb[i];
             acc = wave_sum(acc);
             if (lane == 0) {
-                p.T[(size_t)a * kq + bcol] = acc;
-                p.T[(size_t)bcol * kq + a] = acc;
+                gp.T[(size_t)a * kq + bcol] = acc;
+                gp.T[(size_t)bcol * kq + a] = acc;
             }
         }
         __syncthreads();
@@ -421,7 +435,7 @@ struct Wg {
     // Cosines of the projected candidates (eq. of the cosine matrix) from the
     // Gram matrix in T, and the greedy acceptance of Algorithm 2.  Compacts G
     // to the accepted columns.
-    __device__ void greedy_from_gram() {
+    __device__ __forceinline__ void greedy_from_gram() {
         const int m = p.m, c = s.ncol, kq = p.kq;
         if (tid == 0) {
             const int cap = p.m - s.nP;
@@ -430,11 +444,11 @@ struct Wg {
             acc[0] = 0;
             for (int t = 1; t < c; ++t) {
                 if (na >= cap) break;
-                const double nt = sqrt(p.T[(size_t)t * kq + t]);
+                const double nt = sqrt(gp.T[(size_t)t * kq + t]);
                 bool ok = true;
                 for (int q = 0; q < na; ++q) {
                     const int a = acc[q];
-                    const double th = p.T[(size_t)a * kq + t] / (nt * sqrt(p.T[(size_t)a * kq + a]));
+                    const double th = gp.T[(size_t)a * kq + t] / (nt * sqrt(gp.T[(size_t)a * kq + a]));
                     if (!(fabs(th) < prm.delta)) {
                         ok = false;
                         break;
@@ -454,12 +468,12 @@ struct Wg {
         for (int q = 1; q < k; ++q) {
             const int from = (int)s.vec[q];
             if (from != q)
-                for (int i = tid; i < m; i += WG) p.G[(size_t)q * m + i] = p.G[(size_t)from * m + i];
+                for (int i = tid; i < m; i += WG) gp.G[(size_t)q * m + i] = gp.G[(size_t)from * m + i];
             __syncthreads();
         }
     }
 
-    __device__ void deviation_maximization() {
+    __device__ __forceinline__ void deviation_maximization() {
         candidate_gram();
         greedy_from_gram();
     }
@@ -469,14 +483,14 @@ struct Wg {
     // s.beta the new diagonal of R, s.tau the reflector scalars.  Per column:
     // one pass for all dot products with the reflector, one pass for the update
     // that also accumulates the norm of the next column.
-    __device__ void panel_qr() {
+    __device__ __forceinline__ void panel_qr() {
         const int m = p.m, k = s.kr, r0 = s.nP;
         double part0 = 0.0;
-        for (int i = r0 + tid; i < m; i += WG) part0 += p.G[i] * p.G[i];
+        for (int i = r0 + tid; i < m; i += WG) part0 += gp.G[i] * gp.G[i];
         double nrm2 = sum(part0);
         for (int t = 0; t < k; ++t) {
             const int rt = r0 + t;
-            double* g = p.G + (size_t)t * m;
+            gdouble* g = gp.G + (size_t)t * m;
             const double x0 = g[rt];
             const double normx = sqrt(nrm2);
             double tau = 0.0, beta = x0, scal = 0.0;
@@ -505,7 +519,7 @@ struct Wg {
                     for (int qq = 0; qq < 16; ++qq) {
                         const int q = q0 + qq;
                         if (q < nrest) {
-                            const double* col = (q < nrest - 1) ? p.G + (size_t)(t + 1 + q) * m : p.bt;
+                            const gdouble* col = (q < nrest - 1) ? gp.G + (size_t)(t + 1 + q) * m : gp.bt;
                             pd[qq] += vi * col[i];
                         }
                     }
@@ -520,7 +534,7 @@ struct Wg {
             for (int i = rt + tid; i < m; i += WG) {
                 const double vi = g[i];
                 for (int q = 0; q < nrest; ++q) {
-                    double* col = (q < nrest - 1) ? p.G + (size_t)(t + 1 + q) * m : p.bt;
+                    gdouble* col = (q < nrest - 1) ? gp.G + (size_t)(t + 1 + q) * m : gp.bt;
                     const double nv = col[i] - (tau * s.vec[q]) * vi;
                     col[i] = nv;
                     if (q == 0 && i > rt && t + 1 < k) nn += nv * nv;
@@ -532,18 +546,18 @@ struct Wg {
     }
 
     // Explicit V (zeros above the unit diagonal, rows >= n_P).
-    __device__ void explicit_v() {
+    __device__ __forceinline__ void explicit_v() {
         const int m = p.m, k = s.kr, r0 = s.nP;
         for (int t = 0; t < k; ++t) {
-            const double* g = p.G + (size_t)t * m;
-            double* v = p.V + (size_t)t * m;
+            const gdouble* g = gp.G + (size_t)t * m;
+            gdouble* v = gp.V + (size_t)t * m;
             for (int i = tid; i < m; i += WG) v[i] = (i < r0 + t) ? 0.0 : g[i];
         }
         __syncthreads();
     }
 
     // V^T V, strictly upper part, into W (k x k, column-major ld kq).
-    __device__ void vtv() {
+    __device__ __forceinline__ void vtv() {
         const int m = p.m, k = s.kr, r0 = s.nP, kq = p.kq;
         const int npair = k * (k - 1) / 2;
         for (int pr = wid; pr < npair; pr += NW) {
@@ -553,26 +567,26 @@ struct Wg {
                 ++a;
             }
             const int b = rem;   // pair (b, a), b < a
-            const double* va = p.V + (size_t)a * m;
-            const double* vb = p.V + (size_t)b * m;
+            const gdouble* va = gp.V + (size_t)a * m;
+            const gdouble* vb = gp.V + (size_t)b * m;
             double acc = 0.0;
             for (int i = r0 + a + lane; i < m; i += 64) acc += vb[i] * va[i];
             acc = wave_sum(acc);
-            if (lane == 0) p.W[(size_t)a * kq + b] = acc;
+            if (lane == 0) gp.W[(size_t)a * kq + b] = acc;
         }
         __syncthreads();
     }
 
     // Compact-WY factor T with H_0 H_1 ... H_{k-1} = I - V T V^T (forward,
     // columnwise) from s.tau and V^T V in W.
-    __device__ void form_t() {
+    __device__ __forceinline__ void form_t() {
         const int k = s.kr, kq = p.kq;
         if (tid == 0) {
-            double* T = p.T;
+            gdouble* T = gp.T;
             for (int t = 0; t < k; ++t) {
                 T[(size_t)t * kq + t] = s.tau[t];
                 double z[KM];
-                for (int i = 0; i < t; ++i) z[i] = -s.tau[t] * p.W[(size_t)t * kq + i];
+                for (int i = 0; i < t; ++i) z[i] = -s.tau[t] * gp.W[(size_t)t * kq + i];
                 for (int i = 0; i < t; ++i) {
                     double acc = 0.0;
                     for (int l = i; l < t; ++l) acc += T[(size_t)l * kq + i] * z[l];
@@ -584,17 +598,17 @@ struct Wg {
         __syncthreads();
     }
 
-    __device__ void form_wy() {
+    __device__ __forceinline__ void form_wy() {
         explicit_v();
         vtv();
         form_t();
     }
 
     // New R columns: [Q_P^T a_J ; R_JJ].
-    __device__ void append_r() {
+    __device__ __forceinline__ void append_r() {
         const int m = p.m, k = s.kr, r0 = s.nP;
         for (int t = 0; t < k; ++t) {
-            const double* g = p.G + (size_t)t * m;
+            const gdouble* g = gp.G + (size_t)t * m;
             for (int i = tid; i < r0 + t + 1; i += WG) {
                 double v;
                 if (i < r0 + t) v = g[i];
@@ -612,9 +626,12 @@ struct Wg {
     //   Q_t^T -= V W2^T    (16 trailing columns of Q per product, K = k),
     // with W^T and then W2^T in the wave's part of the LDS work area.
     template <int NT>
-    __device__ void update_q_tiles() {
+    __device__ __forceinline__ void update_q_tiles() {
         const int m = p.m, k = s.kr, r0 = s.nP, kq = p.kq;
         const int g = lane >> 4, cl = lane & 15;
+        auto* __restrict__ Q = gmem(gp.Q);
+        const auto* __restrict__ V = gmem(gp.V);
+        const auto* __restrict__ T = gmem(gp.T);
         lds_double* wt = lx + wid * (KM * 17);   // [KM][17]: row t = column t of W (16 rows of Q)
         const int ntile = (m + 15) / 16;
         for (int tile = wid; tile < ntile; tile += NW) {
@@ -625,24 +642,25 @@ struct Wg {
             for (int t = 0; t < NT; ++t) acc[t] = wd4{0.0, 0.0, 0.0, 0.0};
             // W^T(t, i) = sum_l V(l, t) Q(i, l): lane (c, g) feeds V column 16 t + c and
             // Q row i0 + c at rows l0 + 8 g .. l0 + 8 g + 7
-            // two 32-row steps per trip, all their loads before their products
-            for (int l0 = r0; l0 < m; l0 += 64) {
-                double bq[2][8], av[2][NT][8];
+            // HS 32-row steps per trip, all their loads before their products
+            constexpr int HS = NT <= 2 ? 2 : 1;
+            for (int l0 = r0; l0 < m; l0 += 32 * HS) {
+                double bq[HS][8], av[HS][NT][8];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < HS; ++h) {
                     const int lb = l0 + 32 * h + 8 * g;
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) bq[h][u] = (lb + u < m) ? Qat(ic, lb + u) : 0.0;
+                    for (int u = 0; u < 8; ++u) bq[h][u] = (lb + u < m) ? Q[(size_t)(lb + u) * m + ic] : 0.0;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         const int tc = 16 * t + cl;
-                        const double* vc = p.V + (size_t)min(tc, k - 1) * m;
+                        const auto* vc = V + (size_t)min(tc, k - 1) * m;
 #pragma unroll
                         for (int u = 0; u < 8; ++u) av[h][t][u] = (tc < k && lb + u < m) ? vc[lb + u] : 0.0;
                     }
                 }
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                for (int h = 0; h < HS; ++h)
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -668,7 +686,7 @@ struct Wg {
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         const int tc = 16 * t + cl;
-                        at[ks][t] = (kk < k && tc < k) ? p.T[(size_t)tc * kq + kk] : 0.0;
+                        at[ks][t] = (kk < k && tc < k) ? T[(size_t)tc * kq + kk] : 0.0;
                     }
                 }
 #pragma unroll
@@ -704,13 +722,13 @@ struct Wg {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int l = l0 + 16 * h + 4 * v + g;
-                        qv[h][v] = (l < m && i0 + cl < m) ? Qat(i0 + cl, l) : 0.0;
+                        qv[h][v] = (l < m && i0 + cl < m) ? Q[(size_t)l * m + i0 + cl] : 0.0;
                     }
                 double av[4 * NT][HQ];
 #pragma unroll
                 for (int ks = 0; ks < 4 * NT; ++ks) {
                     const int kk = 4 * ks + g;
-                    const double* vk = p.V + (size_t)min(kk, k - 1) * m;
+                    const auto* vk = V + (size_t)min(kk, k - 1) * m;
 #pragma unroll
                     for (int h = 0; h < HQ; ++h) {
                         const int lc = l0 + 16 * h + cl;
@@ -728,7 +746,7 @@ struct Wg {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int l = l0 + 16 * h + 4 * v + g;
-                            if (l < m) Qat(i0 + cl, l) = qv[h][v] - d[h][v];
+                            if (l < m) Q[(size_t)l * m + i0 + cl] = qv[h][v] - d[h][v];
                         }
                 }
             }
@@ -737,7 +755,7 @@ struct Wg {
         __syncthreads();
     }
 
-    __device__ void update_q() {
+    __device__ __forceinline__ void update_q() {
         const int k = s.kr;
         if (k <= 16) update_q_tiles<1>();
         else if (k <= 32) update_q_tiles<2>();
@@ -747,7 +765,7 @@ struct Wg {
 
     // a5: feasibility loop on J (Algorithm 3): keep the longest prefix of J whose
     // own least-squares components are all positive.
-    __device__ void jloop() {
+    __device__ __forceinline__ void jloop() {
         if (prm.nojloop) {   // Theorem 4: the block is taken whole
             if (tid == 0) s.k = s.kr;
             __syncthreads();
@@ -758,7 +776,7 @@ struct Wg {
             int k = s.kr;
             while (k > 0) {
                 double yy[KM];
-                for (int i = 0; i < k; ++i) yy[i] = p.bt[r0 + i];
+                for (int i = 0; i < k; ++i) yy[i] = gp.bt[r0 + i];
                 double mn = INFINITY;
                 for (int j = k - 1; j >= 0; --j) {
                     const double yj = yy[j] / Rat(r0 + j, r0 + j);
@@ -783,20 +801,20 @@ struct Wg {
     // unit when step j reaches it); then every thread subtracts the block's
     // contribution from its rows above, with 32 columns' loads in flight.
     static constexpr int TS = WG_TS;
-    __device__ void trsv() {
+    __device__ __forceinline__ void trsv() {
         lds_double(*Rd)[TS + 1] = reinterpret_cast<lds_double(*)[TS + 1]>(lx);
         lds_int* sl = reinterpret_cast<lds_int*>(lx + TS * (TS + 1));   // slot of every position
         const int nP = s.nP;
         for (int i = tid; i < nP; i += WG) {
-            s.c[i] = p.bt[i];
-            sl[i] = p.slot[i];
+            s.c[i] = gp.bt[i];
+            sl[i] = gp.slot[i];
         }
         for (int r0 = ((nP - 1) / TS) * TS; r0 >= 0 && nP > 0; r0 -= TS) {
             const int nr = min(nP, r0 + TS) - r0;
             __syncthreads();   // rows >= r0 of c are final; Rd is free
             for (int e = tid; e < TS * TS; e += WG) {
                 const int j = e / TS, i = e % TS;   // consecutive threads: consecutive rows of a column
-                Rd[i][j] = (j < nr && i <= j) ? p.R[(size_t)sl[r0 + j] * p.kc + r0 + i] : 0.0;
+                Rd[i][j] = (j < nr && i <= j) ? gp.R[(size_t)sl[r0 + j] * p.kc + r0 + i] : 0.0;
             }
             __syncthreads();
             if (wid == 0) {
@@ -820,7 +838,7 @@ struct Wg {
                     double rv[32];
 #pragma unroll
                     for (int k = 0; k < 32; ++k)
-                        rv[k] = (j0 + k < nr) ? p.R[(size_t)sl[r0 + j0 + k] * p.kc + i] : 0.0;
+                        rv[k] = (j0 + k < nr) ? gp.R[(size_t)sl[r0 + j0 + k] * p.kc + i] : 0.0;
 #pragma unroll
                     for (int k = 0; k < 32; ++k)
                         if (j0 + k < nr) acc = fma(rv[k], yv[r0 + j0 + k], acc);
@@ -832,15 +850,15 @@ struct Wg {
     }
 
     // a6: one inner iteration: step length, new iterate, removal set.  Leaves
-    // the ascending removal positions in p.rm[0..s.q).
-    __device__ void inner_step() {
+    // the ascending removal positions in gp.rm[0..s.q).
+    __device__ __forceinline__ void inner_step() {
 #pragma clang fp contract(off)
         const int nP = s.nP;
         double al = INFINITY;
         for (int c = tid; c < nP; c += WG) {
             const double yc = yv[c];
             if (yc <= 0.0) {
-                const double xc = p.x[p.P[c]];
+                const double xc = gp.x[gp.P[c]];
                 al = fmin(al, step_ratio(xc, yc));
             }
         }
@@ -856,33 +874,33 @@ struct Wg {
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
                 const int c = min(cb + u, c1 - 1);
-                j[u] = p.P[c];
+                j[u] = gp.P[c];
                 yc[u] = yv[c];
             }
 #pragma unroll
-            for (int u = 0; u < LB; ++u) xc[u] = p.x[j[u]];
+            for (int u = 0; u < LB; ++u) xc[u] = gp.x[j[u]];
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
                 if (cb + u < c1) {
                     double xn = xc[u] + al * (yc[u] - xc[u]);
                     if (yc[u] <= 0.0 && step_ratio(xc[u], yc[u]) == al) xn = 0.0;
                     if (xn <= 0.0) xn = 0.0;
-                    p.x[j[u]] = xn;
+                    gp.x[j[u]] = xn;
                 }
             }
         }
         collect_removals();
     }
 
-    // p.rm[0..s.q) = ascending passive positions whose x is <= 0.
-    __device__ void collect_removals() {
-        collect_positions([&](int c, int j) { return p.x[j] <= 0.0; });
+    // gp.rm[0..s.q) = ascending passive positions whose x is <= 0.
+    __device__ __forceinline__ void collect_removals() {
+        collect_positions([&](int c, int j) { return gp.x[j] <= 0.0; });
     }
 
-    // p.rm[0..s.q) = ascending passive positions c (column j = P[c]) for which
+    // gp.rm[0..s.q) = ascending passive positions c (column j = P[c]) for which
     // pick(c, j) holds.
     template <typename Pick>
-    __device__ void collect_positions(Pick pick) {
+    __device__ __forceinline__ void collect_positions(Pick pick) {
         const int nP = s.nP;
         const int chunk = (nP + WG - 1) / WG;
         const int c0 = tid * chunk, c1 = min(nP, c0 + chunk);
@@ -893,7 +911,7 @@ struct Wg {
         for (int cb = c0; cb < c1; cb += LB) {
             int j[LB];
 #pragma unroll
-            for (int u = 0; u < LB; ++u) j[u] = p.P[min(cb + u, c1 - 1)];
+            for (int u = 0; u < LB; ++u) j[u] = gp.P[min(cb + u, c1 - 1)];
             bool hit[LB];
 #pragma unroll
             for (int u = 0; u < LB; ++u) hit[u] = pick(min(cb + u, c1 - 1), j[u]);
@@ -920,12 +938,12 @@ struct Wg {
         if (tid == WG - 1) s.q = o + mine;
         if (chunk <= 64) {
             while (mask) {
-                p.rm[o++] = c0 + __builtin_ctzll(mask);
+                gp.rm[o++] = c0 + __builtin_ctzll(mask);
                 mask &= mask - 1;
             }
         } else {
             for (int c = c0; c < c1; ++c)
-                if (pick(c, p.P[c])) p.rm[o++] = c;
+                if (pick(c, gp.P[c])) gp.rm[o++] = c;
         }
         __syncthreads();
     }
@@ -936,7 +954,7 @@ struct Wg {
     // component is -y > 0; the residual is unchanged, so the inner loop ends.
     // Returns false, changing nothing, when a component is exactly 0 (the
     // ordinary inner iteration then runs).
-    __device__ bool sign_flip() {
+    __device__ __forceinline__ bool sign_flip() {
         const int nP = s.nP;
         int zero = 0;
         for (int c = tid; c < nP; c += WG) zero |= (yv[c] == 0.0) ? 1 : 0;
@@ -944,16 +962,16 @@ struct Wg {
         collect_positions([&](int c, int j) { return yv[c] < 0.0; });
         const int q = s.q;
         for (int t = 0; t < q; ++t) {
-            const int c = p.rm[t];
-            double* col = p.R + (size_t)p.slot[c] * p.kc;
+            const int c = gp.rm[t];
+            gdouble* col = gp.R + (size_t)gp.slot[c] * p.kc;
             for (int i = tid; i <= c; i += WG) col[i] = -col[i];
         }
         for (int t = tid; t < q; t += WG) {
-            const int c = p.rm[t], j = p.P[c], tw = twin_of(p, j);
-            p.P[c] = tw;
-            p.pos[j] = -1;
-            p.pos[tw] = c;
-            p.x[j] = 0.0;
+            const int c = gp.rm[t], j = gp.P[c], tw = twin_of(p, j);
+            gp.P[c] = tw;
+            gp.pos[j] = -1;
+            gp.pos[tw] = c;
+            gp.x[j] = 0.0;
             yv[c] = -yv[c];
         }
         __syncthreads();
@@ -975,17 +993,17 @@ struct Wg {
     // thread per row, loads sixteen columns ahead).  Same rotations, in the
     // same order, as the general sweep.
     static constexpr int DB = WG_DB;
-    __device__ void downdate_unit() {
+    __device__ __forceinline__ void downdate_unit() {
         lds_double(*win)[DB] = reinterpret_cast<lds_double(*)[DB]>(lx);
         lds_double* rot = lx + (DB + 1) * DB;   // (c, s) of rotation e at 2 e, 2 e + 1
-        const int nP = s.nP, first = p.rm[0], m = p.m;
+        const int nP = s.nP, first = gp.rm[0], m = p.m;
         const int nd = nP - 1 - first;
         if (wid == 0 && nd > 0) {
             const int nb = (nd + DB - 1) / DB;
             for (int b = 0; b < nb; ++b) {
                 const int e = b * DB + lane;
                 const bool valid = e < nd;
-                double* col = p.R + (size_t)p.slot[first + 1 + (valid ? e : nd - 1)] * p.kc;
+                gdouble* col = gp.R + (size_t)gp.slot[first + 1 + (valid ? e : nd - 1)] * p.kc;
                 double run = 0.0;   // entry carried from one window to the next
                 for (int bb = 0; bb <= b; ++bb) {
                     const int rlo = first + DB * bb;
@@ -1040,7 +1058,7 @@ struct Wg {
         if (nd > 0) {
             // bt and the columns of Q: row `row` of [Q; bt^T], running entry in a register
             for (int row = tid; row <= m; row += WG) {
-                double* base = (row < m) ? p.Q + row : p.bt;
+                gdouble* base = (row < m) ? gp.Q + row : gp.bt;
                 const size_t stride = (row < m) ? (size_t)m : 1;
                 double x = base[(size_t)first * stride];
                 for (int e0 = 0; e0 < nd; e0 += 16) {
@@ -1063,19 +1081,19 @@ struct Wg {
         compact();
     }
 
-    // Algorithm 5: delete the passive positions p.rm[0..q) from R and restore the
+    // Algorithm 5: delete the passive positions gp.rm[0..q) from R and restore the
     // triangle with Givens rotations, column by column, bottom-up within a
     // column; rotations are applied to R, bt and the columns of Q.
-    __device__ void downdate() {
+    __device__ __forceinline__ void downdate() {
         if (s.q == 1) {
             downdate_unit();
             return;
         }
         const int q = s.q, nP = s.nP, m = p.m;
-        const int first = p.rm[0];
+        const int first = gp.rm[0];
         int ri = 0;
         for (int oc = first; oc < nP; ++oc) {
-            if (ri < q && p.rm[ri] == oc) {
+            if (ri < q && gp.rm[ri] == oc) {
                 ++ri;
                 continue;
             }
@@ -1088,8 +1106,8 @@ struct Wg {
                     givens(a, bb, cs, sn, rr);
                     Rat(i - 1, oc) = cs * a + sn * bb;
                     Rat(i, oc) = 0.0;
-                    p.rot[2 * g] = cs;
-                    p.rot[2 * g + 1] = sn;
+                    gp.rot[2 * g] = cs;
+                    gp.rot[2 * g + 1] = sn;
                 }
             }
             __syncthreads();
@@ -1100,15 +1118,15 @@ struct Wg {
                     // is oc2 deleted?  (rm is ascending; scan from ri)
                     bool del = false;
                     for (int t = rj; t < q; ++t) {
-                        if (p.rm[t] == oc2) {
+                        if (gp.rm[t] == oc2) {
                             del = true;
                             break;
                         }
-                        if (p.rm[t] > oc2) break;
+                        if (gp.rm[t] > oc2) break;
                     }
                     if (del) continue;
                     for (int i = oc, g = 0; i > c; --i, ++g) {
-                        const double cs = p.rot[2 * g], sn = p.rot[2 * g + 1];
+                        const double cs = gp.rot[2 * g], sn = gp.rot[2 * g + 1];
                         const double a = Rat(i - 1, oc2), bb = Rat(i, oc2);
                         Rat(i - 1, oc2) = cs * a + sn * bb;
                         Rat(i, oc2) = -sn * a + cs * bb;
@@ -1117,15 +1135,15 @@ struct Wg {
             }
             if (tid == 0) {
                 for (int i = oc, g = 0; i > c; --i, ++g) {
-                    const double cs = p.rot[2 * g], sn = p.rot[2 * g + 1];
-                    const double a = p.bt[i - 1], bb = p.bt[i];
-                    p.bt[i - 1] = cs * a + sn * bb;
-                    p.bt[i] = -sn * a + cs * bb;
+                    const double cs = gp.rot[2 * g], sn = gp.rot[2 * g + 1];
+                    const double a = gp.bt[i - 1], bb = gp.bt[i];
+                    gp.bt[i - 1] = cs * a + sn * bb;
+                    gp.bt[i] = -sn * a + cs * bb;
                 }
             }
             for (int row = tid; row < m; row += WG) {
                 for (int i = oc, g = 0; i > c; --i, ++g) {
-                    const double cs = p.rot[2 * g], sn = p.rot[2 * g + 1];
+                    const double cs = gp.rot[2 * g], sn = gp.rot[2 * g + 1];
                     const double a = Qat(row, i - 1), bb = Qat(row, i);
                     Qat(row, i - 1) = cs * a + sn * bb;
                     Qat(row, i) = -sn * a + cs * bb;
@@ -1139,11 +1157,11 @@ struct Wg {
     // Drop the removed positions from P; their R slots move behind the kept ones
     // (slot stays a permutation, free slots at [n_P, kc)).  Kept position c
     // moves to c - #{removed < c}; the t-th removed slot goes to n_P - q + t.
-    __device__ void compact() {
+    __device__ __forceinline__ void compact() {
         const int q = s.q, nP = s.nP;
         if (q == 0) return;
-        int* oldP = p.itmp;
-        int* oldS = p.itmp + p.kc;
+        gint* oldP = gp.itmp;
+        gint* oldS = gp.itmp + p.kc;
         // the int arrays may alias as far as the compiler knows: each batch's
         // loads go out before its stores, instead of one round trip per position
         for (int c0 = tid; c0 < nP; c0 += WG * LB) {
@@ -1151,8 +1169,8 @@ struct Wg {
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
                 const int c = min(c0 + WG * u, nP - 1);
-                pv[u] = p.P[c];
-                sv[u] = p.slot[c];
+                pv[u] = gp.P[c];
+                sv[u] = gp.slot[c];
             }
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
@@ -1179,18 +1197,18 @@ struct Wg {
                 int lo = 0, hi = q;
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if (p.rm[mid] < c) lo = mid + 1;
+                    if (gp.rm[mid] < c) lo = mid + 1;
                     else hi = mid;
                 }
                 const int j = pv[u];
-                if (lo < q && p.rm[lo] == c) {
-                    p.pos[j] = -1;
-                    p.slot[nP - q + lo] = sv[u];
+                if (lo < q && gp.rm[lo] == c) {
+                    gp.pos[j] = -1;
+                    gp.slot[nP - q + lo] = sv[u];
                 } else {
                     const int w = c - lo;
-                    p.P[w] = j;
-                    p.slot[w] = sv[u];
-                    p.pos[j] = w;
+                    gp.P[w] = j;
+                    gp.slot[w] = sv[u];
+                    gp.pos[j] = w;
                 }
             }
         }
@@ -1201,26 +1219,26 @@ struct Wg {
 
     // a7: r = b - A_P x_P.  P is staged in LDS and each thread keeps sixteen
     // columns' loads in flight; the sum still runs over the positions in order.
-    __device__ void residual() {
+    __device__ __forceinline__ void residual() {
         const int m = p.m, nP = s.nP;
         lds_int* Pl = reinterpret_cast<lds_int*>(lx);
-        for (int c = tid; c < nP; c += WG) Pl[c] = p.P[c];
+        for (int c = tid; c < nP; c += WG) Pl[c] = gp.P[c];
         __syncthreads();
         for (int i = tid; i < m; i += WG) {
-            double acc = p.b[i];
+            double acc = gp.b[i];
             for (int c0 = 0; c0 < nP; c0 += 16) {
                 double av[16];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     double sg;
-                    const double* a = col_ptr(p, Pl[min(c0 + u, nP - 1)], sg);
+                    const gdouble* a = gcol(Pl[min(c0 + u, nP - 1)], sg);
                     av[u] = sg * a[i];
                 }
 #pragma unroll
                 for (int u = 0; u < 16; ++u)
                     if (c0 + u < nP) acc -= av[u] * yv[c0 + u];
             }
-            p.r[i] = acc;
+            gp.r[i] = acc;
         }
         __syncthreads();
     }
@@ -1231,7 +1249,7 @@ struct Wg {
     // (r, then the added and dropped columns of Q, or the trailing ones) go
     // through the matrix-core product DVL at a time, so A is read once per
     // chunk instead of once per vector.
-    __device__ void dual_and_norms(int kadd) {
+    __device__ __forceinline__ void dual_and_norms(int kadd) {
         const int m = p.m, nph = p.nph, nP = s.nP, nPa = s.nPa;
         const int ndrop = nPa - nP;
         const bool exact = (m - nP) <= kadd + ndrop;
@@ -1247,36 +1265,36 @@ struct Wg {
                     const int e = e0 + WG * u, t = e / m, i = e - t * m, v = c0 + t;
                     val[u] = 0.0;
                     if (e < m * nvp && t < nv) {
-                        if (v == 0) val[u] = p.r[i];
+                        if (v == 0) val[u] = gp.r[i];
                         else if (exact) val[u] = Qat(i, nP + v - 1);
-                        else if (v <= kadd) val[u] = p.Qadd[(size_t)(v - 1) * m + i];
+                        else if (v <= kadd) val[u] = gp.Qadd[(size_t)(v - 1) * m + i];
                         else val[u] = Qat(i, nP + v - 1 - kadd);
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < LB; ++u) {
                     const int e = e0 + WG * u, t = e / m, i = e - t * m;
-                    if (e < m * nvp) p.Dv[(size_t)i * DVL + t] = val[u];
+                    if (e < m * nvp) gp.Dv[(size_t)i * DVL + t] = val[u];
                 }
             }
             __syncthreads();
-            colmat_any(p.A, p.lda, nph, nv, [&](int j, const lds_double* c, int nvv) {
+            colmat_any(gp.A, p.lda, nph, nv, [&](int j, const lds_double* c, int nvv) {
                 double u2;
                 int t = 0;
                 if (c0 == 0) {
-                    p.w[j] = c[0];
-                    if (tw) p.w[j + nph] = -c[0];
-                    u2 = exact ? 0.0 : p.u2[j];
+                    gp.w[j] = c[0];
+                    if (tw) gp.w[j + nph] = -c[0];
+                    u2 = exact ? 0.0 : gp.u2[j];
                     t = 1;
                 } else {
-                    u2 = p.u2[j];
+                    u2 = gp.u2[j];
                 }
                 for (; t < nvv; ++t) {
                     const double d = c[t];
                     if (exact || c0 + t > kadd) u2 += d * d;
                     else u2 -= d * d;
                 }
-                p.u2[j] = u2;
+                gp.u2[j] = u2;
             });
         }
         // clamp; columns whose updated norm lost most of its digits are
@@ -1286,21 +1304,21 @@ struct Wg {
             bool flag = false;
             double u2 = 0.0;
             if (j < nph) {
-                u2 = p.u2[j];
+                u2 = gp.u2[j];
                 if (!exact) {
                     u2 = fmax(u2, 0.0);
-                    flag = p.pos[j] < 0 && !twin_passive(p, j) && u2 < RECOMP_FRAC * p.an2[j];
+                    flag = gp.pos[j] < 0 && !gtwin_passive(j) && u2 < RECOMP_FRAC * gp.an2[j];
                 }
                 if (!flag) {
-                    p.u2[j] = u2;
-                    if (tw) p.u2[j + nph] = u2;
+                    gp.u2[j] = u2;
+                    if (tw) gp.u2[j + nph] = u2;
                 }
             }
             unsigned long long mask = __ballot(flag);
             while (mask) {
                 const int jj = base + __ffsll((long long)mask) - 1;
                 mask &= mask - 1;
-                const double* a = Acol(jj);
+                const gdouble* a = Acol(jj);
                 double r2 = 0.0;
                 for (int t = nP; t < m; ++t) {
                     double d = 0.0;
@@ -1309,8 +1327,8 @@ struct Wg {
                     r2 += d * d;
                 }
                 if (lane == 0) {
-                    p.u2[jj] = r2;
-                    if (tw) p.u2[jj + nph] = r2;
+                    gp.u2[jj] = r2;
+                    if (tw) gp.u2[jj + nph] = r2;
                 }
             }
         }
@@ -1318,45 +1336,45 @@ struct Wg {
     }
 
     // r and w for the current x (used when the loop stops inside an inner loop)
-    __device__ void refresh_dual() {
+    __device__ __forceinline__ void refresh_dual() {
         const int m = p.m, nph = p.nph;
         for (int i = tid; i < m; i += WG) {
-            double acc = p.b[i];
+            double acc = gp.b[i];
             for (int c = 0; c < s.nP; ++c) {
-                const int j = p.P[c];
+                const int j = gp.P[c];
                 double sg;
-                const double* a = col_ptr(p, j, sg);
-                acc -= (sg * a[i]) * p.x[j];
+                const gdouble* a = gcol(j, sg);
+                acc -= (sg * a[i]) * gp.x[j];
             }
-            p.r[i] = acc;
+            gp.r[i] = acc;
         }
         __syncthreads();
         for (int j = wid; j < nph; j += NW) {
-            const double* a = Acol(j);
+            const gdouble* a = Acol(j);
             double acc = 0.0;
-            for (int i = lane; i < m; i += 64) acc += a[i] * p.r[i];
+            for (int i = lane; i < m; i += 64) acc += a[i] * gp.r[i];
             acc = wave_sum(acc);
             if (lane == 0) {
-                p.w[j] = acc;
-                if (nph != p.n) p.w[j + nph] = -acc;
+                gp.w[j] = acc;
+                if (nph != p.n) gp.w[j + nph] = -acc;
             }
         }
         __syncthreads();
     }
 
-    __device__ void finalize() {
+    __device__ __forceinline__ void finalize() {
         const int n = p.n, m = p.m, nP = s.nP;
         double vz = 0.0, vp = 0.0;
         for (int j = tid; j < n; j += WG) {
-            const double wj = p.w[j];
-            if (p.pos[j] >= 0) vp = fmax(vp, fabs(wj));
+            const double wj = gp.w[j];
+            if (gp.pos[j] >= 0) vp = fmax(vp, fabs(wj));
             else vz = fmax(vz, fmax(wj, 0.0));
-            if (p.passive) p.passive[j] = (j < nP) ? p.P[j] : -1;
+            if (gp.passive) gp.passive[j] = (j < nP) ? gp.P[j] : -1;
         }
         vz = vmax(vz);
         vp = vmax(vp);
         double rr = 0.0;
-        for (int i = tid; i < m; i += WG) rr += p.r[i] * p.r[i];
+        for (int i = tid; i < m; i += WG) rr += gp.r[i] * gp.r[i];
         rr = sum(rr);
         if (tid == 0 && p.info) {
             double scale = s.anmax * s.bnorm;
@@ -1376,7 +1394,7 @@ struct Wg {
     }
 
     // ---------------- the whole solve ----------------
-    __device__ void run() {
+    __device__ __forceinline__ void run() {
         init();
         if (s.status == LHDM_STATUS_NONFINITE) {
             finalize();
@@ -1400,8 +1418,8 @@ struct Wg {
             else {
                 // one reflector: V = [0; 1; v], T = tau
                 const int m = p.m, r0 = s.nP;
-                for (int i = tid; i < m; i += WG) p.V[i] = (i < r0) ? 0.0 : p.G[i];
-                if (tid == 0) p.T[0] = s.tau[0];
+                for (int i = tid; i < m; i += WG) gp.V[i] = (i < r0) ? 0.0 : gp.G[i];
+                if (tid == 0) gp.T[0] = s.tau[0];
                 __syncthreads();
             }
             append_r();
@@ -1411,25 +1429,25 @@ struct Wg {
             const int k = s.k;
             if (k == 0) {
                 if (tid == 0) {
-                    p.excl[j1] = 1;
+                    gp.excl[j1] = 1;
                     s.any_excl = 1;
                 }
                 __syncthreads();
                 continue;
             }
             if (s.any_excl) {
-                for (int j = tid; j < p.n; j += WG) p.excl[j] = 0;
+                for (int j = tid; j < p.n; j += WG) gp.excl[j] = 0;
                 __syncthreads();
                 if (tid == 0) s.any_excl = 0;
             }
             // passive set grows by J, in order
             const int m = p.m, r0 = s.nP;
             for (int t = 0; t < k; ++t)
-                for (int i = tid; i < m; i += WG) p.Qadd[(size_t)t * m + i] = Qat(i, r0 + t);
+                for (int i = tid; i < m; i += WG) gp.Qadd[(size_t)t * m + i] = Qat(i, r0 + t);
             if (tid == 0) {
                 for (int t = 0; t < k; ++t) {
-                    p.P[r0 + t] = s.J[t];
-                    p.pos[s.J[t]] = r0 + t;
+                    gp.P[r0 + t] = s.J[t];
+                    gp.pos[s.J[t]] = r0 + t;
                 }
                 s.nP = r0 + k;
                 s.nPa = r0 + k;
@@ -1460,7 +1478,7 @@ struct Wg {
                 refresh_dual();
                 break;
             }
-            for (int c = tid; c < s.nP; c += WG) p.x[p.P[c]] = yv[c];
+            for (int c = tid; c < s.nP; c += WG) gp.x[gp.P[c]] = yv[c];
             __syncthreads();
             residual();
             dual_and_norms(k);
