@@ -319,32 +319,40 @@ struct Wg {
             for (int b = 0; b < TB; ++b)
 #pragma unroll
                 for (int t = 0; t < NT; ++t) acc[b][t] = wd4{0.0, 0.0, 0.0, 0.0};
+            // product s = 2 h + e of a 32-row step takes row r0 + 8 h + 2 g + e for
+            // K index g: the four lanes of a column read 64 contiguous bytes per
+            // load (16-byte loads where X allows them)
             for (int r0 = 0; r0 < m; r0 += 32) {
-                const int rb = r0 + 8 * g;
                 double av[TB][8];
                 if (r0 + 32 <= m && al16) {
 #pragma unroll
-                    for (int b = 0; b < TB; ++b) {
-                        const __attribute__((address_space(1))) wd2* s2 =
-                            reinterpret_cast<const __attribute__((address_space(1))) wd2*>(xc[b] + rb);
+                    for (int b = 0; b < TB; ++b)
 #pragma unroll
                         for (int h = 0; h < 4; ++h) {
-                            const wd2 x = s2[h];
+                            const wd2 x = *reinterpret_cast<const __attribute__((address_space(1))) wd2*>(
+                                xc[b] + r0 + 8 * h + 2 * g);
                             av[b][2 * h] = x[0];
                             av[b][2 * h + 1] = x[1];
                         }
-                    }
                 } else {
 #pragma unroll
                     for (int b = 0; b < TB; ++b)
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) av[b][u] = (rb + u < m) ? xc[b][rb + u] : 0.0;
+                        for (int u = 0; u < 8; ++u) {
+                            const int row = r0 + 8 * (u >> 1) + 2 * g + (u & 1);
+                            const double x = xc[b][min(row, m - 1)];
+                            av[b][u] = (row < m) ? x : 0.0;
+                        }
                 }
                 double bv[NT][8];
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) bv[t][u] = (rb + u < m) ? D[(size_t)(rb + u) * DVL + 16 * t + cl] : 0.0;
+                    for (int u = 0; u < 8; ++u) {
+                        const int row = r0 + 8 * (u >> 1) + 2 * g + (u & 1);
+                        const double x = D[(size_t)min(row, m - 1) * DVL + 16 * t + cl];
+                        bv[t][u] = (row < m) ? x : 0.0;
+                    }
 #pragma unroll
                 for (int b = 0; b < TB; ++b)
 #pragma unroll
@@ -641,22 +649,29 @@ struct Wg {
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] = wd4{0.0, 0.0, 0.0, 0.0};
             // W^T(t, i) = sum_l V(l, t) Q(i, l): lane (c, g) feeds V column 16 t + c and
-            // Q row i0 + c at rows l0 + 8 g .. l0 + 8 g + 7
+            // Q row i0 + c; product s = 2 h + e of a 32-row step takes l = l0 + 8 h + 2 g + e
             // HS 32-row steps per trip, all their loads before their products
             constexpr int HS = NT <= 2 ? 2 : 1;
             for (int l0 = r0; l0 < m; l0 += 32 * HS) {
                 double bq[HS][8], av[HS][NT][8];
 #pragma unroll
                 for (int h = 0; h < HS; ++h) {
-                    const int lb = l0 + 32 * h + 8 * g;
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) bq[h][u] = (lb + u < m) ? Q[(size_t)(lb + u) * m + ic] : 0.0;
+                    for (int u = 0; u < 8; ++u) {
+                        const int l = l0 + 32 * h + 8 * (u >> 1) + 2 * g + (u & 1);
+                        const double x = Q[(size_t)min(l, m - 1) * m + ic];
+                        bq[h][u] = (l < m) ? x : 0.0;
+                    }
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         const int tc = 16 * t + cl;
                         const auto* vc = V + (size_t)min(tc, k - 1) * m;
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) av[h][t][u] = (tc < k && lb + u < m) ? vc[lb + u] : 0.0;
+                        for (int u = 0; u < 8; ++u) {
+                            const int l = l0 + 32 * h + 8 * (u >> 1) + 2 * g + (u & 1);
+                            const double x = vc[min(l, m - 1)];
+                            av[h][t][u] = (tc < k && l < m) ? x : 0.0;
+                        }
                     }
                 }
 #pragma unroll
@@ -682,11 +697,13 @@ struct Wg {
 #pragma unroll
                 for (int ks = 0; ks < 4 * NT; ++ks) {
                     const int kk = 4 * ks + g;
-                    bw[ks] = (kk < k) ? wt[kk * 17 + cl] : 0.0;
+                    const double wv = wt[min(kk, KM - 1) * 17 + cl];
+                    bw[ks] = (kk < k) ? wv : 0.0;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         const int tc = 16 * t + cl;
-                        at[ks][t] = (kk < k && tc < k) ? T[(size_t)tc * kq + kk] : 0.0;
+                        const double tv = T[(size_t)min(tc, k - 1) * kq + min(kk, k - 1)];
+                        at[ks][t] = (kk < k && tc < k) ? tv : 0.0;
                     }
                 }
 #pragma unroll
@@ -707,7 +724,8 @@ struct Wg {
 #pragma unroll
             for (int ks = 0; ks < 4 * NT; ++ks) {
                 const int kk = 4 * ks + g;
-                bw[ks] = (kk < k) ? wt[kk * 17 + cl] : 0.0;
+                const double wv = wt[min(kk, KM - 1) * 17 + cl];
+                bw[ks] = (kk < k) ? wv : 0.0;
             }
             constexpr int HQ = NT <= 2 ? 4 : 2;
             for (int l0 = r0; l0 < m; l0 += 16 * HQ) {
@@ -722,7 +740,8 @@ struct Wg {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int l = l0 + 16 * h + 4 * v + g;
-                        qv[h][v] = (l < m && i0 + cl < m) ? Q[(size_t)l * m + i0 + cl] : 0.0;
+                        const double x = Q[(size_t)min(l, m - 1) * m + min(i0 + cl, m - 1)];
+                        qv[h][v] = (l < m && i0 + cl < m) ? x : 0.0;
                     }
                 double av[4 * NT][HQ];
 #pragma unroll
@@ -732,7 +751,8 @@ struct Wg {
 #pragma unroll
                     for (int h = 0; h < HQ; ++h) {
                         const int lc = l0 + 16 * h + cl;
-                        av[ks][h] = (kk < k && lc < m) ? vk[lc] : 0.0;
+                        const double x = vk[min(lc, m - 1)];
+                        av[ks][h] = (kk < k && lc < m) ? x : 0.0;
                     }
                 }
 #pragma unroll
