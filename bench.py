@@ -187,7 +187,7 @@ def _timed(fn, reps):
     return ts[len(ts) // 2], out
 
 
-def run_config(name, reps):
+def run_config(name, reps, engine="auto"):
     """Throughput of the other workloads: C1 and C4 (batched, one persistent
     launch), C2 (single solves on the whole-device engine), C5 (batched forward
     and the backward).  Prints one JSON line; the default run (C3) is the
@@ -200,7 +200,8 @@ def run_config(name, reps):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    out = {"config": name, "data": "synthetic", "dtype": "f64", "timing": f"median of {reps} after 1 warm-up"}
+    out = {"config": name, "data": "synthetic", "dtype": "f64", "timing": f"median of {reps} after 1 warm-up",
+           "batch_engine": engine}
     if name in ("c1", "c4", "c5"):
         if name == "c1":
             insts = [make_c1(1000 + i) for i in range(1000)]
@@ -216,7 +217,7 @@ def run_config(name, reps):
         out["instances"] = B
         out["a_bytes"] = int(pool.A.numel() * 8)
         for meth, use_lh in (("lhdm", False), ("lh", True)):
-            t, (x, passive, infos) = _timed(lambda: lhdm.solve_pooled(pool, use_lh=use_lh), reps)
+            t, (x, passive, infos) = _timed(lambda: lhdm.solve_pooled(pool, use_lh=use_lh, engine=engine), reps)
             out[meth] = {"solves_per_s": B / t, "ms_per_batch": 1e3 * t, **_summary(infos)}
             log(name, meth, out[meth])
             if name == "c5" and meth == "lhdm":
@@ -306,12 +307,14 @@ def main():
     ap.add_argument("--config", choices=("c1", "c2", "c4", "c5", "signflip", "illcond"),
                     help="measure another workload instead of the headline one (one JSON line)")
     ap.add_argument("--reps", type=int, default=10, help="timed repeats for --config")
+    ap.add_argument("--engine", choices=("auto", "fused", "fused2", "phased"), default="auto",
+                    help="batched engine for --config c1|c4|c5 (default: the library's tuning table)")
     args = ap.parse_args()
     if args.config:
         if args.gpus != 1:
             print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
             sys.exit(2)
-        run_config(args.config, args.reps)
+        run_config(args.config, args.reps, args.engine)
         return
     if args.write_traffic:
         write_traffic(*args.write_traffic)

@@ -63,6 +63,21 @@ extern "C" {
  * arithmetic) is left to the inner loop, where a zero iterate entry with a
  * nonpositive least-squares component gives the step length 0. */
 #define LHDM_FLAG_NO_JLOOP         4
+/* Batched solves (lhdm_solve_batched and lhdm_batched_workspace_bytes, which
+   must be given the same flags): the engine.  Without any of these the library
+   takes it from its tuning table (written by the package's autotuner from
+   timings on the target GPU) by instances per compute unit and largest m.
+     FUSED:  one persistent kernel runs whole solves, one workgroup per compute
+             unit, instances taken largest first from a device queue;
+     FUSED2: the same kernel compiled for two workgroups per compute unit;
+     PHASED: one kernel launch per stage of the outer step (append, inner loop,
+             accept) over every unfinished instance, the rounds replayed as a
+             HIP graph; every instance's state stays in the workspace, which is
+             therefore the sum of the instances' own sizes.
+   All three take the same steps in the same order: results are identical. */
+#define LHDM_FLAG_BATCH_FUSED      8
+#define LHDM_FLAG_BATCH_FUSED2     16
+#define LHDM_FLAG_BATCH_PHASED     32
 
 /* Solver parameters [host].  tau1, tau2, delta and kmax are the thresholds of
  * Algorithm 2 (delta is the tau_c of the Algorithm 3 signature); the defaults are

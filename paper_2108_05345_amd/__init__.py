@@ -240,13 +240,22 @@ def pack(As: Sequence[torch.Tensor], bs: Sequence[torch.Tensor]) -> Pool:
     return Pool(m, n, ao, bo, xo, Apool, bpool, xx)
 
 
+BATCH_ENGINES = {"auto": 0, "fused": 8, "fused2": 16, "phased": 32}
+
+
 def solve_pooled(pool: Pool, *, use_lh=False, tau1=0.6, tau2=0.15, delta=0.9, kmax=32, kkt_tol=1e-9,
-                 max_outer=0, max_inner=0):
-    """Batched solve over a packed pool; returns (x_pool, passive_pool, infos)."""
+                 max_outer=0, max_inner=0, engine="auto"):
+    """Batched solve over a packed pool; returns (x_pool, passive_pool, infos).
+
+    ``engine``: "auto" (the library's tuning table), "fused", "fused2" or
+    "phased" (LHDM_FLAG_BATCH_* in lhdm.h)."""
     lib = _lib.load()
     dev = pool.A.device
+    if engine not in BATCH_ENGINES:
+        raise ValueError(f"engine must be one of {sorted(BATCH_ENGINES)}")
     p = default_params(tau1=tau1, tau2=tau2, delta=delta, kmax=kmax, kkt_tol=kkt_tol, max_outer=max_outer,
                        max_inner=max_inner)
+    p.flags |= BATCH_ENGINES[engine]
     B = len(pool.m)
     mm, nn, ao, bo, xo = pool.arrays()
     x = torch.empty(pool.nx, dtype=torch.float64, device=dev)

@@ -15,6 +15,7 @@
 #include "lhdm_large.hpp"
 #include "lhdm_backward.hpp"
 #include "lhdm_testing.hpp"
+#include "lhdm_tuning.hpp"
 
 namespace lhdm {
 
@@ -32,11 +33,14 @@ struct ProbIn {
     int m, n;
 };
 
-// Persistent batched solve: each workgroup owns one workspace slot and takes
-// instances from the queue `order` (largest first; NULL: the given order) until
-// it is exhausted.  An instance without a w buffer (in.w == NULL) keeps its
-// dual in its slot at byte offset w_off.
-__global__ __launch_bounds__(WG) void wg_solve_kernel(const ProbIn* __restrict__ ins, int nprob,
+// Persistent batched solve ("fused" engine): each workgroup owns one workspace
+// slot and takes instances from the queue `order` (largest first; NULL: the
+// given order) until it is exhausted.  An instance without a w buffer
+// (in.w == NULL) keeps its dual in its slot at byte offset w_off.  OCC is the
+// number of workgroups per compute unit the kernel is compiled for (its
+// register budget: 512 or 256 per lane).
+template <int OCC>
+__global__ __launch_bounds__(WG, OCC) void wg_solve_kernel(const ProbIn* __restrict__ ins, int nprob,
                                                       const int* __restrict__ order, int* counter,
                                                       char* slots, size_t slot_stride, DevParams prm,
                                                       size_t w_off) {
@@ -69,6 +73,102 @@ __global__ __launch_bounds__(WG) void wg_solve_kernel(const ProbIn* __restrict__
         wg.run();
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// phased batched engine: one kernel per stage of the outer step over every
+// instance (Wg::stage_*), the rounds captured as a HIP graph.  Each instance
+// keeps its whole state between launches: its control block in `ctl`, its
+// workspace slice (slot_bytes of its own m, n), then its least-squares
+// solution y (kc doubles); its dual goes to in.w, which must be given.
+// ---------------------------------------------------------------------------
+constexpr int PH_INIT = -1;
+
+__device__ __forceinline__ void ph_prob(Prob& p, const ProbIn& in, char* base, const DevParams& prm) {
+    p.A = in.A;
+    p.lda = in.lda;
+    p.b = in.b;
+    p.x = in.x;
+    p.passive = in.passive;
+    p.info = in.info;
+    carve_slot(p, base, in.m, in.n, prm.kmax);
+    p.ybuf = (double*)(base + slot_bytes(in.m, in.n, prm.kmax));
+    p.w = in.w;
+    if (prm.twin) p.nph = in.n / 2;
+}
+
+__host__ __device__ inline size_t ph_slot_bytes(int m, int n, int kmax) {
+    const int kc = m < n ? m : n;
+    return slot_bytes(m, n, kmax) + pad256(sizeof(double) * kc);
+}
+
+// One workgroup per instance (blockIdx.x through `order`); instances not in
+// stage PH return at once.
+template <int PH>
+__global__ __launch_bounds__(WG, 2) void ph_kernel(const ProbIn* __restrict__ ins,
+                                                   const int* __restrict__ order,
+                                                   const size_t* __restrict__ soff, Ctl* __restrict__ ctl,
+                                                   char* slots, DevParams prm) {
+    __shared__ WgLds lds;
+    const int idx = order[blockIdx.x];
+    Ctl* c = ctl + idx;
+    if (PH != PH_INIT && c->stage != PH) return;
+    const ProbIn in = ins[idx];
+    Prob p;
+    ph_prob(p, in, slots + soff[idx], prm);
+    DevParams q = prm;
+    if (q.max_outer <= 0) q.max_outer = 3 * in.n;
+    if (q.max_inner <= 0) q.max_inner = 3 * in.n;
+    Wg wg(p, q, lds.sh, (lds_double*)lds.x);
+    if (PH == PH_INIT) {
+        wg.start();
+    } else {
+        ctl_load(lds.sh, c);
+        if (PH == ST_APPEND) wg.stage_append();
+        else if (PH == ST_INNER) wg.stage_inner();
+        else wg.stage_accept();
+    }
+    if (lds.sh.stage == ST_DONE) wg.finalize();
+    ctl_store(lds.sh, c);
+}
+
+// Number of instances not finished, into live[0] (one workgroup).
+__global__ __launch_bounds__(WG) void ph_count_kernel(const Ctl* __restrict__ ctl, int nprob, int* live) {
+    __shared__ int part[NW];
+    int cnt = 0;
+    for (int i = threadIdx.x; i < nprob; i += WG) cnt += (ctl[i].stage != ST_DONE) ? 1 : 0;
+    cnt = wave_sum_int(cnt);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < NW; ++w) t += part[w];
+        live[0] = t;
+    }
+}
+
+// Instances cut off by the round limit end with the iteration-limit status.
+__global__ __launch_bounds__(WG) void ph_cutoff_kernel(const ProbIn* __restrict__ ins,
+                                                       const int* __restrict__ order,
+                                                       const size_t* __restrict__ soff, Ctl* __restrict__ ctl,
+                                                       char* slots, DevParams prm) {
+    __shared__ WgLds lds;
+    const int idx = order[blockIdx.x];
+    Ctl* c = ctl + idx;
+    if (c->stage == ST_DONE) return;
+    const ProbIn in = ins[idx];
+    Prob p;
+    ph_prob(p, in, slots + soff[idx], prm);
+    Wg wg(p, prm, lds.sh, (lds_double*)lds.x);
+    ctl_load(lds.sh, c);
+    if (threadIdx.x == 0) {
+        lds.sh.status = LHDM_STATUS_MAXITER;
+        lds.sh.stage = ST_DONE;
+    }
+    __syncthreads();
+    wg.refresh_dual();
+    wg.finalize();
+    ctl_store(lds.sh, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -108,21 +208,31 @@ struct WgLayout {
     int nslot;
 };
 
-static int wg_slots_for(int batch) {
+// Batched engines: the fused persistent kernel compiled for one or for two
+// workgroups per compute unit, or the phased kernels.
+enum { BE_FUSED1 = 0, BE_FUSED2 = 1, BE_PHASED = 2 };
+
+static int device_cus() {
     // compute units of the current device (queried per call: a process may use several devices)
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_solve_kernel, WG, 0) != hipSuccess || occ < 1)
-        occ = 1;
-    return std::max(1, std::min(batch, cus * occ));
+    return cus;
 }
 
-static WgLayout wg_layout(int batch, int mmax, int nmax, int kmax) {
+static int wg_slots_for(int batch, int eng = BE_FUSED1) {
+    int occ = 0;
+    const hipError_t e = (eng == BE_FUSED2)
+                             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_solve_kernel<2>, WG, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_solve_kernel<1>, WG, 0);
+    if (e != hipSuccess || occ < 1) occ = 1;
+    return std::max(1, std::min(batch, device_cus() * occ));
+}
+
+static WgLayout wg_layout(int batch, int mmax, int nmax, int kmax, int eng = BE_FUSED1) {
     WgLayout L;
-    L.nslot = wg_slots_for(batch);
+    L.nslot = wg_slots_for(batch, eng);
     size_t o = 0;
     L.off_in = o;
     o += pad256(sizeof(ProbIn) * (size_t)batch);
@@ -137,12 +247,23 @@ static WgLayout wg_layout(int batch, int mmax, int nmax, int kmax) {
     return L;
 }
 
+// largest instances first (longest-processing-time order)
+static std::vector<int> lpt_order(const std::vector<int>& mm, const std::vector<int>& nn) {
+    std::vector<int> order(mm.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (long long)mm[a] * nn[a] > (long long)mm[b] * nn[b];
+    });
+    return order;
+}
+
 static int run_wg_engine(hipStream_t st, const std::vector<ProbIn>& ins, const std::vector<int>& mm,
-                         const std::vector<int>& nn, const DevParams& prm, void* ws, size_t ws_bytes) {
+                         const std::vector<int>& nn, const DevParams& prm, void* ws, size_t ws_bytes,
+                         int eng = BE_FUSED1) {
     const int batch = (int)ins.size();
     const int mmax = *std::max_element(mm.begin(), mm.end());
     const int nmax = *std::max_element(nn.begin(), nn.end());
-    WgLayout L = wg_layout(batch, mmax, nmax, prm.kmax);
+    WgLayout L = wg_layout(batch, mmax, nmax, prm.kmax, eng);
     if (ws == nullptr) {
         int rc = cached_workspace(L.total, &ws);
         if (rc) return rc;
@@ -150,19 +271,143 @@ static int run_wg_engine(hipStream_t st, const std::vector<ProbIn>& ins, const s
         return LHDM_EWORKSPACE;
     }
     char* base = (char*)ws;
-    // largest instances first (longest-processing-time order for the queue)
-    std::vector<int> order(batch);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return (long long)mm[a] * nn[a] > (long long)mm[b] * nn[b];
-    });
+    const std::vector<int> order = lpt_order(mm, nn);
     HIPCHK(hipMemcpyAsync(base + L.off_in, ins.data(), sizeof(ProbIn) * batch, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(base + L.off_order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(base + L.off_counter, 0, sizeof(int), st));
-    hipLaunchKernelGGL(wg_solve_kernel, dim3(L.nslot), dim3(WG), 0, st, (const ProbIn*)(base + L.off_in), batch,
-                       (const int*)(base + L.off_order), (int*)(base + L.off_counter), base + L.off_slots,
-                       L.slot_stride, prm, (size_t)0);
+    if (eng == BE_FUSED2)
+        hipLaunchKernelGGL(wg_solve_kernel<2>, dim3(L.nslot), dim3(WG), 0, st, (const ProbIn*)(base + L.off_in),
+                           batch, (const int*)(base + L.off_order), (int*)(base + L.off_counter),
+                           base + L.off_slots, L.slot_stride, prm, (size_t)0);
+    else
+        hipLaunchKernelGGL(wg_solve_kernel<1>, dim3(L.nslot), dim3(WG), 0, st, (const ProbIn*)(base + L.off_in),
+                           batch, (const int*)(base + L.off_order), (int*)(base + L.off_counter),
+                           base + L.off_slots, L.slot_stride, prm, (size_t)0);
     HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+// Layout of the phased engine's workspace:
+// [ProbIn x batch | order x batch | slot offsets x batch | Ctl x batch | live count | slots]
+// with one slot (ph_slot_bytes of its own size) per instance.
+struct PhLayout {
+    size_t off_in, off_order, off_soff, off_ctl, off_live, off_slots, total;
+};
+
+static PhLayout ph_layout(int batch, const int* m, const int* n, int kmax, std::vector<size_t>* soff) {
+    PhLayout L;
+    size_t o = 0;
+    L.off_in = o;
+    o += pad256(sizeof(ProbIn) * (size_t)batch);
+    L.off_order = o;
+    o += pad256(sizeof(int) * (size_t)batch);
+    L.off_soff = o;
+    o += pad256(sizeof(size_t) * (size_t)batch);
+    L.off_ctl = o;
+    o += pad256(sizeof(Ctl) * (size_t)batch);
+    L.off_live = o;
+    o += 256;
+    L.off_slots = o;
+    size_t so = 0;
+    for (int i = 0; i < batch; ++i) {
+        if (soff) soff->push_back(so);
+        so += ph_slot_bytes(m[i], n[i], kmax);
+    }
+    L.total = o + so;
+    return L;
+}
+
+// Rounds (one APPEND, INNER and ACCEPT launch each) per graph replay.
+constexpr int PH_ROUNDS_PER_GRAPH = 4;
+
+// A stream per device for graph capture (capture needs a stream other than the
+// legacy default one; the graph is then launched on the caller's stream).
+static int capture_stream(hipStream_t* out) {
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return LHDM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!streams[dev]) HIPCHK(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    *out = streams[dev];
+    return 0;
+}
+
+static int run_phased(hipStream_t st, const std::vector<ProbIn>& ins, const std::vector<int>& mm,
+                      const std::vector<int>& nn, const DevParams& prm, void* ws, size_t ws_bytes) {
+    const int batch = (int)ins.size();
+    std::vector<size_t> soff;
+    const PhLayout L = ph_layout(batch, mm.data(), nn.data(), prm.kmax, &soff);
+    if (ws == nullptr) {
+        int rc = cached_workspace(L.total, &ws);
+        if (rc) return rc;
+    } else if (ws_bytes < L.total || ((uintptr_t)ws & 255)) {
+        return LHDM_EWORKSPACE;
+    }
+    char* base = (char*)ws;
+    const std::vector<int> order = lpt_order(mm, nn);
+    HIPCHK(hipMemcpyAsync(base + L.off_in, ins.data(), sizeof(ProbIn) * batch, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + L.off_order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + L.off_soff, soff.data(), sizeof(size_t) * batch, hipMemcpyHostToDevice, st));
+    const ProbIn* d_in = (const ProbIn*)(base + L.off_in);
+    const int* d_order = (const int*)(base + L.off_order);
+    const size_t* d_soff = (const size_t*)(base + L.off_soff);
+    Ctl* d_ctl = (Ctl*)(base + L.off_ctl);
+    int* d_live = (int*)(base + L.off_live);
+    char* slots = base + L.off_slots;
+    hipLaunchKernelGGL(ph_kernel<PH_INIT>, dim3(batch), dim3(WG), 0, st, d_in, d_order, d_soff, d_ctl, slots, prm);
+    HIPCHK(hipGetLastError());
+    // the rounds, captured once per call
+    hipStream_t cs;
+    int rc = capture_stream(&cs);
+    if (rc) return rc;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < PH_ROUNDS_PER_GRAPH; ++r) {
+        hipLaunchKernelGGL(ph_kernel<ST_APPEND>, dim3(batch), dim3(WG), 0, cs, d_in, d_order, d_soff, d_ctl, slots,
+                           prm);
+        hipLaunchKernelGGL(ph_kernel<ST_INNER>, dim3(batch), dim3(WG), 0, cs, d_in, d_order, d_soff, d_ctl, slots,
+                           prm);
+        hipLaunchKernelGGL(ph_kernel<ST_ACCEPT>, dim3(batch), dim3(WG), 0, cs, d_in, d_order, d_soff, d_ctl, slots,
+                           prm);
+    }
+    hipLaunchKernelGGL(ph_count_kernel, dim3(1), dim3(WG), 0, cs, (const Ctl*)d_ctl, batch, d_live);
+    HIPCHK(hipStreamEndCapture(cs, &graph));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        hipGraphDestroy(graph);
+        set_last_hip_error((int)ie);
+        return LHDM_EHIP;
+    }
+    // every round advances each unfinished instance by one outer step or one
+    // exclusion; the limit below is far above what the iteration limits allow
+    int nmax = 1;
+    for (int v : nn) nmax = std::max(nmax, v);
+    const long long outer_cap = prm.max_outer > 0 ? prm.max_outer : 3LL * nmax;
+    const long long max_graphs = (4 * outer_cap + 16) / PH_ROUNDS_PER_GRAPH + 1;
+    int live = batch;
+    int err = 0;
+    for (long long g = 0; g < max_graphs && live > 0; ++g) {
+        hipError_t e = hipGraphLaunch(exec, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&live, d_live, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            set_last_hip_error((int)e);
+            err = LHDM_EHIP;
+            break;
+        }
+    }
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+    if (err) return err;
+    if (live > 0) {
+        hipLaunchKernelGGL(ph_cutoff_kernel, dim3(batch), dim3(WG), 0, st, d_in, d_order, d_soff, d_ctl, slots,
+                           prm);
+        HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipStreamSynchronize(st));
     return 0;
 }
@@ -336,7 +581,7 @@ static int solve_batched_noalloc(hipStream_t st, int batch, const int32_t* m, co
     DevParams prm = dev_params(p, nmax, use_lh ? 1 : 0);
     prm.max_outer = p->max_outer > 0 ? p->max_outer : 0;   // <= 0: 3 n per instance
     prm.max_inner = p->max_inner > 0 ? p->max_inner : 0;
-    hipLaunchKernelGGL(wg_solve_kernel, dim3(nslot), dim3(WG), 0, st, (const ProbIn*)(base + L.off_in), batch,
+    hipLaunchKernelGGL(wg_solve_kernel<1>, dim3(nslot), dim3(WG), 0, st, (const ProbIn*)(base + L.off_in), batch,
                        (const int*)nullptr, (int*)(base + L.off_counter), base + L.off_slots, L.slot_stride, prm,
                        L.w_off);
     HIPCHK(hipGetLastError());
@@ -537,6 +782,29 @@ int lh_solve(void* stream, int32_t m, int32_t n, const double* A, int64_t lda, c
     return solve_one(stream, m, n, A, lda, b, dev_params(&p, n, 1), 0, x, w, passive, info, ws, ws_bytes);
 }
 
+}  // extern "C"
+
+namespace lhdm {
+
+// The batched engine: forced by a flag, else the tuning table's first row whose
+// bounds hold for (instances per compute unit, largest m).
+static int batch_engine(int batch, const int32_t* m, const int32_t* n, int flags) {
+    if (flags & LHDM_FLAG_BATCH_PHASED) return BE_PHASED;
+    if (flags & LHDM_FLAG_BATCH_FUSED2) return BE_FUSED2;
+    if (flags & LHDM_FLAG_BATCH_FUSED) return BE_FUSED1;
+    int mmax = 1;
+    for (int i = 0; i < batch; ++i) mmax = std::max(mmax, (int)m[i]);
+    (void)n;
+    const double per_cu = (double)batch / device_cus();
+    for (const TuneRow& r : kTuneRows)
+        if (per_cu <= r.per_cu_hi && mmax <= r.m_hi) return r.engine;
+    return BE_FUSED1;
+}
+
+}  // namespace lhdm
+
+extern "C" {
+
 size_t lhdm_batched_workspace_bytes(int32_t batch, const int32_t* m, const int32_t* n, const lhdm_params* p) {
     if (batch < 1 || !m || !n) return 0;
     int mmax = 1, nmax = 1;
@@ -547,7 +815,9 @@ size_t lhdm_batched_workspace_bytes(int32_t batch, const int32_t* m, const int32
         wextra += (size_t)std::max(0, (int)n[i]);
     }
     const int kmax = p ? std::max(1, (int)p->kmax) : 32;
-    WgLayout L = wg_layout(batch, mmax, nmax, kmax);
+    const int eng = batch_engine(batch, m, n, p ? p->flags : 0);
+    if (eng == BE_PHASED) return ph_layout(batch, m, n, kmax, nullptr).total + pad256(sizeof(double) * wextra);
+    WgLayout L = wg_layout(batch, mmax, nmax, kmax, eng);
     return L.total + pad256(sizeof(double) * wextra);
 }
 
@@ -579,8 +849,12 @@ int lhdm_solve_batched(void* stream, int32_t batch, const int32_t* m, const int3
     }
     if (ws_bytes < need || ((uintptr_t)ws & 255)) return LHDM_EWORKSPACE;
     const int kmax = use_lh ? 1 : p->kmax;
-    WgLayout L = wg_layout(batch, *std::max_element(mm.begin(), mm.end()), nmax, kmax);
-    double* wpool = (double*)((char*)ws + L.total);
+    const int eng = batch_engine(batch, m, n, p->flags);
+    // the workspace size above was computed with p->kmax; use_lh only shrinks the slots
+    const size_t lay = (eng == BE_PHASED) ? ph_layout(batch, m, n, kmax, nullptr).total
+                                          : wg_layout(batch, *std::max_element(mm.begin(), mm.end()), nmax, kmax,
+                                                      eng).total;
+    double* wpool = (double*)((char*)ws + lay);
     std::vector<ProbIn> ins(batch);
     size_t wo = 0;
     for (int i = 0; i < batch; ++i) {
@@ -599,7 +873,8 @@ int lhdm_solve_batched(void* stream, int32_t batch, const int32_t* m, const int3
     // non-positive limits are resolved per instance (3 n_i) by the kernel
     prm.max_outer = p->max_outer > 0 ? p->max_outer : 0;
     prm.max_inner = p->max_inner > 0 ? p->max_inner : 0;
-    return run_wg_engine((hipStream_t)stream, ins, mm, nn, prm, ws, L.total);
+    if (eng == BE_PHASED) return run_phased((hipStream_t)stream, ins, mm, nn, prm, ws, lay);
+    return run_wg_engine((hipStream_t)stream, ins, mm, nn, prm, ws, lay, eng);
 }
 
 int lhdm_solve_batched_noalloc(void* stream, int32_t batch, const int32_t* m, const int32_t* n,

@@ -222,6 +222,12 @@ __device__ __forceinline__ double wave_min(double v) {
     return __shfl(v, 0, 64);
 }
 
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return __shfl(v, 0, 64);
+}
+
 __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_down(v, o, 64));

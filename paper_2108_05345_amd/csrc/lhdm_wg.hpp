@@ -15,9 +15,12 @@ namespace lhdm {
 // Control state of one solve.  The workgroup engine keeps it in LDS for the
 // whole solve; the large-instance engine keeps it in global memory between
 // launches and copies it into LDS inside each single-workgroup kernel.
+// Stages of an outer step (Wg::stage_*).
+enum { ST_APPEND = 0, ST_INNER = 1, ST_ACCEPT = 2, ST_DONE = 3 };
+
 struct Ctl {
     double tol_w, anmax, bnorm;
-    int nP, nP0, nPa, status, outer, inner, jdrops, ncol, k, kr, done, q, any_excl, j1;
+    int nP, nP0, nPa, status, outer, inner, jdrops, ncol, k, kr, done, q, any_excl, j1, stage;
     int J[KM];
     double tau[KM];          // Householder scalars of the panel
     double beta[KM];         // diagonal of the new R block
@@ -48,8 +51,9 @@ typedef __attribute__((address_space(3))) double lds_double;
 typedef __attribute__((address_space(3))) int lds_int;
 constexpr int WG_TS = 64;                          // triangular-solve block
 constexpr int WG_DB = 64;                          // downdate window
-constexpr int WG_LX = (WG_DB + 1) * WG_DB + 2 * YMAX;
+constexpr int WG_LX = WG_TS * (WG_TS + 1) + YMAX / 2;
 static_assert(WG_LX >= NW * 16 * 65, "colmat tile staging");
+static_assert(WG_LX >= (WG_DB + 1) * WG_DB + 2 * WG_DB, "downdate window and its rotations");
 static_assert(WG_LX >= WG_TS * (WG_TS + 1) + YMAX / 2, "triangular-solve block and slot indices");
 static_assert(WG_LX >= NW * KM * 17, "Q-update tiles");
 struct WgLds {
@@ -1015,7 +1019,8 @@ struct Wg {
     static constexpr int DB = WG_DB;
     __device__ __forceinline__ void downdate_unit() {
         lds_double(*win)[DB] = reinterpret_cast<lds_double(*)[DB]>(lx);
-        lds_double* rot = lx + (DB + 1) * DB;   // (c, s) of rotation e at 2 e, 2 e + 1
+        lds_double* rl = lx + (DB + 1) * DB;   // rotations of the window being applied
+        gdouble* rot = gp.rot;                 // (c, s) of rotation e at 2 e, 2 e + 1
         const int nP = s.nP, first = gp.rm[0], m = p.m;
         const int nd = nP - 1 - first;
         if (wid == 0 && nd > 0) {
@@ -1041,8 +1046,16 @@ struct Wg {
                     if (bb == 0) run = col[rlo];
                     wave_lds_sync();
                     if (bb < b) {
+                        // block bb's rotations (written by this wave) into LDS
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int q = 64 * h + lane;
+                            const double v = rot[2 * DB * bb + min(q, 2 * nw - 1)];
+                            rl[q] = v;
+                        }
+                        wave_lds_sync();
                         for (int k = 0; k < nw; ++k) {
-                            const double cs = rot[2 * (DB * bb + k)], sn = rot[2 * (DB * bb + k) + 1];
+                            const double cs = rl[2 * k], sn = rl[2 * k + 1];
                             const double y = win[k + 1][lane];
                             win[k][lane] = cs * run + sn * y;
                             run = -sn * run + cs * y;
@@ -1064,6 +1077,8 @@ struct Wg {
                         }
                     }
                     win[nw][lane] = run;
+                    // the rotations stored above are read back by this wave in later windows
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                     wave_lds_sync();
                     if (valid) {
                         const int top = (bb < b) ? nw - 1 : nw;   // the carried row goes to the next window
@@ -1413,96 +1428,140 @@ struct Wg {
         __syncthreads();
     }
 
-    // ---------------- the whole solve ----------------
-    __device__ __forceinline__ void run() {
-        init();
-        if (s.status == LHDM_STATUS_NONFINITE) {
-            finalize();
+    // ---------------- stages of an outer step ----------------
+    // One outer step in three stages, so that a solve runs either in one loop
+    // (run) or as one kernel launch per stage over many instances (the phased
+    // batched engine); the stage and everything the next stage needs live in
+    // the control block and the instance's workspace.
+    //   APPEND: selection, projection, deviation maximization, Householder
+    //           panel, compact-WY Q update, feasibility loop on J, y = R^-1 bt;
+    //   INNER:  the inner loop (step length, removals, downdate) until y > 0;
+    //   ACCEPT: x = y, residual, dual and projected-norm update.
+    __device__ __forceinline__ void stage_append() {
+        select();
+        if (s.done) {
+            if (tid == 0) s.stage = ST_DONE;
+            __syncthreads();
             return;
         }
-        while (true) {
-            select();
-            if (s.done) break;
-            const int ncol = s.ncol;
-            project(ncol);
-            if (ncol > 1) {
-                deviation_maximization();
-            } else {
-                if (tid == 0) s.k = 1;
-                __syncthreads();
-            }
-            if (tid == 0) s.kr = s.k;
+        const int ncol = s.ncol;
+        project(ncol);
+        if (ncol > 1) {
+            deviation_maximization();
+        } else {
+            if (tid == 0) s.k = 1;
             __syncthreads();
-            panel_qr();
-            if (s.kr > 1) form_wy();
-            else {
-                // one reflector: V = [0; 1; v], T = tau
-                const int m = p.m, r0 = s.nP;
-                for (int i = tid; i < m; i += WG) gp.V[i] = (i < r0) ? 0.0 : gp.G[i];
-                if (tid == 0) gp.T[0] = s.tau[0];
-                __syncthreads();
-            }
-            append_r();
-            update_q();
-            const int j1 = s.J[0];
-            jloop();
-            const int k = s.k;
-            if (k == 0) {
-                if (tid == 0) {
-                    gp.excl[j1] = 1;
-                    s.any_excl = 1;
-                }
-                __syncthreads();
-                continue;
-            }
-            if (s.any_excl) {
-                for (int j = tid; j < p.n; j += WG) gp.excl[j] = 0;
-                __syncthreads();
-                if (tid == 0) s.any_excl = 0;
-            }
-            // passive set grows by J, in order
+        }
+        if (tid == 0) {
+            s.kr = s.k;
+            s.j1 = s.J[0];
+        }
+        __syncthreads();
+        panel_qr();
+        if (s.kr > 1) form_wy();
+        else {
+            // one reflector: V = [0; 1; v], T = tau
             const int m = p.m, r0 = s.nP;
-            for (int t = 0; t < k; ++t)
-                for (int i = tid; i < m; i += WG) gp.Qadd[(size_t)t * m + i] = Qat(i, r0 + t);
+            for (int i = tid; i < m; i += WG) gp.V[i] = (i < r0) ? 0.0 : gp.G[i];
+            if (tid == 0) gp.T[0] = s.tau[0];
+            __syncthreads();
+        }
+        append_r();
+        update_q();
+        jloop();
+        const int k = s.k;
+        if (k == 0) {
             if (tid == 0) {
-                for (int t = 0; t < k; ++t) {
-                    gp.P[r0 + t] = s.J[t];
-                    gp.pos[s.J[t]] = r0 + t;
-                }
-                s.nP = r0 + k;
-                s.nPa = r0 + k;
-                s.outer += 1;
+                gp.excl[s.j1] = 1;
+                s.any_excl = 1;
+                s.stage = ST_APPEND;
             }
             __syncthreads();
-            trsv();
-            bool stop = false;
-            while (true) {
-                double mn = INFINITY;
-                for (int c = tid; c < s.nP; c += WG) mn = fmin(mn, yv[c]);
-                mn = vmin(mn);
-                if (mn > 0.0) break;
-                if (s.inner >= prm.max_inner) {
-                    stop = true;
-                    break;
-                }
-                __syncthreads();
-                if (tid == 0) s.inner += 1;
-                if (prm.signflip && sign_flip()) break;   // y > 0 now: the inner loop ends
-                inner_step();
-                downdate();
-                trsv();
+            return;
+        }
+        if (s.any_excl) {
+            for (int j = tid; j < p.n; j += WG) gp.excl[j] = 0;
+            __syncthreads();
+            if (tid == 0) s.any_excl = 0;
+        }
+        // passive set grows by J, in order
+        const int m = p.m, r0 = s.nP;
+        for (int t = 0; t < k; ++t)
+            for (int i = tid; i < m; i += WG) gp.Qadd[(size_t)t * m + i] = Qat(i, r0 + t);
+        if (tid == 0) {
+            for (int t = 0; t < k; ++t) {
+                gp.P[r0 + t] = s.J[t];
+                gp.pos[s.J[t]] = r0 + t;
             }
-            if (stop) {
-                if (tid == 0) s.status = LHDM_STATUS_MAXITER;
-                __syncthreads();
-                refresh_dual();
+            s.nP = r0 + k;
+            s.nPa = r0 + k;
+            s.outer += 1;
+            s.stage = ST_INNER;
+        }
+        __syncthreads();
+        trsv();
+    }
+
+    __device__ __forceinline__ void stage_inner() {
+        bool stop = false;
+        while (true) {
+            double mn = INFINITY;
+            for (int c = tid; c < s.nP; c += WG) mn = fmin(mn, yv[c]);
+            mn = vmin(mn);
+            if (mn > 0.0) break;
+            if (s.inner >= prm.max_inner) {
+                stop = true;
                 break;
             }
-            for (int c = tid; c < s.nP; c += WG) gp.x[gp.P[c]] = yv[c];
             __syncthreads();
-            residual();
-            dual_and_norms(k);
+            if (tid == 0) s.inner += 1;
+            if (prm.signflip && sign_flip()) break;   // y > 0 now: the inner loop ends
+            inner_step();
+            downdate();
+            trsv();
         }
+        __syncthreads();
+        if (stop) {
+            if (tid == 0) {
+                s.status = LHDM_STATUS_MAXITER;
+                s.stage = ST_DONE;
+            }
+            __syncthreads();
+            refresh_dual();
+            return;
+        }
+        if (tid == 0) s.stage = ST_ACCEPT;
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void stage_accept() {
+        for (int c = tid; c < s.nP; c += WG) gp.x[gp.P[c]] = yv[c];
+        __syncthreads();
+        residual();
+        dual_and_norms(s.k);
+        if (tid == 0) s.stage = ST_APPEND;
+        __syncthreads();
+    }
+
+    // a0 and the first stage; false when the solve is already finished
+    __device__ __forceinline__ bool start() {
+        init();
+        if (tid == 0) s.stage = (s.status == LHDM_STATUS_NONFINITE) ? ST_DONE : ST_APPEND;
+        __syncthreads();
+        return s.stage != ST_DONE;
+    }
+
+    __device__ __forceinline__ void step() {
+        const int st = s.stage;
+        if (st == ST_APPEND) stage_append();
+        else if (st == ST_INNER) stage_inner();
+        else if (st == ST_ACCEPT) stage_accept();
+    }
+
+    // ---------------- the whole solve ----------------
+    __device__ __forceinline__ void run() {
+        if (start())
+            while (s.stage != ST_DONE) step();
         finalize();
     }
 };
