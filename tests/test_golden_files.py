@@ -43,3 +43,24 @@ def test_golden_solution_satisfies_kkt(c3, delta):
     rep = oracle.kkt_report(c3.A, c3.b, x)
     assert rep["kkt"] <= 1e-9 and rep["feasible"]
     assert abs(rep["kkt"] - float(z["kkt"])) <= 1e-12
+
+
+def test_batch_fixture_matches_its_instances():
+    # the stored passive sets index columns of the instances they were made for,
+    # every stored solve converged, and instance i generated alone is instance i
+    # of the batch
+    import os
+    import numpy as np
+    from workloads import make_c4_batch, make_c4_instance
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "c4_seed4000_lhdm.npz"), allow_pickle=False)
+    assert len(z["P_len"]) == 2000 and int(z["P_len"].sum()) == len(z["P_flat"])
+    assert (z["counters"][:, 0] == 0).all()
+    assert (z["counters"][:, 4] == z["P_len"]).all()
+    batch = make_c4_batch(4000, count=2000)
+    offs = np.concatenate([[0], np.cumsum(z["P_len"])])
+    for i in (0, 1, 999, 1999):
+        one = make_c4_instance(i, 4000)
+        assert np.array_equal(one.A, batch[i].A) and np.array_equal(one.b, batch[i].b)
+        P = z["P_flat"][offs[i]:offs[i + 1]]
+        assert len(set(P.tolist())) == len(P) and P.min() >= 0 and P.max() < one.A.shape[1]
+        assert len(P) <= min(one.A.shape)

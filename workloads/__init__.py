@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     make_c2,
     make_c3,
     make_c4_batch,
+    make_c4_instance,
     make_c5_batch,
     make_small,
     make_illcond,

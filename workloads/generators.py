@@ -107,19 +107,27 @@ def make_c3(seed: int = 3000, m: int = 4096, n: int = 16384, k: int = 820) -> In
                     f"c3-gauss-{m}x{n}", seed, {"m": m, "n": n, "k": k, "noise_std": 1e-3})
 
 
+def _c4_from_child(child, i, seed, m_lo, m_hi):
+    rng = _rng(child)
+    m = int(rng.integers(m_lo, m_hi + 1))
+    n = int(round(m * rng.uniform(2.0, 4.0)))
+    A = rng.uniform(0.0, 1.0, (m, n))
+    k = int(round(0.1 * n))
+    return _planted(rng, A, k, lambda r, kk: r.uniform(0.0, 1.0, kk), 1e-2,
+                    f"c4-uniform-{i}", (seed, i), {"m": m, "n": n, "k": k})
+
+
 def make_c4_batch(seed: int = 4000, count: int = 2000, m_lo: int = 32, m_hi: int = 512):
     """Uneven batch: m ~ U{m_lo..m_hi}, n = round(m U[2,4]), A ~ U[0,1], 10%-dense U[0,1]
     nonnegative x, noise std 1e-2.  Child seeds come from SeedSequence(seed).spawn(count)."""
-    out = []
-    for i, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
-        rng = _rng(child)
-        m = int(rng.integers(m_lo, m_hi + 1))
-        n = int(round(m * rng.uniform(2.0, 4.0)))
-        A = rng.uniform(0.0, 1.0, (m, n))
-        k = int(round(0.1 * n))
-        out.append(_planted(rng, A, k, lambda r, kk: r.uniform(0.0, 1.0, kk), 1e-2,
-                            f"c4-uniform-{i}", (seed, i), {"m": m, "n": n, "k": k}))
-    return out
+    return [_c4_from_child(child, i, seed, m_lo, m_hi)
+            for i, child in enumerate(np.random.SeedSequence(seed).spawn(count))]
+
+
+def make_c4_instance(i: int, seed: int = 4000, count: int = 2000, m_lo: int = 32, m_hi: int = 512):
+    """Instance i of make_c4_batch(seed, count, m_lo, m_hi), generated alone."""
+    child = np.random.SeedSequence(seed).spawn(count)[i]
+    return _c4_from_child(child, i, seed, m_lo, m_hi)
 
 
 def make_c5_batch(seed: int = 5000, count: int = 256, m: int = 256, n: int = 512):
