@@ -64,3 +64,25 @@ def test_batch_fixture_matches_its_instances():
         P = z["P_flat"][offs[i]:offs[i + 1]]
         assert len(set(P.tolist())) == len(P) and P.min() >= 0 and P.max() < one.A.shape[1]
         assert len(P) <= min(one.A.shape)
+
+
+def test_c2_fixture_is_the_planted_solution():
+    # noiseless sparse recovery: the stored oracle solutions are the planted x
+    # (the unique NNLS solution); the passive set holds its support, plus at
+    # most a column whose coefficient is rounding noise (zero residual)
+    import os
+    import numpy as np
+    from workloads import make_c2
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_seeds2000-2019.npz"), allow_pickle=False)
+    for method in ("lhdm", "lh"):
+        offs = np.concatenate([[0], np.cumsum(z[f"{method}_P_len"])])
+        assert (z[f"{method}_counters"][:, 0] == 0).all()
+        for i, seed in enumerate(z["seeds"][:4]):
+            inst = make_c2(int(seed))
+            P = z[f"{method}_P"][offs[i]:offs[i + 1]]
+            x = np.zeros(inst.A.shape[1])
+            x[P] = z[f"{method}_xP"][offs[i]:offs[i + 1]]
+            supp = sorted(np.nonzero(x > 1e-12)[0].tolist())
+            assert supp == sorted(np.nonzero(inst.x_true)[0].tolist())
+            assert set(supp) <= set(P.tolist())
+            np.testing.assert_allclose(x, inst.x_true, rtol=0, atol=1e-10)

@@ -100,3 +100,42 @@ def test_backward_at_the_differentiation_shape(lhdm):
         scale = max(np.abs(rA).max(), 1.0)
         assert np.abs(gAi - rA).max() <= 1e-8 * scale, i
         assert np.abs(gb[bo:bo + m] - rb).max() <= 1e-8 * max(np.abs(rb).max(), 1.0), i
+
+
+C2_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_seeds2000-2019.npz")
+
+
+@pytest.mark.parametrize("method", ["lhdm", "lh"])
+def test_all_20_sparse_recovery_instances_against_the_oracle(lhdm, method):
+    # m = 1024, n = 4096 (the whole-device engine): the ordered passive set,
+    # the counters and x of every seed against the oracle's stored results,
+    # and the planted solution recovered
+    from parity_util import _dev
+    from workloads import make_c2
+    z = np.load(C2_GOLDEN, allow_pickle=False)
+    offs = np.concatenate([[0], np.cumsum(z[f"{method}_P_len"])])
+    for i, seed in enumerate(z["seeds"]):
+        inst = make_c2(int(seed))
+        A, b = _dev(inst.A, inst.b)
+        r = lhdm.solve(A, b) if method == "lhdm" else lhdm.lh_solve(A, b)
+        Po = [int(j) for j in z[f"{method}_P"][offs[i]:offs[i + 1]]]
+        xo = np.zeros(inst.A.shape[1])
+        xo[Po] = z[f"{method}_xP"][offs[i]:offs[i + 1]]
+        st, outer, inner, jd, npas = (int(v) for v in z[f"{method}_counters"][i])
+        x = r.x.cpu().numpy()
+        Pg = [int(j) for j in r.passive.cpu().numpy() if j >= 0]
+        tag = f"c2-{seed}-{method}"
+        print(f"[{tag}] gpu {r.info} oracle outer={outer} inner={inner} jd={jd}", flush=True)
+        assert st == 0 and r.info["status"] == 0, tag
+        assert r.info["kkt_residual"] <= KKT, tag
+        assert _rel(x, xo) <= XTOL, (tag, _rel(x, xo))
+        if float(xo[Po].min()) > SEP * float(np.abs(xo).max()) and float(x[Pg].min()) > SEP * float(np.abs(x).max()):
+            assert Pg == Po, tag
+            assert (r.info["outer_iters"], r.info["inner_iters"], r.info["jloop_drops"]) == (outer, inner, jd), tag
+        else:
+            # a column entered with a rounding-level coefficient (zero residual):
+            # the significant columns in the same order, the same outer steps
+            big = SIG * max(float(np.abs(xo).max()), float(np.abs(x).max()))
+            assert [j for j in Pg if x[j] > big] == [j for j in Po if xo[j] > big], tag
+            assert r.info["outer_iters"] == outer, tag
+        assert np.abs(x - inst.x_true).max() <= 1e-9 * np.abs(inst.x_true).max(), tag
