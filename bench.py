@@ -307,6 +307,8 @@ def main():
     ap.add_argument("--config", choices=("c1", "c2", "c4", "c5", "signflip", "illcond"),
                     help="measure another workload instead of the headline one (one JSON line)")
     ap.add_argument("--reps", type=int, default=10, help="timed repeats for --config")
+    ap.add_argument("--panel", choices=("auto", "householder"), default="auto",
+                    help="block factorisation of the whole-device engine (default: CholeskyQR2 where it applies)")
     ap.add_argument("--engine", choices=("auto", "fused", "fused2", "phased"), default="auto",
                     help="batched engine for --config c1|c4|c5 (default: the library's tuning table)")
     args = ap.parse_args()
@@ -348,7 +350,7 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     for _ in range(args.warmup):
-        r = lhdm.solve(A, b, delta=args.delta, max_outer=args.max_outer)
+        r = lhdm.solve(A, b, delta=args.delta, max_outer=args.max_outer, panel=args.panel)
         log("warmup lhdm", r.info)
     torch.cuda.synchronize()
 
@@ -358,7 +360,7 @@ def main():
     t0 = time.perf_counter()
     infos = []
     for _ in range(args.steps):
-        r = lhdm.solve(A, b, delta=args.delta, max_outer=args.max_outer)
+        r = lhdm.solve(A, b, delta=args.delta, max_outer=args.max_outer, panel=args.panel)
         infos.append(r.info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -393,12 +395,12 @@ def main():
         for d in (0.2, 0.5):
             if d == args.delta:
                 continue
-            r = lhdm.solve(A, b, delta=d)   # untimed first call
+            r = lhdm.solve(A, b, delta=d, panel=args.panel)   # untimed first call
             torch.cuda.synchronize()
             sw_infos = []
             t4 = time.perf_counter()
             for _ in range(args.sweep_steps):
-                sw_infos.append(lhdm.solve(A, b, delta=d).info)
+                sw_infos.append(lhdm.solve(A, b, delta=d, panel=args.panel).info)
             torch.cuda.synchronize()
             t5 = time.perf_counter()
             sweep[f"delta_{d}"] = {"value": args.sweep_steps / (t5 - t4), "unit": "solves/s",

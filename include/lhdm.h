@@ -78,6 +78,14 @@ extern "C" {
 #define LHDM_FLAG_BATCH_FUSED      8
 #define LHDM_FLAG_BATCH_FUSED2     16
 #define LHDM_FLAG_BATCH_PHASED     32
+/* Whole-device engine: factor every appended block column by column
+   (Algorithm 4's Householder steps, one cross-workgroup exchange per column)
+   instead of by default, for blocks of 2 to 32 columns, through CholeskyQR2 on
+   the block's Gram matrix with the Householder reflectors rebuilt from the
+   orthonormal factor.  Both produce the R, reflectors and compact-WY factor of
+   Algorithm 4 (up to rounding); the default falls back to the column-by-column
+   factorisation by itself when the block's Gram matrix is poorly conditioned. */
+#define LHDM_FLAG_PANEL_HOUSEHOLDER 64
 
 /* Solver parameters [host].  tau1, tau2, delta and kmax are the thresholds of
  * Algorithm 2 (delta is the tau_c of the Algorithm 3 signature); the defaults are
@@ -105,7 +113,8 @@ typedef struct lhdm_info {
     int32_t inner_iters;   /* inner (feasibility) iterations */
     int32_t jloop_drops;   /* columns dropped by the feasibility loop on J */
     int32_t n_passive;     /* |P| at exit */
-    int32_t reserved;
+    int32_t cq_panels;     /* whole-device engine: appended blocks factored by CholeskyQR2
+                              (the rest column by column); 0 on the one-workgroup engine */
     double  kkt_residual;  /* max(max_Z w+, max_P |w|) / (max_j ||a_j|| ||b||) */
     double  objective;     /* ||b - A x||^2 */
 } lhdm_info;

@@ -76,7 +76,7 @@ def _info_dicts(buf: torch.Tensor, count: int) -> List[dict]:
     out = []
     for i in range(count):
         inf = LhdmInfo.from_buffer_copy(raw[i * _lib.INFO_BYTES:(i + 1) * _lib.INFO_BYTES])
-        out.append({f: getattr(inf, f) for f, _ in LhdmInfo._fields_ if f != "reserved"})
+        out.append({f: getattr(inf, f) for f, _ in LhdmInfo._fields_})
     return out
 
 
@@ -111,16 +111,23 @@ ENGINES = {"auto": 0, "workgroup": 1, "device": 2}
 
 
 FLAG_NO_JLOOP = 4
+FLAG_PANEL_HOUSEHOLDER = 64
 
 
 def solve(A: torch.Tensor, b: torch.Tensor, *, tau1=0.6, tau2=0.15, delta=0.9, kmax=32, kkt_tol=1e-9,
-          max_outer=0, max_inner=0, engine="auto", no_jloop=False) -> Result:
+          max_outer=0, max_inner=0, engine="auto", no_jloop=False, panel="auto") -> Result:
     """LHDM solve of min ||A x - b|| s.t. x >= 0 (Algorithm 3 with Algorithm 2).
 
     ``engine``: "auto", "workgroup" (one workgroup per instance, m <= 2048) or
     "device" (one instance over the whole GPU).  ``no_jloop``: the variant of
-    Theorem 4 without the feasibility loop on J (needs tau1 = 1, tau2 <= 1/2)."""
+    Theorem 4 without the feasibility loop on J (needs tau1 = 1, tau2 <= 1/2).
+    ``panel`` (whole-device engine): "auto" factors blocks of 2 to 32 columns by
+    CholeskyQR2 with rebuilt reflectors, "householder" every block column by
+    column (Algorithm 4's steps)."""
+    if panel not in ("auto", "householder"):
+        raise ValueError(f"panel must be 'auto' or 'householder', not {panel!r}")
     flags = ENGINES[engine] | (FLAG_NO_JLOOP if no_jloop else 0)
+    flags |= FLAG_PANEL_HOUSEHOLDER if panel == "householder" else 0
     p = default_params(tau1=tau1, tau2=tau2, delta=delta, kmax=kmax, kkt_tol=kkt_tol, max_outer=max_outer,
                        max_inner=max_inner, flags=flags)
     return _single(A, b, "lhdm", p)

@@ -42,7 +42,7 @@ class LhdmInfo(ctypes.Structure):
         ("inner_iters", ctypes.c_int32),
         ("jloop_drops", ctypes.c_int32),
         ("n_passive", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("cq_panels", ctypes.c_int32),
         ("kkt_residual", ctypes.c_double),
         ("objective", ctypes.c_double),
     ]
@@ -87,6 +87,8 @@ SIGNATURES = {
     # test-only entry points (include/lhdm_testing.h)
     "lhdm_test_downdate": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _pi32, _vp, _vp, _vp, _pi32,
                                           _pi32]),
+    "lhdm_test_cq_factors": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                            ctypes.POINTER(ctypes.c_double)]),
 }
 
 _LIB = None

@@ -198,6 +198,7 @@ static DevParams dev_params(const lhdm_params* p, int n, int lh) {
     d.max_inner = p->max_inner > 0 ? p->max_inner : 3 * n;
     d.lh = lh;
     d.nojloop = (p->flags & LHDM_FLAG_NO_JLOOP) ? 1 : 0;
+    d.panel_hh = (p->flags & LHDM_FLAG_PANEL_HOUSEHOLDER) ? 1 : 0;
     return d;
 }
 

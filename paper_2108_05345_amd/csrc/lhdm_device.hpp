@@ -36,6 +36,7 @@ struct DevParams {
     int nojloop;   // feasibility loop on J not evaluated (Theorem 4 regime)
     int twin;      // positivity trick: the matrix is [A, -A], -A never formed
     int signflip;  // inner loop by the sign flip of the positivity-trick case
+    int panel_hh;  // whole-device engine: every panel column by column (no CholeskyQR2)
 };
 
 // One instance: caller buffers plus its workspace slice.

@@ -50,6 +50,8 @@ struct LgExtra {
     int pending;      // removals left over from a sweep capped at RQ positions
     int gident;       // 1: every candidate of the outer step was accepted
     int ccount;       // candidates collected by the selection (may exceed CAND_CAP)
+    int cq_ok;        // 1: this outer step's panel is factored by CholeskyQR2 (lg_cq_*)
+    int ncq;          // panels factored by CholeskyQR2 so far
     int gmap[KM];     // candidate panel column of accepted column q
     int seg_start[RQ + 1];
     int seg_off[RQ + 1];
@@ -91,6 +93,7 @@ struct LgArgs {
     int* candi;       // CAND_CAP: and column indices
     u64* pll;         // 2 * (2 PNW + 2) x (KM + 1) : panel partials (dots, pivot row)
     double* wpart;    // ceil(m / QCB) x kq x m : pass-1 partial products of the Q update
+    double* cq;       // CQ_DOUBLES: small factors of the CholeskyQR2 panel (R1, U R2, Y1, z)
     Mirror* hmir;     // device view of the host mirror
 };
 
@@ -283,6 +286,8 @@ __global__ __launch_bounds__(WG) void lg_init_ctl(LgArgs a, const unsigned long 
         s.kr = 0;
         a.ex->err = 0;
         a.ex->nrecomp = 0;
+        a.ex->cq_ok = 0;
+        a.ex->ncq = 0;
     }
     ctl_store(s, a.ctl);
 }
@@ -700,15 +705,205 @@ __device__ inline void gram_entries(const double* part, int nblk, int n, Keep ke
     }
 }
 
+// --------------------------------------------------------------------------
+// Panel factorisation by CholeskyQR2 with Householder reconstruction
+// --------------------------------------------------------------------------
+// The accepted block's projected columns X = G[n_P:m, J] (2 <= kr <= CQ_MAX)
+// are factored as X = Q R from Gram matrices: R1 is the Cholesky factor of
+// X^T X (whose entries lg_greedy already holds), Q1 = X R1^{-1}, R2 the
+// Cholesky factor of Q1^T Q1, Q = Q1 R2^{-1} and R = R2 R1 (CholeskyQR2,
+// Fukaya, Nakatsukasa, Yanagisawa and Yamamoto, 2014).  The reflectors of
+// Algorithm 4 are then rebuilt from Q (Ballard, Demmel, Grigori, Jacquelin,
+// Nguyen and Solomonik, 2015): an LU factorisation without pivoting of Q's
+// top kr x kr block minus S, S = diag(s_t) with s_t the opposite of the sign
+// of step t's pivot (so every pivot of U is at least 1 in magnitude), gives
+// Q - [S; 0] = Y U with Y unit lower trapezoidal.  Y is the matrix of
+// reflectors with unit diagonal, S R the new diagonal block of R (the signs of
+// the column-by-column factorisation), and the rows of Y below the top block
+// are y = q U^{-1} = q1 (U R2)^{-1}.  The compact-WY factor T follows from
+// Y^T Y (lg_panel_b) with tau_t = 2 / ||y_t||^2, which keeps the block
+// reflector orthogonal to rounding.  The row passes multiply 16-row tiles by
+// the explicit triangular inverses R1^{-1} and (U R2)^{-1} on the matrix
+// cores; the small factors are formed by one wave with the matrices in
+// registers (one column per lane).  Two row passes over the panel and two
+// one-workgroup steps replace the per-column exchange; a block whose Gram
+// matrix is far from well conditioned goes the column-by-column way.
+constexpr int CQ_MAX = 32;          // widest panel (one column per lane of a wave)
+constexpr int CQ_ROWS = 128;        // panel rows per workgroup of the row passes
+constexpr int CQ_XW = 49;           // LDS row of the row passes: three 16-column tiles and a pad
+constexpr double CQ_SIN2 = 1e-6;    // smallest squared sine of a column against the earlier ones
+constexpr double CQ_ORTH = 1e-4;    // largest |Q1^T Q1 - I| entry taken by the second pass
+constexpr int CQ_SQ = CQ_MAX * CQ_MAX;
+constexpr int CQ_R1 = 0;            // R1 (row-major, CQ_MAX x CQ_MAX, zero outside kr x kr)
+constexpr int CQ_R1I = CQ_SQ;       // R1^{-1}
+constexpr int CQ_M2I = 2 * CQ_SQ;   // (U R2)^{-1}
+constexpr int CQ_Y1 = 3 * CQ_SQ;    // top block of Y (unit lower)
+constexpr int CQ_Z = 4 * CQ_SQ;     // z = T^T (Y^T bt)
+constexpr int CQ_DOUBLES = 4 * CQ_SQ + CQ_MAX;
+// dynamic LDS of the second row pass (inside lg_panel_mw): the row block and (U R2)^{-1}
+constexpr size_t CQ_P2_LDS = sizeof(double) * (CQ_ROWS * CQ_XW + CQ_MAX * (CQ_MAX + 1));
+static_assert(WG == 2 * CQ_ROWS && NW == 4, "row passes: two threads per row, four waves");
+typedef lds_double CqRow[CQ_MAX + 1];   // a row of a small matrix in LDS
+typedef lds_double CqX[CQ_XW];          // a row of a row block in LDS
+
+// Cholesky factor and its inverse in one pass, by one wave.  G: an n x n
+// symmetric positive definite matrix in LDS (n <= CQ_MAX, upper triangle
+// read).  The elimination runs on blockdiag(G, I) (steps past n are identity
+// steps, so no step needs a guard) augmented by the identity: lane j < 32
+// holds column j of the matrix (its upper triangle), lane 32 + c column c of
+// the identity.  Step t scales row t by the inverse square root of its pivot
+// and subtracts R[t][i] times it from row i > t (the multipliers are the
+// scaled row's entries, broadcast through rowbuf, 64 doubles of LDS).  The
+// matrix lanes end with R (R^T R = G), the identity lanes with R^{-T}.  R and
+// Ri (= R^{-1}) are written whole, zero outside the n x n triangle.  Returns
+// the smallest R[t][t]^2 / G[t][t] over t < n (the squared sine of column t's
+// angle with the span of the columns before it), or -1 when a pivot is not a
+// positive finite number.  All lanes of one wave call it.
+// 1 / sqrt(d) and 1 / u: the hardware estimates refined by two Newton steps
+// each (every step squares the relative error).
+__device__ __forceinline__ double rsqrt_nr(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-(d * y), y, 1.0), y);
+    return y;
+}
+__device__ __forceinline__ double rcp_nr(double u) {
+    double y = __builtin_amdgcn_rcp(u);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(y, fma(-u, y, 1.0), y);
+    return y;
+}
+
+__device__ __forceinline__ double chol_inv_wave(const CqRow* G, int n, CqRow* R, CqRow* Ri, lds_double* rowbuf) {
+    const int lane = threadIdx.x & 63, j = lane & 31;
+    const bool mat = lane < 32;
+    double g[CQ_MAX];
+#pragma unroll
+    for (int i = 0; i < CQ_MAX; ++i) {
+        const double gij = G[i][j];
+        g[i] = (mat && j < n) ? ((i <= j) ? gij : 0.0) : (i == j ? 1.0 : 0.0);
+    }
+    // the next pivot is taken ahead of the broadcast: lane t + 1's own
+    // multiplier is its own entry of the scaled row
+    double dn = readlane_d(g[0], 0);
+#pragma unroll
+    for (int t = 0; t < CQ_MAX; ++t) {
+        const double ri = rsqrt_nr(dn);
+        const double v = (lane == t) ? dn * ri : g[t] * ri;
+        g[t] = v;
+        rowbuf[lane] = v;
+        if (t + 1 < CQ_MAX) dn = readlane_d(fma(-v, v, g[t + 1]), t + 1);
+        wave_lds_sync();   // the other lanes' entries of the row are read below
+        // all multipliers in one LDS round trip, then the updates
+        double mu[CQ_MAX];
+#pragma unroll
+        for (int i = t + 1; i < CQ_MAX; ++i) mu[i] = rowbuf[i];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = t + 1; i < CQ_MAX; ++i) g[i] = fma(-mu[i], v, g[i]);
+        wave_lds_sync();   // before the next step overwrites the row
+    }
+    // pivot test: lane t < n holds R[t][t] in g[t]
+    double rtt = 0.0;
+#pragma unroll
+    for (int t = 0; t < CQ_MAX; ++t) rtt = (lane == t) ? g[t] : rtt;
+    double q = 1.0;
+    if (mat && j < n) {
+        const double ratio = rtt * rtt / G[j][j];
+        q = (rtt > 0.0 && rtt < INFINITY && ratio == ratio) ? ratio : -1.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) q = fmin(q, __shfl_xor(q, o, 64));
+    const bool live = j < n;
+#pragma unroll
+    for (int i = 0; i < CQ_MAX; ++i) {
+        if (mat) R[i][j] = (live && i <= j) ? g[i] : 0.0;
+        else Ri[j][i] = (live && i >= j && i < n) ? g[i] : 0.0;
+    }
+    return q;
+}
+
+// LU factorisation without pivoting of W - S and the inverse of U in one
+// pass, by one wave (the reconstruction's LU).  W: n x n in LDS (n <= CQ_MAX,
+// zero outside n x n); S = diag(s_t), s_t = +1 when step t's pivot is negative
+// and -1 otherwise, so every pivot of U is at least 1 in magnitude.  Column
+// elimination on [W; I]: lane r < 32 holds row r of W, lane 32 + q row q of
+// the identity; step t takes the pivot from lane t, scales column t by its
+// inverse and subtracts U[t][c] times it from column c > t (row t of U, from
+// lane t, broadcast through rowbuf).  Steps past n meet a zero row and act as
+// identity steps.  The matrix lanes end with the unit lower L (W - S = L U),
+// the identity lanes with U^{-1}.  L and Ui are written whole (zero outside n x
+// n, L with its unit diagonal); sg[t] = s_t.
+__device__ __forceinline__ void lu_inv_wave(const CqRow* W, int n, CqRow* L, CqRow* Ui, lds_double* sg,
+                                            lds_double* rowbuf) {
+    const int lane = threadIdx.x & 63, r = lane & 31;
+    const bool mat = lane < 32;
+    double w[CQ_MAX];
+#pragma unroll
+    for (int c = 0; c < CQ_MAX; ++c) {
+        const double wrc = W[r][c];
+        w[c] = mat ? wrc : (c == r ? 1.0 : 0.0);
+    }
+    // the next pivot is taken ahead of the broadcast (U[t][t + 1] by readlane)
+    double pn = readlane_d(w[0], 0);
+#pragma unroll
+    for (int t = 0; t < CQ_MAX; ++t) {
+        const double piv = pn;
+        const double st = (piv < 0.0) ? 1.0 : -1.0;
+        const double ru = rcp_nr(piv - st);
+        if (lane == t) {
+#pragma unroll
+            for (int c = t + 1; c < CQ_MAX; ++c) rowbuf[c] = w[c];
+        }
+        if (lane == 0) sg[t] = st;
+        const double wt = (lane == t) ? 1.0 : w[t] * ru;
+        w[t] = wt;
+        if (t + 1 < CQ_MAX) pn = readlane_d(fma(-readlane_d(w[t + 1], t), wt, w[t + 1]), t + 1);
+        wave_lds_sync();   // lane t's row is read by every lane below
+        // all of row t of U in one LDS round trip, then the updates
+        double ut[CQ_MAX];
+#pragma unroll
+        for (int c = t + 1; c < CQ_MAX; ++c) ut[c] = rowbuf[c];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = t + 1; c < CQ_MAX; ++c) w[c] = fma(-ut[c], wt, w[c]);
+        wave_lds_sync();   // before the next step overwrites the row
+    }
+    const bool live = r < n;
+#pragma unroll
+    for (int c = 0; c < CQ_MAX; ++c) {
+        if (mat) L[r][c] = (live && c < n) ? ((c < r) ? w[c] : (c == r) ? 1.0 : 0.0) : 0.0;
+        else Ui[r][c] = (live && c >= r && c < n) ? w[c] : 0.0;
+    }
+}
+
+// C = A B for 32 x 32 matrices in LDS on the matrix cores, one 16 x 16 tile
+// of C per wave (all four waves call it); C must not alias A or B.
+__device__ __forceinline__ void mm32(const CqRow* A, const CqRow* B, CqRow* C) {
+    const int lane = threadIdx.x & 63, wv = wave_index();
+    const int ti = wv >> 1, tj = wv & 1, r = lane & 15, g = lane >> 4;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < CQ_MAX; kk += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[16 * ti + r][kk + g], B[kk + g][16 * tj + r], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) C[16 * ti + 4 * v + g][16 * tj + r] = acc[v];
+}
+
 // Deviation maximization's greedy test (Algorithm 2) on the candidates' Gram
 // matrix, or the single column of Lawson-Hanson.  The pairwise cosines are
 // evaluated in parallel into bit masks (bit a of bad[t]: |cos(a, t)| >= delta);
 // the greedy scan in candidate order is then one mask test per candidate.
 // Accepted candidates' panel columns go to gmap; the panel factorisation
 // reads the candidate panel through it.
-__global__ __launch_bounds__(WG) void lg_greedy(LgArgs a, const double* part) {
+// With cq set (and 2 <= k <= CQ_MAX accepted) it also factors the accepted
+// columns' Gram matrix for the CholeskyQR2 panel (R1 into a.cq) and sets
+// ex->cq_ok when every column keeps a squared sine of at least CQ_SIN2 against
+// the ones before it; otherwise ex->cq_ok = 0.
+__global__ __launch_bounds__(WG, 1) void lg_greedy(LgArgs a, const double* part, int cq) {
     __shared__ WgShared s;
     __shared__ double Tl[KM][KM + 1];
+    __shared__ double Gs_[CQ_MAX][CQ_MAX + 1], R1s_[CQ_MAX][CQ_MAX + 1], R1is_[CQ_MAX][CQ_MAX + 1];
+    __shared__ double rowbuf_[64];
     __shared__ double sq[KM];
     __shared__ unsigned long long bad[KM];
     __shared__ int gm[KM];
@@ -762,6 +957,29 @@ __global__ __launch_bounds__(WG) void lg_greedy(LgArgs a, const double* part) {
     }
     __syncthreads();
     if (tid < s.k) ex->gmap[tid] = gm[tid];
+    const int na = s.k;
+    if (cq && c > 1 && na >= 2 && na <= CQ_MAX) {
+        // R1 and R1^{-1} of the accepted columns (one wave)
+        CqRow* Gs = (CqRow*)Gs_;
+        CqRow* R1s = (CqRow*)R1s_;
+        CqRow* R1is = (CqRow*)R1is_;
+        for (int e = tid; e < CQ_SQ; e += WG) {
+            const int q = e / CQ_MAX, r = e % CQ_MAX;
+            Gs[q][r] = (q <= r && r < na) ? Tl[gm[q]][gm[r]] : 0.0;
+        }
+        __syncthreads();
+        if (wave_index() == 0) {
+            const double sin2 = chol_inv_wave(Gs, na, R1s, R1is, (lds_double*)rowbuf_);
+            if (tid == 0) ex->cq_ok = (sin2 >= CQ_SIN2) ? 1 : 0;
+        }
+        __syncthreads();
+        for (int e = tid; e < CQ_SQ; e += WG) {
+            a.cq[CQ_R1 + e] = R1s[e / CQ_MAX][e % CQ_MAX];
+            a.cq[CQ_R1I + e] = R1is[e / CQ_MAX][e % CQ_MAX];
+        }
+    } else if (tid == 0) {
+        ex->cq_ok = 0;
+    }
     if (tid == 0) s.kr = s.k;
     ctl_store(s, a.ctl);
 }
@@ -775,6 +993,300 @@ __device__ inline void compact_panel_row(const Prob& p, const int* gmap, int kr,
 #pragma unroll
     for (int q = 0; q < KM; ++q)
         if (q < kr) p.G[(size_t)q * p.m + row] = v[q];
+}
+
+// Stage a CQ_ROWS x 48 row block into xs: xs[i][q] = src(q, i) for i < nr
+// and q < nc, else 0 (column 48, the pad, is not touched).  Each thread owns
+// one row and every other column, and issues all its loads before its first
+// LDS store.
+template <typename F>
+__device__ __forceinline__ void cq_stage(CqX* xs, int nr, int nc, F src) {
+    const int i = threadIdx.x % CQ_ROWS, h = threadIdx.x / CQ_ROWS;
+    double v[24];
+#pragma unroll
+    for (int u = 0; u < 24; ++u) {
+        const int q = h + 2 * u;
+        v[u] = (i < nr && q < nc) ? src(q, i) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 24; ++u) xs[i][h + 2 * u] = v[u];
+}
+
+// xs[:, 0:ncol] = (xs[:, 0:32] M)[:, 0:ncol] for the row block in LDS (M 32 x
+// 32 in LDS) on the matrix cores.  Wave w takes the 16-row tiles w and w + 4
+// whole (both column tiles), so it overwrites only rows no other wave reads.
+__device__ __forceinline__ void cq_rows_times(CqX* xs, const CqRow* M, int ncol) {
+    const int lane = threadIdx.x & 63, wv = wave_index(), r = lane & 15, g = lane >> 4;
+    for (int rb = wv; rb < CQ_ROWS / 16; rb += NW) {
+        d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+#pragma unroll
+        for (int kk = 0; kk < CQ_MAX; kk += 4) {
+            const double x = xs[16 * rb + r][kk + g];
+            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, M[kk + g][r], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, M[kk + g][16 + r], a1, 0, 0, 0);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * rb + 4 * v + g;
+            if (r < ncol) xs[row][r] = a0[v];
+            if (16 + r < ncol) xs[row][16 + r] = a1[v];
+        }
+    }
+}
+
+// Partial Gram X^T X of the row block xs (nc columns; its columns nc .. 47
+// and its rows past the panel zero) into out (64 x 64, row-major, upper 16 x
+// 16 tiles: the layout of lg_gram_part), on the matrix cores.
+__device__ __forceinline__ void cq_gram_tiles(const CqX* xs, int nc, double* out) {
+    const int lane = threadIdx.x & 63, wv = wave_index(), g = lane >> 4;
+    const int nt = (nc + 15) / 16;
+    int tile = 0;
+    for (int ti = 0; ti < nt; ++ti)
+        for (int tj = ti; tj < nt; ++tj, ++tile) {
+            if ((tile % NW) != wv) continue;
+            d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+            const int ca = ti * 16 + (lane & 15), cb = tj * 16 + (lane & 15);
+#pragma unroll 4
+            for (int r = 0; r < CQ_ROWS; r += 8) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[r + g][ca], xs[r + g][cb], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[r + 4 + g][ca], xs[r + 4 + g][cb], acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                out[(ti * 16 + 4 * v + (lane >> 4)) * 64 + tj * 16 + (lane & 15)] = acc0[v] + acc1[v];
+        }
+}
+
+// CholeskyQR2 panel, first row pass.  Workgroup w < nb = ceil((m - n_P) /
+// CQ_ROWS) takes panel rows n_P + w CQ_ROWS ...: Q1 = X R1^{-1} for its rows,
+// Q1 into W (column-major) and the block's partial Q1^T Q1 into slot w of
+// gpart.  The workgroups past nb copy the accepted candidates' rows above the
+// panel into the new columns of R.
+__global__ __launch_bounds__(WG) void lg_cq_p1(LgArgs a) {
+    __shared__ double xs_[CQ_ROWS][CQ_XW];
+    __shared__ double Mi_[CQ_MAX][CQ_MAX + 1];
+    __shared__ int gml[CQ_MAX];
+    const LgExtra* ex = a.ex;
+    if (!ex->cq_ok) return;
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int r0 = ctl->nP, kr = ctl->kr, m = p.m, tid = threadIdx.x;
+    const int nb = (m - r0 + CQ_ROWS - 1) / CQ_ROWS;
+    if ((int)blockIdx.x >= nb) {
+        const int row = ((int)blockIdx.x - nb) * WG + tid;
+        int gm[CQ_MAX], sl[CQ_MAX];
+#pragma unroll
+        for (int t = 0; t < CQ_MAX; ++t) {
+            gm[t] = (t < kr) ? ex->gmap[t] : 0;
+            sl[t] = (t < kr) ? p.slot[r0 + t] : 0;
+        }
+        if (row < r0) {
+            double v[CQ_MAX];
+#pragma unroll
+            for (int t = 0; t < CQ_MAX; ++t) v[t] = (t < kr) ? p.G[(size_t)gm[t] * m + row] : 0.0;
+#pragma unroll
+            for (int t = 0; t < CQ_MAX; ++t)
+                if (t < kr) p.R[(size_t)sl[t] * p.kc + row] = v[t];
+        }
+        return;
+    }
+    CqX* xs = (CqX*)xs_;
+    CqRow* Mi = (CqRow*)Mi_;
+    const int rs = r0 + (int)blockIdx.x * CQ_ROWS, nr = min(m - rs, CQ_ROWS);
+    if (tid < CQ_MAX) gml[tid] = (tid < kr) ? ex->gmap[tid] : 0;
+    double mr[CQ_SQ / WG];
+#pragma unroll
+    for (int u = 0; u < CQ_SQ / WG; ++u) mr[u] = a.cq[CQ_R1I + tid + WG * u];
+    __syncthreads();
+    cq_stage(xs, nr, kr, [&](int q, int i) { return p.G[(size_t)gml[q] * m + rs + i]; });
+#pragma unroll
+    for (int u = 0; u < CQ_SQ / WG; ++u) {
+        const int e = tid + WG * u;
+        Mi[e / CQ_MAX][e % CQ_MAX] = mr[u];
+    }
+    __syncthreads();
+    cq_rows_times(xs, Mi, CQ_MAX);   // columns >= kr stay zero (R1^{-1} is zero there)
+    __syncthreads();
+    {
+        const int i = tid % CQ_ROWS, h = tid / CQ_ROWS;
+#pragma unroll
+        for (int u = 0; u < CQ_MAX / 2; ++u) {
+            const int q = h + 2 * u;
+            if (q < kr && i < nr) p.W[(size_t)q * m + rs + i] = xs[i][q];
+        }
+    }
+    cq_gram_tiles(xs, kr, a.gpart + (size_t)blockIdx.x * 64 * 64);
+}
+
+// CholeskyQR2 panel, the small factors (one workgroup): R2 from the summed
+// Q1^T Q1 (ex->cq_ok = 0 when an entry of Q1^T Q1 - I exceeds CQ_ORTH or a
+// pivot fails: the column-by-column panel then runs), R = R2 R1, Q's top block
+// Q1_top R2^{-1}, its LU with signs (U, S, unit lower Y1), the new columns' rows
+// n_P .. n_P + t of R (S R, diagonal into ctl->beta), and (U R2)^{-1} = R2^{-1}
+// U^{-1} and Y1 for the second row pass.  The serial parts (Cholesky, the two
+// triangular inverses, the LU) run on one wave with the matrices in
+// registers; the products on the matrix cores.
+__global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
+    // lifetimes: G2 then Q_top in A0; R1 then (U R2)^{-1} in A1; Q1_top then U^{-1} in A2
+    __shared__ double A0_[CQ_MAX][CQ_MAX + 1], A1_[CQ_MAX][CQ_MAX + 1], A2_[CQ_MAX][CQ_MAX + 1];
+    __shared__ double R2_[CQ_MAX][CQ_MAX + 1], R2i_[CQ_MAX][CQ_MAX + 1], Rr_[CQ_MAX][CQ_MAX + 1];
+    __shared__ double L_[CQ_MAX][CQ_MAX + 1];
+    __shared__ double sg_[CQ_MAX], rowbuf_[64];
+    __shared__ int ok;
+    LgExtra* ex = a.ex;
+    if (!ex->cq_ok) return;
+    Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int r0 = ctl->nP, kr = ctl->kr, m = p.m, tid = threadIdx.x, lane = tid & 63, wv = wave_index();
+    const int nb = (m - r0 + CQ_ROWS - 1) / CQ_ROWS;
+    CqRow* G2 = (CqRow*)A0_;
+    CqRow* Qt = (CqRow*)A0_;
+    CqRow* R1 = (CqRow*)A1_;
+    CqRow* M2i = (CqRow*)A1_;
+    CqRow* Q1t = (CqRow*)A2_;
+    CqRow* Ui = (CqRow*)A2_;
+    CqRow* R2 = (CqRow*)R2_;
+    CqRow* R2i = (CqRow*)R2i_;
+    CqRow* Rr = (CqRow*)Rr_;
+    CqRow* L = (CqRow*)L_;
+    lds_double* sg = (lds_double*)sg_;
+    lds_double* rowbuf = (lds_double*)rowbuf_;
+    {
+        double lr[CQ_SQ / WG], lw[CQ_SQ / WG];
+#pragma unroll
+        for (int u = 0; u < CQ_SQ / WG; ++u) {
+            const int e = tid + WG * u, i = e / CQ_MAX, t = e % CQ_MAX;
+            lr[u] = a.cq[CQ_R1 + e];
+            lw[u] = (i < kr && t < kr) ? p.W[(size_t)t * m + r0 + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < CQ_SQ / WG; ++u) {
+            const int e = tid + WG * u, i = e / CQ_MAX, t = e % CQ_MAX;
+            R1[i][t] = lr[u];
+            Q1t[i][t] = lw[u];
+            G2[i][t] = 0.0;
+        }
+    }
+    __syncthreads();
+    gram_entries(a.gpart, nb, kr, [](int i, int t) { return i <= t; }, [&](int i, int t, double v) { G2[i][t] = v; });
+    __syncthreads();
+    if (wv == 0) {
+        // largest deviation of Q1^T Q1 from the identity (upper triangle)
+        const int c = lane & 31;
+        double dev = 0.0;
+#pragma unroll
+        for (int i = 0; i < CQ_MAX; ++i) {
+            const double e = fabs(G2[i][c] - (i == c ? 1.0 : 0.0));
+            dev = (i <= c && lane < kr) ? fmax(dev, e) : dev;
+        }
+        if (!(dev == dev)) dev = INFINITY;
+        for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, 64));
+        const double piv = chol_inv_wave(G2, kr, R2, R2i, rowbuf);
+        if (lane == 0) ok = (piv > 0.0 && dev <= CQ_ORTH) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!ok) {
+        if (tid == 0) ex->cq_ok = 0;
+        return;
+    }
+    mm32(R2, R1, Rr);     // R = R2 R1
+    mm32(Q1t, R2i, Qt);   // Q's top block (G2 is no longer needed)
+    __syncthreads();
+    if (wv == 0) lu_inv_wave(Qt, kr, L, Ui, sg, rowbuf);   // Q1_top is no longer needed
+    __syncthreads();
+    mm32(R2i, Ui, M2i);   // (U R2)^{-1}; R1 is no longer needed
+    __syncthreads();
+    {
+        int sl[CQ_SQ / WG];
+#pragma unroll
+        for (int u = 0; u < CQ_SQ / WG; ++u) {
+            const int j = (tid + WG * u) % CQ_MAX;
+            sl[u] = (j < kr) ? p.slot[r0 + j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < CQ_SQ / WG; ++u) {
+            const int e = tid + WG * u, i = e / CQ_MAX, j = e % CQ_MAX;
+            a.cq[CQ_M2I + e] = M2i[i][j];
+            a.cq[CQ_Y1 + e] = L[i][j];
+            if (i <= j && j < kr) p.R[(size_t)sl[u] * p.kc + r0 + i] = sg[i] * Rr[i][j];
+        }
+    }
+    if (tid < kr) ctl->beta[tid] = sg[tid] * Rr[tid][tid];
+}
+
+// CholeskyQR2 panel, second row pass (run by lg_panel_mw's workgroups w <
+// nb): the reflectors.  Rows n_P .. n_P + kr - 1 take Y1 (unit diagonal, zeros
+// above), the others y = q1 (U R2)^{-1}; y into V (column-major) and V^T
+// (row-major), and the block's partial Gram of [Y, bt] (kr + 1 columns: Y^T Y
+// and Y^T bt) into slot w of gpart.  dyn: CQ_P2_LDS bytes of LDS.
+__device__ inline void cq_second_pass(const LgArgs& a, lds_double* dyn) {
+    const Ctl* ctl = a.ctl;
+    const Prob& p = a.p;
+    const int r0 = ctl->nP, kr = ctl->kr, m = p.m, tid = threadIdx.x;
+    const int nb = (m - r0 + CQ_ROWS - 1) / CQ_ROWS;
+    if ((int)blockIdx.x >= nb) return;
+    CqX* xs = (CqX*)dyn;
+    CqRow* Mi = (CqRow*)(dyn + CQ_ROWS * CQ_XW);
+    const int rs = r0 + (int)blockIdx.x * CQ_ROWS, nr = min(m - rs, CQ_ROWS);
+    double mr[CQ_SQ / WG];
+#pragma unroll
+    for (int u = 0; u < CQ_SQ / WG; ++u) mr[u] = a.cq[CQ_M2I + tid + WG * u];
+    cq_stage(xs, nr, kr + 1,
+             [&](int q, int i) { return (q < kr) ? p.W[(size_t)q * m + rs + i] : p.bt[rs + i]; });
+#pragma unroll
+    for (int u = 0; u < CQ_SQ / WG; ++u) {
+        const int e = tid + WG * u;
+        Mi[e / CQ_MAX][e % CQ_MAX] = mr[u];
+    }
+    __syncthreads();
+    cq_rows_times(xs, Mi, kr);   // rows of (U R2)^{-1} past kr are zero: bt does not enter
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        // the top rows: Y1 (block 0 starts at row n_P; kr <= nr)
+        double y[CQ_SQ / WG];
+#pragma unroll
+        for (int u = 0; u < CQ_SQ / WG; ++u) y[u] = a.cq[CQ_Y1 + tid + WG * u];
+#pragma unroll
+        for (int u = 0; u < CQ_SQ / WG; ++u) {
+            const int e = tid + WG * u, i = e / CQ_MAX, q = e % CQ_MAX;
+            if (i < kr && q < kr) xs[i][q] = y[u];
+        }
+        __syncthreads();
+    }
+    {
+        const int i = tid % CQ_ROWS, h = tid / CQ_ROWS;
+#pragma unroll
+        for (int u = 0; u < CQ_MAX / 2; ++u) {
+            const int q = h + 2 * u;
+            if (q < kr && i < nr) p.V[(size_t)q * m + rs + i] = xs[i][q];
+        }
+        for (int e = tid; e < nr * kr; e += WG) {
+            const int ii = e / kr, q = e % kr;
+            p.Vt[(size_t)(rs + ii) * p.kq + q] = xs[ii][q];
+        }
+    }
+    cq_gram_tiles(xs, kr + 1, a.gpart + (size_t)blockIdx.x * 64 * 64);
+}
+
+// CholeskyQR2 panel: bt[n_P + kr : m] -= Y z with z = T^T (Y^T bt) from
+// lg_panel_b (which updates the rows n_P .. n_P + kr - 1 itself).
+__global__ __launch_bounds__(WG) void lg_cq_bt(LgArgs a) {
+    if (!a.ex->cq_ok) return;
+    const Prob& p = a.p;
+    const int r0 = a.ctl->nP, kr = a.ctl->kr, m = p.m, tid = threadIdx.x;
+    double z[CQ_MAX];
+#pragma unroll
+    for (int t = 0; t < CQ_MAX; ++t) z[t] = (t < kr) ? a.cq[CQ_Z + t] : 0.0;
+    for (int row = r0 + kr + (int)blockIdx.x * WG + tid; row < m; row += (int)gridDim.x * WG) {
+        double v[CQ_MAX];
+#pragma unroll
+        for (int t = 0; t < CQ_MAX; ++t) v[t] = (t < kr) ? p.V[(size_t)t * m + row] : 0.0;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < CQ_MAX; ++t) acc = fma(v[t], z[t], acc);
+        p.bt[row] -= acc;
+    }
 }
 
 // Householder QR of the panel G[n_P:m, 0:kr] with bt[n_P:m] carried as column
@@ -797,6 +1309,10 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
     __shared__ double dpart[NW][PSLOT];   // per gathering wave: dots of the pivot column with columns t .. kr
     __shared__ double prow[PSLOT];        // pivot row entries of columns t .. kr
     __shared__ double betal[PSLOT];       // new diagonal entries (the same in every workgroup)
+    if (a.ex->cq_ok) {   // the CholeskyQR2 kernels factor this panel: their second row pass
+        cq_second_pass(a, (lds_double*)pan);
+        return;
+    }
     const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
     const int r0 = ctl->nP, kr = ctl->kr, m = p.m;
@@ -1088,18 +1604,31 @@ __device__ inline void wy_t_columns(const double (*Wl)[KM + 1], const double* ta
     }
 }
 
-// part: nblk partial Gram blocks of V (the panel's workgroups, or 128-row blocks)
-__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, int nblk) {
+// part: nblk partial Gram blocks of V (the panel's workgroups, or 128-row
+// blocks), or, when the CholeskyQR2 kernels factored the panel, nblk_cq
+// blocks of [V, bt] (the CholeskyQR2 second row pass): then tau_t = 2 / ||v_t||^2, and this kernel
+// also forms z = T^T (V^T bt) for lg_cq_bt and the rows n_P .. n_P + kr - 1 of
+// bt = (I - V T^T V^T) bt.
+__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, int nblk, int nblk_cq) {
     __shared__ WgShared s;
     __shared__ double Tl[KM][KM + 1];
     __shared__ double Wl[KM][KM + 1];
+    __shared__ double zl[CQ_MAX];
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
     const Prob& p = a.p;
     const int kr = s.kr, kq = p.kq, tid = threadIdx.x;
+    const bool cq = a.ex->cq_ok != 0;
     // T of the compact WY form, from V^T V (summed from the partial blocks)
-    gram_entries(part, nblk, kr, [](int i, int t) { return i < t; },   // consecutive threads: consecutive t
-                 [&](int i, int t, double v) { Wl[i][t] = v; });
+    if (cq) {
+        gram_entries(part, nblk_cq, kr + 1, [](int i, int t) { return i <= t; },
+                     [&](int i, int t, double v) { Wl[i][t] = v; });
+        __syncthreads();
+        if (tid < kr) s.tau[tid] = 2.0 / Wl[tid][tid];
+    } else {
+        gram_entries(part, nblk, kr, [](int i, int t) { return i < t; },   // consecutive threads: consecutive t
+                     [&](int i, int t, double v) { Wl[i][t] = v; });
+    }
     __syncthreads();
     if (tid < 64) {
         if (kr <= 32) {
@@ -1122,8 +1651,32 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, i
         const int i = e % kq, t = e / kq;
         p.T[(size_t)t * kq + i] = (i < kr) ? Tl[i][t] : 0.0;
     }
-    // feasibility loop on J: longest prefix of J whose own LS components are positive
     const int r0 = s.nP;
+    if (cq) {
+        // z = T^T (V^T bt) (T is upper triangular, zero below its diagonal in Tl)
+        if (tid < kr) {
+            double z = 0.0;
+#pragma unroll
+            for (int i = 0; i < CQ_MAX; ++i)
+                if (i < kr) z = fma(Tl[i][tid], Wl[i][kr], z);
+            zl[tid] = z;
+            a.cq[CQ_Z + tid] = z;
+        }
+        double y1[CQ_MAX];   // row tid of the top block of V
+#pragma unroll
+        for (int t = 0; t < CQ_MAX; ++t) y1[t] = (tid < kr && t < kr) ? a.cq[CQ_Y1 + tid * CQ_MAX + t] : 0.0;
+        __syncthreads();
+        if (tid < kr) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < CQ_MAX; ++t)
+                if (t < kr) acc = fma(y1[t], zl[t], acc);
+            p.bt[r0 + tid] -= acc;
+        }
+        if (tid == 0) a.ex->ncq += 1;
+        __syncthreads();
+    }
+    // feasibility loop on J: longest prefix of J whose own LS components are positive
     for (int e = tid; e < kr * kr; e += WG) {
         const int i = e % kr, t = e / kr;
         Wl[i][t] = (i <= t) ? p.R[(size_t)p.slot[r0 + t] * p.kc + r0 + i] : 0.0;
@@ -1139,6 +1692,7 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, i
         double rrow[KM];
 #pragma unroll
         for (int j = 0; j < KM; ++j) rrow[j] = (lk && j > lane && j < kr) ? Wl[lane][j] * rinv : 0.0;
+        // (with cq, this thread itself wrote bt[r0 + lane] above)
         const double bl = lk ? p.bt[r0 + lane] * rinv : 0.0;
         int k = kr;
         while (k > 0 && !a.prm.nojloop) {   // not evaluated in the Theorem 4 regime
@@ -1465,6 +2019,7 @@ __global__ __launch_bounds__(WG) void lg_finalize(LgArgs a) {
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
     wg.finalize();
+    if (threadIdx.x == 0 && a.p.info) a.p.info->cq_panels = a.ex->ncq;
 }
 
 // --------------------------------------------------------------------------
@@ -2949,7 +3504,7 @@ __global__ __launch_bounds__(64 * (1 + QNL)) void lg_qrot(LgArgs a, int skipbt) 
 struct LargeLayout {
     size_t slot, ybuf, Vt, Dt, rot, ocol, lcnt, roff, flt, flg, recomp, rpart, gpart, selv, seli, candw, candi, ctl,
         ex, misc,
-        ppart, wfall, wpart, total;
+        ppart, wfall, wpart, cq, total;
 };
 
 static LargeLayout large_layout(int m, int n, int kmax) {
@@ -2985,6 +3540,7 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.misc, 256);
     put(L.wfall, sizeof(double) * (size_t)n);
     put(L.wpart, sizeof(double) * (size_t)((m + QCB - 1) / QCB) * kq * m);
+    put(L.cq, sizeof(double) * CQ_DOUBLES);
     L.total = o;
     return L;
 }
@@ -3059,6 +3615,7 @@ static void large_bind(LgArgs& a, const LargeLayout& L, char* base, int m, int n
     a.candw = (double*)(base + L.candw);
     a.candi = (int*)(base + L.candi);
     a.pll = (u64*)(base + L.ppart);
+    a.cq = (double*)(base + L.cq);
     a.hmir = nullptr;
 }
 
@@ -3219,14 +3776,23 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         if (mir->ctl.ncol > 1) {
             hipLaunchKernelGGL(lg_gram_part, dim3(gblk), dim3(WG), 0, cs, a, 0, a.gpart);
         }
-        hipLaunchKernelGGL(lg_greedy, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart);
         int pblk = 0;   // partial Gram blocks of V read by lg_panel_b
+        const int mp = m - mir->ctl.nP;
+        const int cqb = (mp + CQ_ROWS - 1) / CQ_ROWS;   // row blocks of the CholeskyQR2 passes
+        bool cq_try = false;
         {
-            const int mp = m - mir->ctl.nP;
             int rpw = std::max(64, (mp + PNW - 1) / PNW);
             rpw = ((rpw + 63) / 64) * 64;
             const int npw = (mp + rpw - 1) / rpw;
             const size_t lds = sizeof(double) * (size_t)rpw * (mir->ctl.ncol + 1);
+            // CholeskyQR2 when the block may have 2 .. CQ_MAX columns; lg_greedy
+            // decides (ex->cq_ok) and lg_panel_mw stands by for the rest
+            cq_try = !prm.panel_hh && mir->ctl.ncol > 1 && mir->ctl.ncol <= CQ_MAX && lds <= (size_t)PANEL_LDS_MAX;
+            hipLaunchKernelGGL(lg_greedy, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart, (int)cq_try);
+            if (cq_try) {
+                hipLaunchKernelGGL(lg_cq_p1, dim3(cqb + (mir->ctl.nP + WG - 1) / WG), dim3(WG), 0, cs, a);
+                hipLaunchKernelGGL(lg_cq_b, dim3(1), dim3(WG), 0, cs, a);
+            }
             // the attribute is per device: set it once on each device a thread uses
             static thread_local unsigned long long attr_devs = 0;
             int cur_dev = 0;
@@ -3239,9 +3805,11 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             ++ep_p;
             if (lds <= (size_t)PANEL_LDS_MAX) {
-                // also writes V, V^T, the new R columns and the partial V^T V
-                hipLaunchKernelGGL(lg_panel_mw, dim3(npw + (mir->ctl.nP + WG - 1) / WG), dim3(WG), lds, cs, a, rpw,
-                                   ep_p * 256);
+                // also writes V, V^T, the new R columns and the partial V^T V;
+                // after a CholeskyQR2 factorisation only the second row pass
+                const int gmw = npw + (mir->ctl.nP + WG - 1) / WG;
+                hipLaunchKernelGGL(lg_panel_mw, dim3(cq_try ? std::max(gmw, cqb) : gmw), dim3(WG),
+                                   cq_try ? std::max(lds, CQ_P2_LDS) : lds, cs, a, rpw, ep_p * 256);
                 pblk = npw;
             } else {
                 hipLaunchKernelGGL(lg_panel_1wg, dim3(1), dim3(WG), 0, cs, a);
@@ -3250,7 +3818,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
                 pblk = (m - mir->ctl.nP + GRAM_ROWS - 1) / GRAM_ROWS;   // the blocks of rows >= n_P
             }
         }
-        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart, pblk);
+        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart, pblk, cqb);
         // the triangular solve needs R, bt and the accepted count only: it runs
         // beside the Q update and the commit, on two streams.  The longer of
         // the two branches follows lg_panel_b on its stream and the other one
@@ -3264,6 +3832,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         ++ep_t;
         hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, ts, a, ep_t, 1);
         HIPCHK(hipGetLastError());
+        if (cq_try) hipLaunchKernelGGL(lg_cq_bt, dim3((mp + WG - 1) / WG), dim3(WG), 0, qs, a);
         hipLaunchKernelGGL(lg_qup1, dim3((m + QRB - 1) / QRB, (m - mir->ctl.nP + QCB - 1) / QCB), dim3(WG), 0, qs, a);
         // one or two reflectors (plain LH): the single-kernel pass 2 is cheaper
         // than forming W2 in a launch of its own

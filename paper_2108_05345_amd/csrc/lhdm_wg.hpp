@@ -1420,7 +1420,7 @@ struct Wg {
             inf.inner_iters = s.inner;
             inf.jloop_drops = s.jdrops;
             inf.n_passive = nP;
-            inf.reserved = 0;
+            inf.cq_panels = 0;
             inf.kkt_residual = fmax(vz, vp) / scale;
             inf.objective = rr;
             *p.info = inf;
