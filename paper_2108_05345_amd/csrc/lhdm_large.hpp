@@ -616,17 +616,24 @@ __global__ __launch_bounds__(WG) void lg_gather_cand(LgArgs a, int pair) {
     }
 }
 
-// Partial Gram matrix of X[r0:m, 0:c] (column-major, ld ldx) over row blocks of
-// 256 rows, on the matrix cores; symmetric tiles ti <= tj only.  which = 0: the
+// Partial Gram matrix of X[r0:m, 0:c] (column-major, ld m) over row blocks of
+// GRAM_ROWS rows, on the matrix cores; symmetric tiles ti <= tj only.  which = 0: the
 // projected candidates (G, c = ncol); which = 1: the reflectors (V, c = kr).
 constexpr int GRAM_ROWS = 128;   // rows per workgroup of the partial Gram
+// Layout of a partial Gram block (at most 64 x 64, symmetric): its upper 16 x
+// 16 tiles (ti <= tj), each stored whole and row-major in 256 consecutive
+// doubles, tile (ti, tj) at position tj (tj + 1) / 2 + ti, so a matrix of up
+// to 16 c columns occupies the first c (c + 1) / 2 tiles.
+constexpr int GP_TILE = 256;
+constexpr int GP_STRIDE = 10 * GP_TILE;   // doubles per block (64 columns: ten tiles)
+__device__ __forceinline__ int gp_tile(int ti, int tj) { return tj * (tj + 1) / 2 + ti; }
 
 // Partial Gram X^T X over one block of GRAM_ROWS rows of the trailing part
 // (rows >= n_P): X = G (projected candidates, which = 0) or V (reflectors,
 // which = 1), c columns.  The block is staged in LDS with coalesced loads
 // (columns past c are zero); each wave takes upper 16 x 16 tiles and runs two
 // independent MFMA accumulators over the block.  Block blk writes its tiles
-// to part[blk][64][64] (row-major, upper tiles only).
+// to part + blk GP_STRIDE in the partial-Gram layout.
 __global__ __launch_bounds__(WG) void lg_gram_part(LgArgs a, int which, double* part) {
     __shared__ double xs[GRAM_ROWS][KM + 1];
     const Ctl* ctl = a.ctl;
@@ -644,7 +651,7 @@ __global__ __launch_bounds__(WG) void lg_gram_part(LgArgs a, int which, double* 
         xs[i][q] = (i < nr && q < c) ? X[(size_t)q * m + rs + i] : 0.0;
     }
     __syncthreads();
-    double* out = part + (size_t)blockIdx.x * 64 * 64;
+    double* out = part + (size_t)blockIdx.x * GP_STRIDE;
     int tile = 0;
     for (int ti = 0; ti < nt; ++ti)
         for (int tj = ti; tj < nt; ++tj, ++tile) {
@@ -658,49 +665,50 @@ __global__ __launch_bounds__(WG) void lg_gram_part(LgArgs a, int which, double* 
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                out[(ti * 16 + 4 * v + (lane >> 4)) * 64 + tj * 16 + (lane & 15)] = acc0[v] + acc1[v];
+                out[gp_tile(ti, tj) * GP_TILE + (4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc0[v] + acc1[v];
         }
 }
 
-// The entries e = tid, tid + WG, ... of an n x n Gram matrix ((i, j) = (e / n,
-// e % n)) for which keep(i, j) holds, each the sum of the nblk partial blocks
-// in block order (from 0.0, block 0 first), handed to put(i, j, value);
-// put(i, j, 0.0) for the other entries.  A thread takes its entries GS_E at a time and keeps
-// the loads of GS_B blocks in flight for all of them together, so the sums
-// cost about nblk / GS_B memory round trips per GS_E entries instead of
-// nblk / 8 per entry.
-constexpr int GS_E = 4, GS_B = 16;
-template <typename Keep, typename Put>
-__device__ inline void gram_entries(const double* part, int nblk, int n, Keep keep, Put put) {
-    const int tid = threadIdx.x, ne = n * n;
-    for (int e0 = tid; e0 < ne; e0 += WG * GS_E) {
-        int off[GS_E];
-        bool use[GS_E];
-        double acc[GS_E];
+// The upper triangle (i <= j < n, n <= 64) of an n x n Gram matrix from its
+// nblk partial blocks (the partial-Gram layout, GP_STRIDE apart), each entry
+// the sum of the blocks in block order (from 0.0, block 0 first), handed to
+// put(i, j, value).  Thread p takes position p of every tile: GU_T tiles of
+// GU_B blocks are loaded together (coalesced, one memory round trip), so n <=
+// 32 with nblk <= 32 takes one round trip.
+constexpr int GU_T = 3, GU_B = 32;
+template <typename Put>
+__device__ inline void gram_upper(const double* part, int nblk, int n, Put put) {
+    const int p = threadIdx.x, pr = p >> 4, pc = p & 15;
+    const int nt = (n + 15) / 16, ntile = nt * (nt + 1) / 2;
+    for (int k0 = 0; k0 < ntile; k0 += GU_T) {
+        double acc[GU_T];
 #pragma unroll
-        for (int u = 0; u < GS_E; ++u) {
-            const int e = e0 + WG * u, i = e / n, j = e % n;
-            use[u] = e < ne && keep(i, j);
-            off[u] = use[u] ? i * 64 + j : 0;
-            acc[u] = 0.0;
-        }
-        for (int b0 = 0; b0 < nblk; b0 += GS_B) {
-            double v[GS_E][GS_B];
+        for (int e = 0; e < GU_T; ++e) acc[e] = 0.0;
+        for (int b0 = 0; b0 < nblk; b0 += GU_B) {
+            double v[GU_T][GU_B];
 #pragma unroll
-            for (int u = 0; u < GS_E; ++u)
+            for (int e = 0; e < GU_T; ++e)
 #pragma unroll
-                for (int bb = 0; bb < GS_B; ++bb)
-                    v[u][bb] = (use[u] && b0 + bb < nblk) ? part[(size_t)(b0 + bb) * 64 * 64 + off[u]] : 0.0;
+                for (int bb = 0; bb < GU_B; ++bb)
+                    v[e][bb] = (k0 + e < ntile && b0 + bb < nblk)
+                                   ? part[(size_t)(b0 + bb) * GP_STRIDE + (k0 + e) * GP_TILE + p]
+                                   : 0.0;
 #pragma unroll
-            for (int u = 0; u < GS_E; ++u)
+            for (int e = 0; e < GU_T; ++e)
 #pragma unroll
-                for (int bb = 0; bb < GS_B; ++bb)
-                    if (b0 + bb < nblk) acc[u] += v[u][bb];
+                for (int bb = 0; bb < GU_B; ++bb)
+                    if (b0 + bb < nblk) acc[e] += v[e][bb];
         }
 #pragma unroll
-        for (int u = 0; u < GS_E; ++u) {
-            const int e = e0 + WG * u;
-            if (e < ne) put(e / n, e % n, use[u] ? acc[u] : 0.0);
+        for (int e = 0; e < GU_T; ++e) {
+            const int k = k0 + e;
+            if (k < ntile) {
+                int tj = 0;
+                while ((tj + 1) * (tj + 2) / 2 <= k) ++tj;
+                const int ti = k - tj * (tj + 1) / 2;
+                const int i = 16 * ti + pr, j = 16 * tj + pc;
+                if (i <= j && j < n) put(i, j, acc[e]);
+            }
         }
     }
 }
@@ -733,6 +741,7 @@ constexpr int CQ_ROWS = 128;        // panel rows per workgroup of the row passe
 constexpr int CQ_XW = 49;           // LDS row of the row passes: three 16-column tiles and a pad
 constexpr double CQ_SIN2 = 1e-6;    // smallest squared sine of a column against the earlier ones
 constexpr double CQ_ORTH = 1e-4;    // largest |Q1^T Q1 - I| entry taken by the second pass
+constexpr double CQ_SER = 1e-8;     // up to this |Q1^T Q1 - I| entry, R2 and R2^{-1} by series
 constexpr int CQ_SQ = CQ_MAX * CQ_MAX;
 constexpr int CQ_R1 = 0;            // R1 (row-major, CQ_MAX x CQ_MAX, zero outside kr x kr)
 constexpr int CQ_R1I = CQ_SQ;       // R1^{-1}
@@ -828,13 +837,12 @@ __device__ __forceinline__ double chol_inv_wave(const CqRow* G, int n, CqRow* R,
 // and -1 otherwise, so every pivot of U is at least 1 in magnitude.  Column
 // elimination on [W; I]: lane r < 32 holds row r of W, lane 32 + q row q of
 // the identity; step t takes the pivot from lane t, scales column t by its
-// inverse and subtracts U[t][c] times it from column c > t (row t of U, from
-// lane t, broadcast through rowbuf).  Steps past n meet a zero row and act as
+// inverse and subtracts U[t][c] times it from column c > t (row t of U, read
+// from lane t through the scalar unit).  Steps past n meet a zero row and act as
 // identity steps.  The matrix lanes end with the unit lower L (W - S = L U),
 // the identity lanes with U^{-1}.  L and Ui are written whole (zero outside n x
 // n, L with its unit diagonal); sg[t] = s_t.
-__device__ __forceinline__ void lu_inv_wave(const CqRow* W, int n, CqRow* L, CqRow* Ui, lds_double* sg,
-                                            lds_double* rowbuf) {
+__device__ __forceinline__ void lu_inv_wave(const CqRow* W, int n, CqRow* L, CqRow* Ui, lds_double* sg) {
     const int lane = threadIdx.x & 63, r = lane & 31;
     const bool mat = lane < 32;
     double w[CQ_MAX];
@@ -843,30 +851,20 @@ __device__ __forceinline__ void lu_inv_wave(const CqRow* W, int n, CqRow* L, CqR
         const double wrc = W[r][c];
         w[c] = mat ? wrc : (c == r ? 1.0 : 0.0);
     }
-    // the next pivot is taken ahead of the broadcast (U[t][t + 1] by readlane)
+    // the next pivot is taken ahead of the update
     double pn = readlane_d(w[0], 0);
 #pragma unroll
     for (int t = 0; t < CQ_MAX; ++t) {
         const double piv = pn;
         const double st = (piv < 0.0) ? 1.0 : -1.0;
         const double ru = rcp_nr(piv - st);
-        if (lane == t) {
-#pragma unroll
-            for (int c = t + 1; c < CQ_MAX; ++c) rowbuf[c] = w[c];
-        }
         if (lane == 0) sg[t] = st;
         const double wt = (lane == t) ? 1.0 : w[t] * ru;
         w[t] = wt;
         if (t + 1 < CQ_MAX) pn = readlane_d(fma(-readlane_d(w[t + 1], t), wt, w[t + 1]), t + 1);
-        wave_lds_sync();   // lane t's row is read by every lane below
-        // all of row t of U in one LDS round trip, then the updates
-        double ut[CQ_MAX];
+        // row t of U from lane t (its entries past t are not changed by this step)
 #pragma unroll
-        for (int c = t + 1; c < CQ_MAX; ++c) ut[c] = rowbuf[c];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int c = t + 1; c < CQ_MAX; ++c) w[c] = fma(-ut[c], wt, w[c]);
-        wave_lds_sync();   // before the next step overwrites the row
+        for (int c = t + 1; c < CQ_MAX; ++c) w[c] = fma(-readlane_d(w[c], t), wt, w[c]);
     }
     const bool live = r < n;
 #pragma unroll
@@ -914,10 +912,7 @@ __global__ __launch_bounds__(WG, 1) void lg_greedy(LgArgs a, const double* part,
     if (c > 1) {
         // the candidates' Gram matrix from the partial blocks (upper part)
         const int nblk = (p.m - s.nP + GRAM_ROWS - 1) / GRAM_ROWS;
-        gram_entries(part, nblk, c, [](int ra, int t) { return ra <= t; },
-                     [&](int ra, int t, double v) {
-                         if (ra <= t) Tl[ra][t] = v;
-                     });
+        gram_upper(part, nblk, c, [&](int ra, int t, double v) { Tl[ra][t] = v; });
         __syncthreads();
         if (tid < c) sq[tid] = sqrt(Tl[tid][tid]);
         __syncthreads();
@@ -1036,8 +1031,8 @@ __device__ __forceinline__ void cq_rows_times(CqX* xs, const CqRow* M, int ncol)
 }
 
 // Partial Gram X^T X of the row block xs (nc columns; its columns nc .. 47
-// and its rows past the panel zero) into out (64 x 64, row-major, upper 16 x
-// 16 tiles: the layout of lg_gram_part), on the matrix cores.
+// and its rows past the panel zero) into out (the partial-Gram layout), on
+// the matrix cores.
 __device__ __forceinline__ void cq_gram_tiles(const CqX* xs, int nc, double* out) {
     const int lane = threadIdx.x & 63, wv = wave_index(), g = lane >> 4;
     const int nt = (nc + 15) / 16;
@@ -1054,7 +1049,7 @@ __device__ __forceinline__ void cq_gram_tiles(const CqX* xs, int nc, double* out
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                out[(ti * 16 + 4 * v + (lane >> 4)) * 64 + tj * 16 + (lane & 15)] = acc0[v] + acc1[v];
+                out[gp_tile(ti, tj) * GP_TILE + (4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc0[v] + acc1[v];
         }
 }
 
@@ -1116,7 +1111,7 @@ __global__ __launch_bounds__(WG) void lg_cq_p1(LgArgs a) {
             if (q < kr && i < nr) p.W[(size_t)q * m + rs + i] = xs[i][q];
         }
     }
-    cq_gram_tiles(xs, kr, a.gpart + (size_t)blockIdx.x * 64 * 64);
+    cq_gram_tiles(xs, kr, a.gpart + (size_t)blockIdx.x * GP_STRIDE);
 }
 
 // CholeskyQR2 panel, the small factors (one workgroup): R2 from the summed
@@ -1133,7 +1128,7 @@ __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
     __shared__ double R2_[CQ_MAX][CQ_MAX + 1], R2i_[CQ_MAX][CQ_MAX + 1], Rr_[CQ_MAX][CQ_MAX + 1];
     __shared__ double L_[CQ_MAX][CQ_MAX + 1];
     __shared__ double sg_[CQ_MAX], rowbuf_[64];
-    __shared__ int ok;
+    __shared__ int mode;
     LgExtra* ex = a.ex;
     if (!ex->cq_ok) return;
     Ctl* ctl = a.ctl;
@@ -1151,7 +1146,6 @@ __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
     CqRow* Rr = (CqRow*)Rr_;
     CqRow* L = (CqRow*)L_;
     lds_double* sg = (lds_double*)sg_;
-    lds_double* rowbuf = (lds_double*)rowbuf_;
     {
         double lr[CQ_SQ / WG], lw[CQ_SQ / WG];
 #pragma unroll
@@ -1169,7 +1163,7 @@ __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
         }
     }
     __syncthreads();
-    gram_entries(a.gpart, nb, kr, [](int i, int t) { return i <= t; }, [&](int i, int t, double v) { G2[i][t] = v; });
+    gram_upper(a.gpart, nb, kr, [&](int i, int t, double v) { G2[i][t] = v; });
     __syncthreads();
     if (wv == 0) {
         // largest deviation of Q1^T Q1 from the identity (upper triangle)
@@ -1182,18 +1176,62 @@ __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
         }
         if (!(dev == dev)) dev = INFINITY;
         for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, 64));
-        const double piv = chol_inv_wave(G2, kr, R2, R2i, rowbuf);
-        if (lane == 0) ok = (piv > 0.0 && dev <= CQ_ORTH) ? 1 : 0;
+        if (lane == 0) mode = (dev <= CQ_SER) ? 2 : (dev <= CQ_ORTH) ? 1 : 0;
     }
     __syncthreads();
-    if (!ok) {
+    if (mode == 2) {
+        // Q1^T Q1 = I + E with |E| <= CQ_SER: R2 = I + F, F upper triangular
+        // with F + F^T + F^T F = E, to second order F = Phi(E) - Phi(F0^T F0)
+        // with F0 = Phi(E) (Phi: strict upper triangle plus half the
+        // diagonal); R2^{-1} = I - F + F^2.  The neglected terms are of third
+        // order in |E| <= CQ_MAX CQ_SER.
+        CqRow* F0 = R2;
+        CqRow* F0t = R2i;
+        CqRow* P = Rr;
+        CqRow* F = L;
+        for (int e = tid; e < CQ_SQ; e += WG) {
+            const int i = e / CQ_MAX, j = e % CQ_MAX;
+            const bool in = j < kr;
+            const double eij = (i < j) ? G2[i][j] : (i == j) ? 0.5 * (G2[i][i] - 1.0) : 0.0;
+            F0[i][j] = in ? eij : 0.0;
+            F0t[j][i] = in ? eij : 0.0;
+        }
+        __syncthreads();
+        mm32(F0t, F0, P);   // F0^T F0 (symmetric)
+        __syncthreads();
+        for (int e = tid; e < CQ_SQ; e += WG) {
+            const int i = e / CQ_MAX, j = e % CQ_MAX;
+            const double pij = (i < j) ? P[i][j] : (i == j) ? 0.5 * P[i][i] : 0.0;
+            F[i][j] = F0[i][j] - pij;
+        }
+        __syncthreads();
+        mm32(F, F, P);      // F^2
+        __syncthreads();
+        for (int e = tid; e < CQ_SQ; e += WG) {
+            const int i = e / CQ_MAX, j = e % CQ_MAX;
+            const bool in = i < kr && j < kr;
+            const double id = (i == j) ? 1.0 : 0.0;
+            R2[i][j] = in ? id + F[i][j] : 0.0;
+            R2i[i][j] = in ? (id - F[i][j]) + P[i][j] : 0.0;
+        }
+    } else if (mode == 1) {
+        __shared__ int ok;
+        if (wv == 0) {
+            const double piv = chol_inv_wave(G2, kr, R2, R2i, (lds_double*)rowbuf_);
+            if (lane == 0) ok = (piv > 0.0) ? 1 : 0;
+        }
+        __syncthreads();
+        if (!ok) mode = 0;   // read by every thread below after the barrier
+    }
+    __syncthreads();
+    if (mode == 0) {
         if (tid == 0) ex->cq_ok = 0;
         return;
     }
     mm32(R2, R1, Rr);     // R = R2 R1
     mm32(Q1t, R2i, Qt);   // Q's top block (G2 is no longer needed)
     __syncthreads();
-    if (wv == 0) lu_inv_wave(Qt, kr, L, Ui, sg, rowbuf);   // Q1_top is no longer needed
+    if (wv == 0) lu_inv_wave(Qt, kr, L, Ui, sg);   // Q1_top is no longer needed
     __syncthreads();
     mm32(R2i, Ui, M2i);   // (U R2)^{-1}; R1 is no longer needed
     __syncthreads();
@@ -1266,7 +1304,7 @@ __device__ inline void cq_second_pass(const LgArgs& a, lds_double* dyn) {
             p.Vt[(size_t)(rs + ii) * p.kq + q] = xs[ii][q];
         }
     }
-    cq_gram_tiles(xs, kr + 1, a.gpart + (size_t)blockIdx.x * 64 * 64);
+    cq_gram_tiles(xs, kr + 1, a.gpart + (size_t)blockIdx.x * GP_STRIDE);
 }
 
 // CholeskyQR2 panel: bt[n_P + kr : m] -= Y z with z = T^T (Y^T bt) from
@@ -1511,12 +1549,12 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
         const int i = e / kr, t = e % kr, row = rs + i;
         p.Vt[(size_t)row * p.kq + t] = (row >= r0 + t) ? pan[i * ld + t] : 0.0;
     }
-    // Partial V^T V over this workgroup's rows into slot w of gpart (the layout
-    // of lg_gram_part; lg_panel_b adds the npw slots in order): upper 16 x 16
-    // tiles on the matrix cores, V read from LDS with the same zeros as above
+    // Partial V^T V over this workgroup's rows into slot w of gpart (the
+    // partial-Gram layout; lg_panel_b adds the npw slots in order): upper 16 x
+    // 16 tiles on the matrix cores, V read from LDS with the same zeros as above
     // (the padding rows past nr are zero).
     {
-        double* out = a.gpart + (size_t)w * 64 * 64;
+        double* out = a.gpart + (size_t)w * GP_STRIDE;
         const int nt = (kr + 15) / 16;
         const int g = lane >> 4;
         auto vv = [&](int i, int q) {
@@ -1535,7 +1573,7 @@ __global__ __launch_bounds__(WG) void lg_panel_mw(LgArgs a, int rpw, int ebase) 
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    out[(ti * 16 + 4 * v + (lane >> 4)) * 64 + tj * 16 + (lane & 15)] = acc0[v] + acc1[v];
+                    out[gp_tile(ti, tj) * GP_TILE + (4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc0[v] + acc1[v];
             }
     }
 }
@@ -1609,7 +1647,7 @@ __device__ inline void wy_t_columns(const double (*Wl)[KM + 1], const double* ta
 // blocks of [V, bt] (the CholeskyQR2 second row pass): then tau_t = 2 / ||v_t||^2, and this kernel
 // also forms z = T^T (V^T bt) for lg_cq_bt and the rows n_P .. n_P + kr - 1 of
 // bt = (I - V T^T V^T) bt.
-__global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, int nblk, int nblk_cq) {
+__global__ __launch_bounds__(WG, 1) void lg_panel_b(LgArgs a, const double* part, int nblk, int nblk_cq) {
     __shared__ WgShared s;
     __shared__ double Tl[KM][KM + 1];
     __shared__ double Wl[KM][KM + 1];
@@ -1621,13 +1659,11 @@ __global__ __launch_bounds__(WG) void lg_panel_b(LgArgs a, const double* part, i
     const bool cq = a.ex->cq_ok != 0;
     // T of the compact WY form, from V^T V (summed from the partial blocks)
     if (cq) {
-        gram_entries(part, nblk_cq, kr + 1, [](int i, int t) { return i <= t; },
-                     [&](int i, int t, double v) { Wl[i][t] = v; });
+        gram_upper(part, nblk_cq, kr + 1, [&](int i, int t, double v) { Wl[i][t] = v; });
         __syncthreads();
         if (tid < kr) s.tau[tid] = 2.0 / Wl[tid][tid];
     } else {
-        gram_entries(part, nblk, kr, [](int i, int t) { return i < t; },   // consecutive threads: consecutive t
-                     [&](int i, int t, double v) { Wl[i][t] = v; });
+        gram_upper(part, nblk, kr, [&](int i, int t, double v) { Wl[i][t] = v; });
     }
     __syncthreads();
     if (tid < 64) {
@@ -3530,7 +3566,7 @@ static LargeLayout large_layout(int m, int n, int kmax) {
     put(L.roff, sizeof(int) * kc);
     put(L.recomp, sizeof(int) * (size_t)n);
     put(L.rpart, sizeof(double) * (size_t)RES_CHUNKS * m);
-    put(L.gpart, sizeof(double) * (size_t)std::max((m + GRAM_ROWS - 1) / GRAM_ROWS, PNW) * 64 * 64);
+    put(L.gpart, sizeof(double) * (size_t)std::max((m + GRAM_ROWS - 1) / GRAM_ROWS, PNW) * GP_STRIDE);
     put(L.selv, sizeof(double) * 3 * 64);
     put(L.seli, sizeof(int) * 64);
     put(L.candw, sizeof(double) * CAND_CAP);

@@ -177,7 +177,7 @@ __global__ __launch_bounds__(WG, 1) void test_cq_factors_kernel(int n, const dou
     if (wave_index() == 0) {
         const double q = chol_inv_wave((CqRow*)G_, n, (CqRow*)R_, (CqRow*)Ri_, (lds_double*)rowbuf_);
         if (tid == 0) *sin2 = q;
-        lu_inv_wave((CqRow*)W_, n, (CqRow*)L_, (CqRow*)Ui_, (lds_double*)sg_, (lds_double*)rowbuf_);
+        lu_inv_wave((CqRow*)W_, n, (CqRow*)L_, (CqRow*)Ui_, (lds_double*)sg_);
     }
     __syncthreads();
     for (int e = tid; e < n * n; e += WG) {
