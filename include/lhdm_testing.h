@@ -51,12 +51,12 @@ int lhdm_test_downdate(void* stream, int32_t engine, int32_t m, int32_t nP, cons
  *     triangle read): R [dev] n x n upper (R^T R = G) and Ri [dev] n x n = R^{-1};
  *     sin2 [host]: the smallest R[t][t]^2 / G[t][t], or -1 when a pivot is not a
  *     positive finite number.
- *   W [dev] n x n, column-major: LU without pivoting of W - S with S =
+ *   W [dev] n x n, column-major: LU without pivoting of W - S = L U with S =
  *     diag(sg), sg[t] = +1 when step t's pivot is negative and -1 otherwise:
- *     L [dev] n x n unit lower, Ui [dev] n x n = U^{-1}, sg [dev] n.
+ *     U [dev] n x n upper, Li [dev] n x n = L^{-1} (unit lower), sg [dev] n.
  * 1 <= n <= 32.  Returns LHDM_EINVAL on bad sizes or pointers. */
 int lhdm_test_cq_factors(void* stream, int32_t n, const double* G, const double* W, double* R, double* Ri,
-                         double* L, double* Ui, double* sg, double* sin2);
+                         double* U, double* Li, double* sg, double* sin2);
 
 #ifdef __cplusplus
 }

@@ -728,14 +728,16 @@ __device__ inline void gram_upper(const double* part, int nblk, int n, Put put) 
 // Q - [S; 0] = Y U with Y unit lower trapezoidal.  Y is the matrix of
 // reflectors with unit diagonal, S R the new diagonal block of R (the signs of
 // the column-by-column factorisation), and the rows of Y below the top block
-// are y = q U^{-1} = q1 (U R2)^{-1}.  The compact-WY factor T follows from
-// Y^T Y (lg_panel_b) with tau_t = 2 / ||y_t||^2, which keeps the block
-// reflector orthogonal to rounding.  The row passes multiply 16-row tiles by
-// the explicit triangular inverses R1^{-1} and (U R2)^{-1} on the matrix
-// cores; the small factors are formed by one wave with the matrices in
-// registers (one column per lane).  Two row passes over the panel and two
-// one-workgroup steps replace the per-column exchange; a block whose Gram
-// matrix is far from well conditioned goes the column-by-column way.
+// are y = q U^{-1} = q1 (U R2)^{-1}.  The compact-WY factor is T = -U S
+// Y1^{-T}.  The LU runs twice side by side on two waves, as row operations on
+// [Q_top - S, I] (leaving U and Y1^{-1}, so T is one product) and as column
+// operations on [Q_top - S; I] (leaving Y1 and U^{-1}); both form the same
+// Schur complements with the same products, so their pivots and signs agree
+// bit for bit.  The row passes multiply 16-row tiles by the explicit inverses
+// R1^{-1} and (U R2)^{-1} on the matrix cores; the small factors are formed by
+// one wave each with the matrices in registers (one column or row per lane).  Two row passes over the panel and two one-workgroup steps
+// replace the per-column exchange; a block whose Gram matrix is far from well
+// conditioned goes the column-by-column way.
 constexpr int CQ_MAX = 32;          // widest panel (one column per lane of a wave)
 constexpr int CQ_ROWS = 128;        // panel rows per workgroup of the row passes
 constexpr int CQ_XW = 49;           // LDS row of the row passes: three 16-column tiles and a pad
@@ -747,10 +749,12 @@ constexpr int CQ_R1 = 0;            // R1 (row-major, CQ_MAX x CQ_MAX, zero outs
 constexpr int CQ_R1I = CQ_SQ;       // R1^{-1}
 constexpr int CQ_M2I = 2 * CQ_SQ;   // (U R2)^{-1}
 constexpr int CQ_Y1 = 3 * CQ_SQ;    // top block of Y (unit lower)
-constexpr int CQ_Z = 4 * CQ_SQ;     // z = T^T (Y^T bt)
-constexpr int CQ_DOUBLES = 4 * CQ_SQ + CQ_MAX;
-// dynamic LDS of the second row pass (inside lg_panel_mw): the row block and (U R2)^{-1}
-constexpr size_t CQ_P2_LDS = sizeof(double) * (CQ_ROWS * CQ_XW + CQ_MAX * (CQ_MAX + 1));
+constexpr int CQ_R22 = 4 * CQ_SQ;   // the new diagonal block S R of R
+constexpr int CQ_Z = 5 * CQ_SQ;     // z = T^T (Y^T bt)
+constexpr int CQ_DOUBLES = 5 * CQ_SQ + CQ_MAX;
+// dynamic LDS of the second row pass (inside lg_panel_mw): the row block,
+// (U R2)^{-1} and eight partial column sums
+constexpr size_t CQ_P2_LDS = sizeof(double) * (CQ_ROWS * CQ_XW + CQ_MAX * (CQ_MAX + 1) + 8 * CQ_MAX);
 static_assert(WG == 2 * CQ_ROWS && NW == 4, "row passes: two threads per row, four waves");
 typedef lds_double CqRow[CQ_MAX + 1];   // a row of a small matrix in LDS
 typedef lds_double CqX[CQ_XW];          // a row of a row block in LDS
@@ -831,6 +835,49 @@ __device__ __forceinline__ double chol_inv_wave(const CqRow* G, int n, CqRow* R,
     return q;
 }
 
+// LU factorisation without pivoting of W - S and the inverse of its L in one
+// pass, by one wave (the reconstruction's LU).  W: n x n in LDS (n <= CQ_MAX,
+// zero outside n x n); S = diag(s_t), s_t = +1 when step t's pivot is
+// negative and -1 otherwise, so every pivot of U is at least 1 in magnitude.
+// Row elimination on [W, I]: lane c < 32 holds column c of W, lane 32 + c
+// column c of the identity; step t takes the pivot from lane t, modifies it by
+// -s_t and subtracts l_i = W[i][t] / pivot times row t from each row i > t
+// (the multipliers are column t's entries, read from lane t through the
+// scalar unit).  Steps past n meet a zero column and act as identity steps.
+// The matrix lanes end with U (W - S = L U), the identity lanes with L^{-1}
+// (unit lower).  U and Li are written whole (zero outside n x n); sg[t] = s_t.
+__device__ __forceinline__ void lu_rows_wave(const CqRow* W, int n, CqRow* U, CqRow* Li, lds_double* sg) {
+    const int lane = threadIdx.x & 63, c = lane & 31;
+    const bool mat = lane < 32;
+    double w[CQ_MAX];
+#pragma unroll
+    for (int i = 0; i < CQ_MAX; ++i) {
+        const double wic = W[i][c];
+        w[i] = mat ? wic : (i == c ? 1.0 : 0.0);
+    }
+    // the next pivot is taken ahead of the update
+    double pn = readlane_d(w[0], 0);
+#pragma unroll
+    for (int t = 0; t < CQ_MAX; ++t) {
+        const double piv = pn;
+        const double st = (piv < 0.0) ? 1.0 : -1.0;
+        const double u = piv - st;
+        const double ru = rcp_nr(u);
+        if (lane == 0) sg[t] = st;
+        if (lane == t) w[t] = u;
+        const double wt = w[t];   // row t of this lane's column
+        if (t + 1 < CQ_MAX) pn = readlane_d(fma(-(readlane_d(w[t + 1], t) * ru), wt, w[t + 1]), t + 1);
+#pragma unroll
+        for (int i = t + 1; i < CQ_MAX; ++i) w[i] = fma(-(readlane_d(w[i], t) * ru), wt, w[i]);
+    }
+    const bool live = c < n;
+#pragma unroll
+    for (int i = 0; i < CQ_MAX; ++i) {
+        if (mat) U[i][c] = (live && i <= c) ? w[i] : 0.0;
+        else Li[i][c] = (live && i < n && i >= c) ? ((i == c) ? 1.0 : w[i]) : 0.0;
+    }
+}
+
 // LU factorisation without pivoting of W - S and the inverse of U in one
 // pass, by one wave (the reconstruction's LU).  W: n x n in LDS (n <= CQ_MAX,
 // zero outside n x n); S = diag(s_t), s_t = +1 when step t's pivot is negative
@@ -874,6 +921,7 @@ __device__ __forceinline__ void lu_inv_wave(const CqRow* W, int n, CqRow* L, CqR
     }
 }
 
+
 // C = A B for 32 x 32 matrices in LDS on the matrix cores, one 16 x 16 tile
 // of C per wave (all four waves call it); C must not alias A or B.
 __device__ __forceinline__ void mm32(const CqRow* A, const CqRow* B, CqRow* C) {
@@ -886,6 +934,19 @@ __device__ __forceinline__ void mm32(const CqRow* A, const CqRow* B, CqRow* C) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) C[16 * ti + 4 * v + g][16 * tj + r] = acc[v];
 }
+
+// C = A B^T, as mm32.
+__device__ __forceinline__ void mm32t(const CqRow* A, const CqRow* B, CqRow* C) {
+    const int lane = threadIdx.x & 63, wv = wave_index();
+    const int ti = wv >> 1, tj = wv & 1, r = lane & 15, g = lane >> 4;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < CQ_MAX; kk += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[16 * ti + r][kk + g], B[16 * tj + r][kk + g], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) C[16 * ti + 4 * v + g][16 * tj + r] = acc[v];
+}
+
 
 // Deviation maximization's greedy test (Algorithm 2) on the candidates' Gram
 // matrix, or the single column of Lawson-Hanson.  The pairwise cosines are
@@ -905,48 +966,70 @@ __global__ __launch_bounds__(WG, 1) void lg_greedy(LgArgs a, const double* part,
     __shared__ double sq[KM];
     __shared__ unsigned long long bad[KM];
     __shared__ int gm[KM];
+    __shared__ double sin2s;
+    __shared__ int gid;
     ctl_load(s, a.ctl);
     const Prob& p = a.p;
     LgExtra* ex = a.ex;
-    const int c = s.ncol, kq = p.kq, tid = threadIdx.x;
+    const int c = s.ncol, tid = threadIdx.x, lane = tid & 63, wv = wave_index();
+    CqRow* Gs = (CqRow*)Gs_;
+    CqRow* R1s = (CqRow*)R1s_;
+    CqRow* R1is = (CqRow*)R1is_;
+    // while wave 0 runs the selection, wave 1 factors the Gram matrix of all
+    // candidates in their order: the accepted block's when the scan keeps
+    // every candidate, which is the common case
+    const bool spec = cq && c > 1 && c <= CQ_MAX;
     if (c > 1) {
         // the candidates' Gram matrix from the partial blocks (upper part)
         const int nblk = (p.m - s.nP + GRAM_ROWS - 1) / GRAM_ROWS;
         gram_upper(part, nblk, c, [&](int ra, int t, double v) { Tl[ra][t] = v; });
         __syncthreads();
-        if (tid < c) sq[tid] = sqrt(Tl[tid][tid]);
-        __syncthreads();
-        if (tid < c) {
-            const int t = tid;
-            const double nt = sq[t];
-            unsigned long long msk = 0;
-            for (int ra = 0; ra < t; ++ra) {
-                const double th = Tl[ra][t] / (nt * sq[ra]);
-                if (!(fabs(th) < a.prm.delta)) msk |= 1ull << ra;
-            }
-            bad[t] = msk;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            const int cap = p.m - s.nP;
-            unsigned long long acc = 1ull;
-            int na = 1;
-            gm[0] = 0;
-            for (int t = 1; t < c; ++t) {
-                if (na >= cap) break;
-                if ((bad[t] & acc) == 0ull) {
-                    acc |= 1ull << t;
-                    gm[na++] = t;
+        if (wv == 0) {
+            // c <= 64: one candidate per lane
+            const int t = lane;
+            if (t < c) sq[t] = sqrt(Tl[t][t]);
+            wave_lds_sync();
+            if (t < c) {
+                const double nt = sq[t];
+                unsigned long long msk = 0;
+                for (int ra = 0; ra < t; ++ra) {
+                    const double th = Tl[ra][t] / (nt * sq[ra]);
+                    if (!(fabs(th) < a.prm.delta)) msk |= 1ull << ra;
                 }
+                bad[t] = msk;
             }
-            for (int q = 0; q < na; ++q) s.J[q] = s.J[gm[q]];
-            s.k = na;
-            ex->gident = (na == c);
+            wave_lds_sync();
+            if (lane == 0) {
+                const int cap = p.m - s.nP;
+                unsigned long long acc = 1ull;
+                int na = 1;
+                gm[0] = 0;
+                for (int t2 = 1; t2 < c; ++t2) {
+                    if (na >= cap) break;
+                    if ((bad[t2] & acc) == 0ull) {
+                        acc |= 1ull << t2;
+                        gm[na++] = t2;
+                    }
+                }
+                for (int q = 0; q < na; ++q) s.J[q] = s.J[gm[q]];
+                s.k = na;
+                gid = (na == c);
+                ex->gident = (na == c);
+            }
+        } else if (wv == 1 && spec) {
+            for (int e = lane; e < CQ_SQ; e += 64) {
+                const int q = e / CQ_MAX, r = e % CQ_MAX;
+                Gs[q][r] = (q <= r && r < c) ? Tl[q][r] : 0.0;
+            }
+            wave_lds_sync();
+            const double q2 = chol_inv_wave(Gs, c, R1s, R1is, (lds_double*)rowbuf_);
+            if (lane == 0) sin2s = q2;
         }
     } else {
         if (tid == 0) {
             s.k = 1;
             gm[0] = 0;
+            gid = 1;
             ex->gident = 1;
         }
     }
@@ -954,20 +1037,20 @@ __global__ __launch_bounds__(WG, 1) void lg_greedy(LgArgs a, const double* part,
     if (tid < s.k) ex->gmap[tid] = gm[tid];
     const int na = s.k;
     if (cq && c > 1 && na >= 2 && na <= CQ_MAX) {
-        // R1 and R1^{-1} of the accepted columns (one wave)
-        CqRow* Gs = (CqRow*)Gs_;
-        CqRow* R1s = (CqRow*)R1s_;
-        CqRow* R1is = (CqRow*)R1is_;
-        for (int e = tid; e < CQ_SQ; e += WG) {
-            const int q = e / CQ_MAX, r = e % CQ_MAX;
-            Gs[q][r] = (q <= r && r < na) ? Tl[gm[q]][gm[r]] : 0.0;
+        if (!(spec && gid)) {
+            // R1 and R1^{-1} of the accepted columns (one wave)
+            for (int e = tid; e < CQ_SQ; e += WG) {
+                const int q = e / CQ_MAX, r = e % CQ_MAX;
+                Gs[q][r] = (q <= r && r < na) ? Tl[gm[q]][gm[r]] : 0.0;
+            }
+            __syncthreads();
+            if (wv == 0) {
+                const double q2 = chol_inv_wave(Gs, na, R1s, R1is, (lds_double*)rowbuf_);
+                if (lane == 0) sin2s = q2;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (wave_index() == 0) {
-            const double sin2 = chol_inv_wave(Gs, na, R1s, R1is, (lds_double*)rowbuf_);
-            if (tid == 0) ex->cq_ok = (sin2 >= CQ_SIN2) ? 1 : 0;
-        }
-        __syncthreads();
+        if (tid == 0) ex->cq_ok = (sin2s >= CQ_SIN2) ? 1 : 0;
         for (int e = tid; e < CQ_SQ; e += WG) {
             a.cq[CQ_R1 + e] = R1s[e / CQ_MAX][e % CQ_MAX];
             a.cq[CQ_R1I + e] = R1is[e / CQ_MAX][e % CQ_MAX];
@@ -1117,35 +1200,44 @@ __global__ __launch_bounds__(WG) void lg_cq_p1(LgArgs a) {
 // CholeskyQR2 panel, the small factors (one workgroup): R2 from the summed
 // Q1^T Q1 (ex->cq_ok = 0 when an entry of Q1^T Q1 - I exceeds CQ_ORTH or a
 // pivot fails: the column-by-column panel then runs), R = R2 R1, Q's top block
-// Q1_top R2^{-1}, its LU with signs (U, S, unit lower Y1), the new columns' rows
-// n_P .. n_P + t of R (S R, diagonal into ctl->beta), and (U R2)^{-1} = R2^{-1}
-// U^{-1} and Y1 for the second row pass.  The serial parts (Cholesky, the two
-// triangular inverses, the LU) run on one wave with the matrices in
-// registers; the products on the matrix cores.
+// Q1_top R2^{-1}, its LU with signs (S, U, Y1 and their inverses, on two
+// waves), T = -U S Y1^{-T} into p.T, the new columns' rows n_P .. n_P + t of
+// R (S R, also in a.cq, diagonal into ctl->beta), and (U R2)^{-1} and Y1 for
+// the second row pass.  The serial parts (Cholesky, LU) run on one wave each
+// with the matrices in registers; the products on the matrix cores.
 __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
-    // lifetimes: G2 then Q_top in A0; R1 then (U R2)^{-1} in A1; Q1_top then U^{-1} in A2
+    // lifetimes: G2 then Q_top in A0; R1 then U S in A1; Q1_top then T in A2;
+    // R2^{-1} then U R2 in R2i_
     __shared__ double A0_[CQ_MAX][CQ_MAX + 1], A1_[CQ_MAX][CQ_MAX + 1], A2_[CQ_MAX][CQ_MAX + 1];
     __shared__ double R2_[CQ_MAX][CQ_MAX + 1], R2i_[CQ_MAX][CQ_MAX + 1], Rr_[CQ_MAX][CQ_MAX + 1];
-    __shared__ double L_[CQ_MAX][CQ_MAX + 1];
-    __shared__ double sg_[CQ_MAX], rowbuf_[64];
+    __shared__ double L_[CQ_MAX][CQ_MAX + 1], Li_[CQ_MAX][CQ_MAX + 1];
+    __shared__ double Lc_[CQ_MAX][CQ_MAX + 1], Ui_[CQ_MAX][CQ_MAX + 1], M2i_[CQ_MAX][CQ_MAX + 1];
+    __shared__ double sg_[CQ_MAX], sg2_[CQ_MAX], rowbuf_[64];
     __shared__ int mode;
     LgExtra* ex = a.ex;
     if (!ex->cq_ok) return;
     Ctl* ctl = a.ctl;
     const Prob& p = a.p;
-    const int r0 = ctl->nP, kr = ctl->kr, m = p.m, tid = threadIdx.x, lane = tid & 63, wv = wave_index();
+    const int r0 = ctl->nP, kr = ctl->kr, m = p.m, kq = p.kq, tid = threadIdx.x, lane = tid & 63,
+              wv = wave_index();
     const int nb = (m - r0 + CQ_ROWS - 1) / CQ_ROWS;
     CqRow* G2 = (CqRow*)A0_;
     CqRow* Qt = (CqRow*)A0_;
     CqRow* R1 = (CqRow*)A1_;
-    CqRow* M2i = (CqRow*)A1_;
+    CqRow* US = (CqRow*)A1_;
     CqRow* Q1t = (CqRow*)A2_;
-    CqRow* Ui = (CqRow*)A2_;
+    CqRow* Tm = (CqRow*)A2_;
     CqRow* R2 = (CqRow*)R2_;
     CqRow* R2i = (CqRow*)R2i_;
     CqRow* Rr = (CqRow*)Rr_;
-    CqRow* L = (CqRow*)L_;
+    CqRow* L = (CqRow*)L_;   // scratch of the series for R2, then U
+    CqRow* U = (CqRow*)L_;
+    CqRow* Li = (CqRow*)Li_;
+    CqRow* Lc = (CqRow*)Lc_;
+    CqRow* Ui = (CqRow*)Ui_;
+    CqRow* M2i = (CqRow*)M2i_;
     lds_double* sg = (lds_double*)sg_;
+    lds_double* sg2 = (lds_double*)sg2_;
     {
         double lr[CQ_SQ / WG], lw[CQ_SQ / WG];
 #pragma unroll
@@ -1231,9 +1323,21 @@ __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
     mm32(R2, R1, Rr);     // R = R2 R1
     mm32(Q1t, R2i, Qt);   // Q's top block (G2 is no longer needed)
     __syncthreads();
-    if (wv == 0) lu_inv_wave(Qt, kr, L, Ui, sg);   // Q1_top is no longer needed
+    if (wv == 0) lu_rows_wave(Qt, kr, U, Li, sg);
+    else if (wv == 1) lu_inv_wave(Qt, kr, Lc, Ui, sg2);
     __syncthreads();
-    mm32(R2i, Ui, M2i);   // (U R2)^{-1}; R1 is no longer needed
+    if (tid < kr && sg[tid] != sg2[tid]) mode = 0;   // cannot happen: the two take the same pivots
+    for (int e = tid; e < CQ_SQ; e += WG) {   // U S (R1 is no longer needed)
+        const int i = e / CQ_MAX, j = e % CQ_MAX;
+        US[i][j] = U[i][j] * sg[j];
+    }
+    __syncthreads();
+    if (mode == 0) {
+        if (tid == 0) ex->cq_ok = 0;
+        return;
+    }
+    mm32t(US, Li, Tm);    // U S Y1^{-T} = -T (Q1_top is no longer needed)
+    mm32(R2i, Ui, M2i);   // (U R2)^{-1} = R2^{-1} U^{-1}
     __syncthreads();
     {
         int sl[CQ_SQ / WG];
@@ -1245,31 +1349,46 @@ __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
 #pragma unroll
         for (int u = 0; u < CQ_SQ / WG; ++u) {
             const int e = tid + WG * u, i = e / CQ_MAX, j = e % CQ_MAX;
+            const double rh = (i <= j && j < kr) ? sg[i] * Rr[i][j] : 0.0;
             a.cq[CQ_M2I + e] = M2i[i][j];
-            a.cq[CQ_Y1 + e] = L[i][j];
-            if (i <= j && j < kr) p.R[(size_t)sl[u] * p.kc + r0 + i] = sg[i] * Rr[i][j];
+            a.cq[CQ_Y1 + e] = Lc[i][j];
+            a.cq[CQ_R22 + e] = rh;
+            if (i <= j && j < kr) p.R[(size_t)sl[u] * p.kc + r0 + i] = rh;
         }
     }
-    if (tid < kr) ctl->beta[tid] = sg[tid] * Rr[tid][tid];
+    // T (column-major, ld kq; zero below the diagonal and past kr rows)
+    for (int e = tid; e < kr * kq; e += WG) {
+        const int t = e / kq, i = e % kq;
+        p.T[(size_t)t * kq + i] = (i < kr) ? -Tm[i][t] : 0.0;
+    }
+    if (tid < kr) {
+        ctl->beta[tid] = sg[tid] * Rr[tid][tid];
+        ctl->tau[tid] = -Tm[tid][tid];
+    }
 }
 
 // CholeskyQR2 panel, second row pass (run by lg_panel_mw's workgroups w <
-// nb): the reflectors.  Rows n_P .. n_P + kr - 1 take Y1 (unit diagonal, zeros
-// above), the others y = q1 (U R2)^{-1}; y into V (column-major) and V^T
-// (row-major), and the block's partial Gram of [Y, bt] (kr + 1 columns: Y^T Y
-// and Y^T bt) into slot w of gpart.  dyn: CQ_P2_LDS bytes of LDS.
+// nb = ceil((m - n_P) / CQ_ROWS)): the reflectors.  Rows n_P .. n_P + kr - 1
+// take Y1 (unit diagonal, zeros above), the others y = q1 (U R2)^{-1}; y into
+// V (column-major) and V^T (row-major), and the block's partial Y^T bt (kr
+// values, summed over its rows in row order) into slot w of gpart.  dyn:
+// CQ_P2_LDS bytes of LDS.
 __device__ inline void cq_second_pass(const LgArgs& a, lds_double* dyn) {
     const Ctl* ctl = a.ctl;
     const Prob& p = a.p;
-    const int r0 = ctl->nP, kr = ctl->kr, m = p.m, tid = threadIdx.x;
+    const int r0 = ctl->nP, kr = ctl->kr, m = p.m, kq = p.kq, tid = threadIdx.x;
     const int nb = (m - r0 + CQ_ROWS - 1) / CQ_ROWS;
     if ((int)blockIdx.x >= nb) return;
     CqX* xs = (CqX*)dyn;
     CqRow* Mi = (CqRow*)(dyn + CQ_ROWS * CQ_XW);
+    lds_double* part8 = dyn + CQ_ROWS * CQ_XW + CQ_MAX * (CQ_MAX + 1);   // 8 x CQ_MAX
     const int rs = r0 + (int)blockIdx.x * CQ_ROWS, nr = min(m - rs, CQ_ROWS);
-    double mr[CQ_SQ / WG];
+    double mr[CQ_SQ / WG], yr[CQ_SQ / WG];
 #pragma unroll
-    for (int u = 0; u < CQ_SQ / WG; ++u) mr[u] = a.cq[CQ_M2I + tid + WG * u];
+    for (int u = 0; u < CQ_SQ / WG; ++u) {
+        mr[u] = a.cq[CQ_M2I + tid + WG * u];
+        yr[u] = (blockIdx.x == 0) ? a.cq[CQ_Y1 + tid + WG * u] : 0.0;
+    }
     cq_stage(xs, nr, kr + 1,
              [&](int q, int i) { return (q < kr) ? p.W[(size_t)q * m + rs + i] : p.bt[rs + i]; });
 #pragma unroll
@@ -1282,13 +1401,10 @@ __device__ inline void cq_second_pass(const LgArgs& a, lds_double* dyn) {
     __syncthreads();
     if (blockIdx.x == 0) {
         // the top rows: Y1 (block 0 starts at row n_P; kr <= nr)
-        double y[CQ_SQ / WG];
-#pragma unroll
-        for (int u = 0; u < CQ_SQ / WG; ++u) y[u] = a.cq[CQ_Y1 + tid + WG * u];
 #pragma unroll
         for (int u = 0; u < CQ_SQ / WG; ++u) {
             const int e = tid + WG * u, i = e / CQ_MAX, q = e % CQ_MAX;
-            if (i < kr && q < kr) xs[i][q] = y[u];
+            if (i < kr && q < kr) xs[i][q] = yr[u];
         }
         __syncthreads();
     }
@@ -1299,12 +1415,37 @@ __device__ inline void cq_second_pass(const LgArgs& a, lds_double* dyn) {
             const int q = h + 2 * u;
             if (q < kr && i < nr) p.V[(size_t)q * m + rs + i] = xs[i][q];
         }
+        // V^T rows, coalesced: element e = ii kr + q of the block's rows
+        const int di = WG / kr, dq = WG % kr;
+        int ii = tid / kr, q = tid % kr;
         for (int e = tid; e < nr * kr; e += WG) {
-            const int ii = e / kr, q = e % kr;
-            p.Vt[(size_t)(rs + ii) * p.kq + q] = xs[ii][q];
+            p.Vt[(size_t)(rs + ii) * kq + q] = xs[ii][q];
+            q += dq;
+            ii += di;
+            if (q >= kr) {
+                q -= kr;
+                ++ii;
+            }
         }
     }
-    cq_gram_tiles(xs, kr + 1, a.gpart + (size_t)blockIdx.x * GP_STRIDE);
+    // Y^T bt over the block's rows: eight groups of 16 rows, then the groups,
+    // each in row order (rows past the panel hold zeros)
+    {
+        const int q = tid & 31, g = tid >> 5;
+        double acc = 0.0;
+        if (q < kr)
+            for (int r = 0; r < CQ_ROWS / 8; ++r) {
+                const int rr = g * (CQ_ROWS / 8) + r;
+                acc = fma(xs[rr][q], xs[rr][kr], acc);
+            }
+        part8[g * CQ_MAX + q] = acc;
+    }
+    __syncthreads();
+    if (tid < CQ_MAX) {
+        double acc = 0.0;
+        for (int g = 0; g < 8; ++g) acc += part8[g * CQ_MAX + tid];
+        a.gpart[(size_t)blockIdx.x * GP_STRIDE + tid] = acc;
+    }
 }
 
 // CholeskyQR2 panel: bt[n_P + kr : m] -= Y z with z = T^T (Y^T bt) from
@@ -1644,63 +1785,52 @@ __device__ inline void wy_t_columns(const double (*Wl)[KM + 1], const double* ta
 
 // part: nblk partial Gram blocks of V (the panel's workgroups, or 128-row
 // blocks), or, when the CholeskyQR2 kernels factored the panel, nblk_cq
-// blocks of [V, bt] (the CholeskyQR2 second row pass): then tau_t = 2 / ||v_t||^2, and this kernel
-// also forms z = T^T (V^T bt) for lg_cq_bt and the rows n_P .. n_P + kr - 1 of
-// bt = (I - V T^T V^T) bt.
+// partial vectors V^T bt (the second row pass; T is then lg_cq_b's): this
+// kernel then forms z = T^T (V^T bt) for lg_cq_bt and the rows n_P .. n_P +
+// kr - 1 of bt = (I - V T^T V^T) bt.
 __global__ __launch_bounds__(WG, 1) void lg_panel_b(LgArgs a, const double* part, int nblk, int nblk_cq) {
     __shared__ WgShared s;
     __shared__ double Tl[KM][KM + 1];
     __shared__ double Wl[KM][KM + 1];
-    __shared__ double zl[CQ_MAX];
+    __shared__ double cl[CQ_MAX], zl[CQ_MAX];
     ctl_load(s, a.ctl);
     Wg wg(a.p, a.prm, s);
     const Prob& p = a.p;
-    const int kr = s.kr, kq = p.kq, tid = threadIdx.x;
-    const bool cq = a.ex->cq_ok != 0;
-    // T of the compact WY form, from V^T V (summed from the partial blocks)
-    if (cq) {
-        gram_upper(part, nblk_cq, kr + 1, [&](int i, int t, double v) { Wl[i][t] = v; });
-        __syncthreads();
-        if (tid < kr) s.tau[tid] = 2.0 / Wl[tid][tid];
-    } else {
-        gram_upper(part, nblk, kr, [&](int i, int t, double v) { Wl[i][t] = v; });
-    }
-    __syncthreads();
-    if (tid < 64) {
-        if (kr <= 32) {
-            wy_t_columns<32>(Wl, s.tau, kr, Tl, tid);
-        } else {
-            // same order of operations, the partial sums kept in Tl itself
-            const int j = tid;
-            if (j < kr) {
-                for (int i = 0; i < kr; ++i) Tl[i][j] = 0.0;
-                for (int i = kr - 1; i >= 0; --i) {
-                    const double tij = (i > j) ? 0.0 : (i == j) ? s.tau[i] : -s.tau[i] * Tl[i][j];
-                    Tl[i][j] = tij;
-                    for (int i2 = 0; i2 < i; ++i2) Tl[i2][j] = fma(Wl[i2][i], tij, Tl[i2][j]);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < kr * kq; e += WG) {
-        const int i = e % kq, t = e / kq;
-        p.T[(size_t)t * kq + i] = (i < kr) ? Tl[i][t] : 0.0;
-    }
+    const int kr = s.kr, kq = p.kq, tid = threadIdx.x, m = p.m;
     const int r0 = s.nP;
+    const bool cq = a.ex->cq_ok != 0;
     if (cq) {
-        // z = T^T (V^T bt) (T is upper triangular, zero below its diagonal in Tl)
+        // V^T bt: the partial vectors in block order
+        if (tid < kr) {
+            double c = 0.0;
+            for (int b0 = 0; b0 < nblk_cq; b0 += 32) {
+                double v[32];
+#pragma unroll
+                for (int bb = 0; bb < 32; ++bb)
+                    v[bb] = (b0 + bb < nblk_cq) ? part[(size_t)(b0 + bb) * GP_STRIDE + tid] : 0.0;
+#pragma unroll
+                for (int bb = 0; bb < 32; ++bb)
+                    if (b0 + bb < nblk_cq) c += v[bb];
+            }
+            cl[tid] = c;
+        }
+        // column tid of T and row tid of the top block of V (both from global
+        // memory, loaded ahead of the barrier)
+        double tc[CQ_MAX], y1[CQ_MAX];
+#pragma unroll
+        for (int i = 0; i < CQ_MAX; ++i) {
+            tc[i] = (tid < kr && i <= tid) ? p.T[(size_t)tid * kq + i] : 0.0;
+            y1[i] = (tid < kr && i <= tid) ? a.cq[CQ_Y1 + tid * CQ_MAX + i] : 0.0;
+        }
+        __syncthreads();
         if (tid < kr) {
             double z = 0.0;
 #pragma unroll
             for (int i = 0; i < CQ_MAX; ++i)
-                if (i < kr) z = fma(Tl[i][tid], Wl[i][kr], z);
+                if (i < kr) z = fma(tc[i], cl[i], z);
             zl[tid] = z;
             a.cq[CQ_Z + tid] = z;
         }
-        double y1[CQ_MAX];   // row tid of the top block of V
-#pragma unroll
-        for (int t = 0; t < CQ_MAX; ++t) y1[t] = (tid < kr && t < kr) ? a.cq[CQ_Y1 + tid * CQ_MAX + t] : 0.0;
         __syncthreads();
         if (tid < kr) {
             double acc = 0.0;
@@ -1710,12 +1840,42 @@ __global__ __launch_bounds__(WG, 1) void lg_panel_b(LgArgs a, const double* part
             p.bt[r0 + tid] -= acc;
         }
         if (tid == 0) a.ex->ncq += 1;
+    } else {
+        // T of the compact WY form, from V^T V (summed from the partial blocks)
+        gram_upper(part, nblk, kr, [&](int i, int t, double v) { Wl[i][t] = v; });
         __syncthreads();
+        if (tid < 64) {
+            if (kr <= 32) {
+                wy_t_columns<32>(Wl, s.tau, kr, Tl, tid);
+            } else {
+                // same order of operations, the partial sums kept in Tl itself
+                const int j = tid;
+                if (j < kr) {
+                    for (int i = 0; i < kr; ++i) Tl[i][j] = 0.0;
+                    for (int i = kr - 1; i >= 0; --i) {
+                        const double tij = (i > j) ? 0.0 : (i == j) ? s.tau[i] : -s.tau[i] * Tl[i][j];
+                        Tl[i][j] = tij;
+                        for (int i2 = 0; i2 < i; ++i2) Tl[i2][j] = fma(Wl[i2][i], tij, Tl[i2][j]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < kr * kq; e += WG) {
+            const int i = e % kq, t = e / kq;
+            p.T[(size_t)t * kq + i] = (i < kr) ? Tl[i][t] : 0.0;
+        }
     }
+    __syncthreads();
     // feasibility loop on J: longest prefix of J whose own LS components are positive
-    for (int e = tid; e < kr * kr; e += WG) {
-        const int i = e % kr, t = e / kr;
-        Wl[i][t] = (i <= t) ? p.R[(size_t)p.slot[r0 + t] * p.kc + r0 + i] : 0.0;
+    if (cq) {
+        // the new diagonal block of R, as lg_cq_b wrote it into R
+        for (int e = tid; e < CQ_SQ; e += WG) Wl[e / CQ_MAX][e % CQ_MAX] = a.cq[CQ_R22 + e];
+    } else {
+        for (int e = tid; e < kr * kr; e += WG) {
+            const int i = e % kr, t = e / kr;
+            Wl[i][t] = (i <= t) ? p.R[(size_t)p.slot[r0 + t] * p.kc + r0 + i] : 0.0;
+        }
     }
     __syncthreads();
     if (tid < 64) {

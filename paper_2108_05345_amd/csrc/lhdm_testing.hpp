@@ -161,10 +161,10 @@ static int test_downdate(hipStream_t st, int engine, int m, int nP, const double
 // The one-wave factorisations of the CholeskyQR2 panel on caller matrices
 // (column-major n x n in, column-major n x n out).
 __global__ __launch_bounds__(WG, 1) void test_cq_factors_kernel(int n, const double* G, const double* W, double* R,
-                                                                double* Ri, double* L, double* Ui, double* sg,
+                                                                double* Ri, double* U, double* Li, double* sg,
                                                                 double* sin2) {
     __shared__ double G_[CQ_MAX][CQ_MAX + 1], W_[CQ_MAX][CQ_MAX + 1], R_[CQ_MAX][CQ_MAX + 1],
-        Ri_[CQ_MAX][CQ_MAX + 1], L_[CQ_MAX][CQ_MAX + 1], Ui_[CQ_MAX][CQ_MAX + 1];
+        Ri_[CQ_MAX][CQ_MAX + 1], U_[CQ_MAX][CQ_MAX + 1], Li_[CQ_MAX][CQ_MAX + 1];
     __shared__ double sg_[CQ_MAX], rowbuf_[64];
     const int tid = threadIdx.x;
     for (int e = tid; e < CQ_SQ; e += WG) {
@@ -177,25 +177,25 @@ __global__ __launch_bounds__(WG, 1) void test_cq_factors_kernel(int n, const dou
     if (wave_index() == 0) {
         const double q = chol_inv_wave((CqRow*)G_, n, (CqRow*)R_, (CqRow*)Ri_, (lds_double*)rowbuf_);
         if (tid == 0) *sin2 = q;
-        lu_inv_wave((CqRow*)W_, n, (CqRow*)L_, (CqRow*)Ui_, (lds_double*)sg_);
+        lu_rows_wave((CqRow*)W_, n, (CqRow*)U_, (CqRow*)Li_, (lds_double*)sg_);
     }
     __syncthreads();
     for (int e = tid; e < n * n; e += WG) {
         const int j = e / n, i = e % n;
         R[e] = R_[i][j];
         Ri[e] = Ri_[i][j];
-        L[e] = L_[i][j];
-        Ui[e] = Ui_[i][j];
+        U[e] = U_[i][j];
+        Li[e] = Li_[i][j];
     }
     if (tid < n) sg[tid] = sg_[tid];
 }
 
-static int test_cq_factors(hipStream_t st, int n, const double* G, const double* W, double* R, double* Ri, double* L,
-                           double* Ui, double* sg, double* sin2) {
-    if (n < 1 || n > CQ_MAX || !G || !W || !R || !Ri || !L || !Ui || !sg || !sin2) return LHDM_EINVAL;
+static int test_cq_factors(hipStream_t st, int n, const double* G, const double* W, double* R, double* Ri, double* U,
+                           double* Li, double* sg, double* sin2) {
+    if (n < 1 || n > CQ_MAX || !G || !W || !R || !Ri || !U || !Li || !sg || !sin2) return LHDM_EINVAL;
     double* d = nullptr;
     HIPCHK(hipMalloc(&d, sizeof(double)));
-    hipLaunchKernelGGL(test_cq_factors_kernel, dim3(1), dim3(WG), 0, st, n, G, W, R, Ri, L, Ui, sg, d);
+    hipLaunchKernelGGL(test_cq_factors_kernel, dim3(1), dim3(WG), 0, st, n, G, W, R, Ri, U, Li, sg, d);
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipMemcpyAsync(sin2, d, sizeof(double), hipMemcpyDeviceToHost, st);
     const hipError_t e3 = hipStreamSynchronize(st);
@@ -210,8 +210,8 @@ static int test_cq_factors(hipStream_t st, int n, const double* G, const double*
 }  // namespace lhdm
 
 extern "C" int lhdm_test_cq_factors(void* stream, int32_t n, const double* G, const double* W, double* R, double* Ri,
-                                    double* L, double* Ui, double* sg, double* sin2) {
-    return lhdm::test_cq_factors((hipStream_t)stream, n, G, W, R, Ri, L, Ui, sg, sin2);
+                                    double* U, double* Li, double* sg, double* sin2) {
+    return lhdm::test_cq_factors((hipStream_t)stream, n, G, W, R, Ri, U, Li, sg, sin2);
 }
 
 extern "C" int lhdm_test_downdate(void* stream, int32_t engine, int32_t m, int32_t nP, const double* Q,

@@ -3,13 +3,13 @@
 The test-only C-ABI entry ``lhdm_test_cq_factors`` runs the two one-wave
 factorisations used by the whole-device engine on caller matrices:
 - the Cholesky factor of a Gram matrix together with its inverse;
-- the LU factorisation without pivoting of W - S (the signs S chosen step by
-  step) together with U^{-1}, which is how the Householder reflectors are
-  rebuilt from an orthonormal basis.
+- the LU factorisation without pivoting of W - S = L U (the signs S chosen
+  step by step) together with L^{-1}, which is how the Householder reflectors
+  and their compact-WY factor are rebuilt from an orthonormal basis.
 
 The results are checked against what defines them: R^T R = G, R R^{-1} = I,
-L U = W - S with L unit lower and |U[t][t]| >= 1.  They are also checked against
-numpy's Cholesky and a plain LU with the same sign rule.
+L^{-1} (W - S) = U with L^{-1} unit lower and |U[t][t]| >= 1.  They are also
+checked against numpy's Cholesky and a plain LU with the same sign rule.
 """
 import ctypes
 
@@ -40,8 +40,8 @@ def _run(lib, G, W):
     rc = lib.lhdm_test_cq_factors(torch.cuda.current_stream(d).cuda_stream, n, tG.data_ptr(), tW.data_ptr(),
                                   *[o.data_ptr() for o in outs], sg.data_ptr(), ctypes.byref(sin2))
     assert rc == 0, rc
-    R, Ri, L, Ui = [o.cpu().numpy().reshape(n, n, order="F") for o in outs]
-    return R, Ri, L, Ui, sg.cpu().numpy(), sin2.value
+    R, Ri, U, Li = [o.cpu().numpy().reshape(n, n, order="F") for o in outs]
+    return R, Ri, U, Li, sg.cpu().numpy(), sin2.value
 
 
 def _lu_signed(W):
@@ -66,7 +66,7 @@ def test_factors_against_their_definitions(lib, n):
     G = X.T @ X
     Q, _ = np.linalg.qr(rng.standard_normal((400, n)))
     W = Q[:n, :].copy()
-    R, Ri, L, Ui, sg, sin2 = _run(lib, G, W)
+    R, Ri, U, Li, sg, sin2 = _run(lib, G, W)
     # Cholesky and inverse
     assert np.array_equal(R, np.triu(R)) and (np.diag(R) > 0).all()
     assert np.abs(R.T @ R - G).max() <= 1e-14 * np.abs(G).max()
@@ -75,14 +75,14 @@ def test_factors_against_their_definitions(lib, n):
     Rn = np.linalg.cholesky(G).T
     assert np.abs(R - Rn).max() <= 1e-13 * np.abs(Rn).max()
     assert sin2 == pytest.approx(float(np.min(np.diag(Rn) ** 2 / np.diag(G))), rel=1e-10)
-    # LU of W - S with its signs, and U^{-1}
+    # LU of W - S with its signs, and L^{-1}
     Lr, Ur, sr = _lu_signed(W)
     assert np.array_equal(sg, sr)
-    assert np.array_equal(L, np.tril(L)) and np.array_equal(np.diag(L), np.ones(n))
-    assert np.array_equal(Ui, np.triu(Ui))
-    U = np.linalg.inv(Ui)
-    assert np.abs(L @ U - (W - np.diag(sg))).max() <= 1e-13
+    assert np.array_equal(Li, np.tril(Li)) and np.array_equal(np.diag(Li), np.ones(n))
+    assert np.array_equal(U, np.triu(U))
+    assert np.abs(Li @ (W - np.diag(sg)) - U).max() <= 1e-13
     assert (np.abs(np.diag(U)) >= 1.0 - 1e-12).all()
+    L = np.linalg.inv(Li)
     assert np.abs(L - Lr).max() <= 1e-12 and np.abs(U - Ur).max() <= 1e-12
 
 
