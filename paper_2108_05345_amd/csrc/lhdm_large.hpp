@@ -1238,24 +1238,26 @@ __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
     CqRow* M2i = (CqRow*)M2i_;
     lds_double* sg = (lds_double*)sg_;
     lds_double* sg2 = (lds_double*)sg2_;
-    {
-        double lr[CQ_SQ / WG], lw[CQ_SQ / WG];
+    // R1, Q1's top rows and the new columns' slots are loaded together with
+    // the partial Gram blocks (their LDS stores follow the reduction)
+    double lr[CQ_SQ / WG], lw[CQ_SQ / WG];
+    int sl[CQ_SQ / WG];
 #pragma unroll
-        for (int u = 0; u < CQ_SQ / WG; ++u) {
-            const int e = tid + WG * u, i = e / CQ_MAX, t = e % CQ_MAX;
-            lr[u] = a.cq[CQ_R1 + e];
-            lw[u] = (i < kr && t < kr) ? p.W[(size_t)t * m + r0 + i] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < CQ_SQ / WG; ++u) {
-            const int e = tid + WG * u, i = e / CQ_MAX, t = e % CQ_MAX;
-            R1[i][t] = lr[u];
-            Q1t[i][t] = lw[u];
-            G2[i][t] = 0.0;
-        }
+    for (int u = 0; u < CQ_SQ / WG; ++u) {
+        const int e = tid + WG * u, i = e / CQ_MAX, t = e % CQ_MAX;
+        lr[u] = a.cq[CQ_R1 + e];
+        lw[u] = (i < kr && t < kr) ? p.W[(size_t)t * m + r0 + i] : 0.0;
+        sl[u] = (t < kr) ? p.slot[r0 + t] : 0;
+        G2[i][t] = 0.0;
     }
     __syncthreads();
     gram_upper(a.gpart, nb, kr, [&](int i, int t, double v) { G2[i][t] = v; });
+#pragma unroll
+    for (int u = 0; u < CQ_SQ / WG; ++u) {
+        const int e = tid + WG * u, i = e / CQ_MAX, t = e % CQ_MAX;
+        R1[i][t] = lr[u];
+        Q1t[i][t] = lw[u];
+    }
     __syncthreads();
     if (wv == 0) {
         // largest deviation of Q1^T Q1 from the identity (upper triangle)
@@ -1340,12 +1342,6 @@ __global__ __launch_bounds__(WG, 1) void lg_cq_b(LgArgs a) {
     mm32(R2i, Ui, M2i);   // (U R2)^{-1} = R2^{-1} U^{-1}
     __syncthreads();
     {
-        int sl[CQ_SQ / WG];
-#pragma unroll
-        for (int u = 0; u < CQ_SQ / WG; ++u) {
-            const int j = (tid + WG * u) % CQ_MAX;
-            sl[u] = (j < kr) ? p.slot[r0 + j] : 0;
-        }
 #pragma unroll
         for (int u = 0; u < CQ_SQ / WG; ++u) {
             const int e = tid + WG * u, i = e / CQ_MAX, j = e % CQ_MAX;
