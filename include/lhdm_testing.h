@@ -44,6 +44,23 @@ int lhdm_test_downdate(void* stream, int32_t engine, int32_t m, int32_t nP, cons
                        double* Q_out, double* R_out, double* bt_out, int32_t* P_out,
                        int32_t* sweeps);
 
+/* The least-squares step of Algorithms 1 and 3: the back substitution R y =
+ * bt of the whole-device engine, exactly as the solver runs it (64-row blocks
+ * chained across workgroups from the bottom; a full block far enough up the
+ * chain is solved through the inverse of its row-scaled diagonal block, formed
+ * while it waits, the others by substitution).
+ *   R  [dev] n x n, column-major (ld n), upper triangular with a nonzero
+ *      diagonal (entries below the diagonal are ignored).
+ *   bt [dev] n: the right-hand side.
+ *   y  [dev] n: the solution.
+ *   inv_blocks [host, may be NULL]: how many blocks are eligible for the
+ *      inverse form (one whose inverse has a non-finite entry falls back to
+ *      substitution).
+ * 1 <= n <= 8192.  Returns LHDM_EINVAL on bad sizes or pointers,
+ * LHDM_EUNSUPPORTED for n > 8192, LHDM_EHIP when a block's wait timed out. */
+int lhdm_test_trsv(void* stream, int32_t n, const double* R, const double* bt, double* y,
+                   int32_t* inv_blocks);
+
 /* The small factorisations of the whole-device engine's CholeskyQR2 panel
  * (Householder reconstruction from an orthonormal basis), each run by one wave
  * as in the solver:
@@ -52,11 +69,15 @@ int lhdm_test_downdate(void* stream, int32_t engine, int32_t m, int32_t nP, cons
  *     sin2 [host]: the smallest R[t][t]^2 / G[t][t], or -1 when a pivot is not a
  *     positive finite number.
  *   W [dev] n x n, column-major: LU without pivoting of W - S = L U with S =
- *     diag(sg), sg[t] = +1 when step t's pivot is negative and -1 otherwise:
- *     U [dev] n x n upper, Li [dev] n x n = L^{-1} (unit lower), sg [dev] n.
+ *     diag(sg), sg[t] = +1 when step t's pivot is negative and -1 otherwise,
+ *     by row elimination (U [dev] n x n upper, Li [dev] n x n = L^{-1}, unit
+ *     lower, sg [dev] n) and, on a second wave at the same time, by column
+ *     elimination (L [dev] n x n unit lower, Ui [dev] n x n = U^{-1}, sg2 [dev]
+ *     n), as the solver runs both.
  * 1 <= n <= 32.  Returns LHDM_EINVAL on bad sizes or pointers. */
 int lhdm_test_cq_factors(void* stream, int32_t n, const double* G, const double* W, double* R, double* Ri,
-                         double* U, double* Li, double* sg, double* sin2);
+                         double* U, double* Li, double* L, double* Ui, double* sg, double* sg2,
+                         double* sin2);
 
 #ifdef __cplusplus
 }

@@ -87,7 +87,8 @@ SIGNATURES = {
     # test-only entry points (include/lhdm_testing.h)
     "lhdm_test_downdate": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _pi32, _vp, _vp, _vp, _pi32,
                                           _pi32]),
-    "lhdm_test_cq_factors": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+    "lhdm_test_trsv": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _pi32]),
+    "lhdm_test_cq_factors": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                             ctypes.POINTER(ctypes.c_double)]),
 }
 

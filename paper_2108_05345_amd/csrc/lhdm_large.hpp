@@ -3164,6 +3164,89 @@ __global__ __launch_bounds__(WG) void lg_qup2v(LgArgs a, int cpw) {
 // barrier in the loop); the R entries of a dependency block are loaded before
 // its part of y is awaited.
 // --------------------------------------------------------------------------
+// Blocks at least TRSV_CHAIN places from the bottom of the chain wait long
+// enough for their four waves to invert the row-scaled diagonal block first;
+// their final step is then one product with the inverse instead of a chain of
+// 64 dependent steps.  The forward error of either form is bounded by the same
+// |U^{-1}| |U| |y| (the inverse itself is formed by substitution).
+constexpr int TRSV_CHAIN = 4;
+
+// Inverse of the unit upper triangular 64 x 64 block U (row-scaled, diagonal
+// 1, strictly upper part in U[i][j], i < j) into X[i][j], i <= j, by the four
+// waves of the workgroup: the 16 x 16 diagonal tiles by back substitution
+// (lane c of wave w forms column c of tile w), then the off-diagonal tiles
+// from the block identity [A B; 0 C]^{-1} = [A^{-1}, -A^{-1} B C^{-1}; 0,
+// C^{-1}] on 16- and then 32-wide blocks, with the products on the FP64
+// matrix cores.  Entries of X below the diagonal tiles are not written.
+// tw: 2 x 16 x 17 doubles, t2: 32 x 33 doubles of scratch.  Ends with a
+// workgroup barrier.
+__device__ __forceinline__ void tri_inv64(double (*U)[TB + 1], double (*X)[TB + 1], double (*tw)[16][17],
+                                          double (*t2)[33]) {
+    const int lane = threadIdx.x & 63, wv = wave_index(), r = lane & 15, g = lane >> 4;
+    {
+        const int o = 16 * wv, c = r;
+        double x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 15; k >= 1; --k) {
+            const double xk = x[k];
+#pragma unroll
+            for (int i = 0; i < k; ++i) x[i] = fma(-U[o + i][o + k], xk, x[i]);
+        }
+        if (lane < 16) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) X[o + i][o + c] = x[i];
+        }
+    }
+    __syncthreads();
+    if (wv < 2) {
+        // X[i][j] = -X[i][i] U[i][j] X[j][j] for the tile pair (i, j) = (2w, 2w + 1)
+        const int oi = 32 * wv, oj = oi + 16;
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(U[oi + r][oj + kk + g], X[oj + kk + g][oj + r], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tw[wv][4 * v + g][r] = acc[v];
+        wave_lds_sync();
+        acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[oi + r][oi + kk + g], tw[wv][kk + g][r], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[oi + 4 * v + g][oj + r] = -acc[v];
+    }
+    __syncthreads();
+    // the top-right 32 x 32 block: t2 = B C^{-1}, then -A^{-1} t2, one 16 x 16
+    // output tile (ti, tj) per wave; zero tiles of the triangular factors are skipped
+    const int ti = wv >> 1, tj = wv & 1;
+    {
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        for (int kt = 0; kt <= tj; ++kt) {
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(U[16 * ti + r][32 + 16 * kt + kk + g],
+                                                           X[32 + 16 * kt + kk + g][32 + 16 * tj + r], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) t2[16 * ti + 4 * v + g][16 * tj + r] = acc[v];
+    }
+    __syncthreads();
+    {
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        for (int kt = ti; kt < 2; ++kt) {
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[16 * ti + r][16 * kt + kk + g],
+                                                           t2[16 * kt + kk + g][16 * tj + r], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[16 * ti + 4 * v + g][32 + 16 * tj + r] = -acc[v];
+    }
+    __syncthreads();
+}
+
 // outer != 0: the solve of an outer step, started before the append is
 // committed (n_P is then the step's starting n_P plus the accepted columns).
 __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch, int outer) {
@@ -3178,8 +3261,18 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch, int outer) {
     const int r0 = b * TB, nr = min(nP, r0 + TB) - r0;
     const int tid = threadIdx.x, lane = tid & 63, wv = wave_index();
     __shared__ double part[NW][TB];
-    __shared__ double ys[NW][TB];
+    __shared__ __attribute__((aligned(16))) double ys[NW][TB];
     __shared__ double Rd[TB][TB + 1];
+    __shared__ double Xd[TB][TB + 1];
+    __shared__ double tw[2][16][17];
+    __shared__ double t2[32][33];
+    __shared__ double dinv[TB];
+    // row `lane` past the diagonal of the finishing matrix (the inverse or the
+    // scaled block) and of M: entries (lane, 2 jp) and (lane, 2 jp + 1) at
+    // [jp][lane], so that a lane reads its row with conflict-free 16-byte loads
+    __shared__ double2 fm[TB / 2][TB];
+    __shared__ double2 mq[TB / 2][TB];
+    __shared__ int nonfin;
     {
         // diagonal block: four threads per column, one slot lookup each
         const int cc = tid >> 2, rq = (tid & 3) * (TB / 4);
@@ -3192,29 +3285,100 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch, int outer) {
     }
     const bool rowok = lane < nr;
     const double btv = rowok ? p.bt[r0 + lane] : 0.0;
-    __syncthreads();
-    // the wave that receives the last dependency (block b + 1) finishes the
-    // block; it holds row `lane` of the diagonal block, scaled by the inverse
-    // diagonal entry and restricted to the strictly upper part, in registers
-    const int fw = (b == nb - 1) ? 0 : ((nb - 2 - b) & (NW - 1));
-    double rrow[TB];
-    double rinv = 0.0;
-    if (wv == fw) {
-        rinv = rowok ? 1.0 / Rd[lane][lane] : 0.0;
+    // A full block far enough up the chain is inverted (row-scaled) while it
+    // waits, and the block below it (b + 1, the last to arrive) is folded in:
+    // with X the inverse, D the diagonal and N = R[block b][block b + 1],
+    //   y_b = X D^{-1} (bt_b - sum_{c > b + 1} R[b][c] y_c) - (X D^{-1} N) y_{b+1},
+    // so once y_{b+1} arrives each wave adds 16 of its columns times M =
+    // X D^{-1} N.  Every wave loads its 16 columns of N here.
+    const bool by_inv = g >= TRSV_CHAIN && nr == TB;
+    const int c1 = (b + 1) * TB, nc1 = by_inv ? min(nP, c1 + TB) - c1 : 0;
+    double nv[16];
+    if (by_inv) {
+        const int slv = p.slot[c1 + min(16 * wv + (lane & 15), nc1 - 1)];
+        const double* rowp = p.R + (size_t)(r0 + lane);
 #pragma unroll
-        for (int j = 0; j < TB; ++j) rrow[j] = (j > lane) ? Rd[lane][j] * rinv : 0.0;
+        for (int k = 0; k < 16; ++k) {
+            const int jj = 16 * wv + k;
+            const int sj = __builtin_amdgcn_readlane(slv, max(0, min(k, nc1 - 1 - 16 * wv)));
+            const double val = rowp[(size_t)sj * p.kc];
+            nv[k] = (jj < nc1) ? val : 0.0;
+        }
     }
+    if (tid == 0) nonfin = 0;
+    __syncthreads();
+    if (tid < TB) dinv[tid] = (tid < nr) ? 1.0 / Rd[tid][tid] : 0.0;
+    __syncthreads();
+    if (by_inv) {
+        for (int e = tid; e < TB * TB; e += WG) {
+            const int i = e >> 6, j = e & (TB - 1);
+            if (j > i) Rd[i][j] *= dinv[i];
+        }
+        __syncthreads();
+        tri_inv64(Rd, Xd, tw, t2);
+        bool fin = true;
+        for (int e = tid; e < TB * TB / 2; e += WG) {
+            const int i = e & (TB - 1), jp = e >> 6, j = 2 * jp;
+            const double x0 = (j > i) ? Xd[i][j] : 0.0, x1 = (j + 1 > i) ? Xd[i][j + 1] : 0.0;
+            fin = fin && fabs(x0) < INFINITY && fabs(x1) < INFINITY;
+            fm[jp][i] = double2{x0, x1};
+        }
+        if (!fin) nonfin = 1;
+        __syncthreads();
+    }
+    // every entry of the inverse finite, else the chain on the scaled block
+    const bool use_inv = by_inv && nonfin == 0;
+    double2 mrow[8];   // this wave's 16 columns of row `lane` of M
+    if (use_inv) {
+        // D^{-1} N into Rd (no longer needed), then M = X (D^{-1} N) on the
+        // matrix cores: wave w forms M's column tile w, skipping X's zero tiles
+        const double di = dinv[lane];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) Rd[lane][16 * wv + k] = nv[k] * di;
+        __syncthreads();
+        const int r = lane & 15, gq = lane >> 4;
+        for (int ti = 0; ti < 4; ++ti) {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int kt = ti; kt < 4; ++kt) {
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xd[16 * ti + r][16 * kt + kk + gq],
+                                                               Rd[16 * kt + kk + gq][16 * wv + r], acc, 0, 0, 0);
+            }
+            double* mdst = reinterpret_cast<double*>(&mq[8 * wv + (r >> 1)][0]) + (r & 1);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) mdst[2 * (16 * ti + 4 * v + gq)] = acc[v];
+        }
+        wave_lds_sync();   // the wave reads back only its own column tile
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mrow[k] = mq[8 * wv + k][lane];
+    } else {
+        for (int e = tid; e < TB * TB / 2; e += WG) {
+            const int i = e & (TB - 1), jp = e >> 6, j = 2 * jp;
+            const double sc = by_inv ? 1.0 : dinv[i];   // an inverted block's Rd is already scaled
+            fm[jp][i] = double2{(j > i) ? Rd[i][j] * sc : 0.0, (j + 1 > i) ? Rd[i][j + 1] * sc : 0.0};
+        }
+        __syncthreads();
+    }
+    // the dependency blocks, every fourth one per wave (block b + 1 too when
+    // it is not folded in); the wave that receives block b + 1 finishes a
+    // block solved by substitution
+    const int fw = (b == nb - 1) ? 0 : ((nb - 2 - b) & (NW - 1));
+    const int last = use_inv ? b + 1 : b;
     double acc = 0.0;
-    for (int cb = nb - 1 - wv; cb > b; cb -= NW) {
+    for (int cb = nb - 1 - wv; cb > last; cb -= NW) {
         const int c0 = cb * TB, nc = min(nP, c0 + TB) - c0;
         // the block's slot indices in one vector load, each broadcast from its
-        // lane, so the 64 column loads wait on a single round trip
+        // lane, so the 64 column loads wait on a single round trip; addresses
+        // are clamped into the block and the values masked, with no branch
         const int slv = p.slot[c0 + min(lane, nc - 1)];
+        const double* rowp = p.R + (size_t)(r0 + min(lane, nr - 1));
         double rv[TB];
 #pragma unroll
         for (int j = 0; j < TB; ++j) {
-            const int sj = __builtin_amdgcn_readlane(slv, j);
-            rv[j] = (j < nc && rowok) ? p.R[(size_t)sj * p.kc + r0 + lane] : 0.0;
+            const int sj = __builtin_amdgcn_readlane(slv, min(j, nc - 1));
+            const double val = rowp[(size_t)sj * p.kc];
+            rv[j] = (j < nc && rowok) ? val : 0.0;
         }
         if (cb != b + 1) ll_wait_word(&a.yll[2 * (c0 + nc - 1) + 1], epoch, &a.ex->err);
         const double yv = ll_get<true>(&a.yll[2 * (c0 + min(lane, nc - 1))], lane < nc, epoch, &a.ex->err);
@@ -3233,15 +3397,53 @@ __global__ __launch_bounds__(WG) void lg_trsv(LgArgs a, int epoch, int outer) {
     }
     part[wv][lane] = acc;
     __syncthreads();
-    if (wv != fw) return;
-    // column-oriented back substitution on the row-scaled block: entry j is
-    // final when step j reads it, and is broadcast through the scalar unit
     double v = 0.0;
-    if (rowok) v = (btv - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane])) * rinv;
+    if (rowok) v = (btv - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane])) * dinv[lane];
+    if (use_inv) {
+        // X s over this wave's 16 columns (s broadcast from LDS), before y_{b+1}
+        ys[wv][lane] = v;
+        wave_lds_sync();
+        const double2* s2 = reinterpret_cast<const double2*>(ys[wv]) + 8 * wv;
+        double q0 = 0.0, q1 = 0.0;
 #pragma unroll
-    for (int j = TB - 1; j >= 0; --j) {
-        const double yj = readlane_d(v, j);
-        v = fma(-rrow[j], yj, v);
+        for (int k = 0; k < 8; ++k) {
+            const double2 f = fm[8 * wv + k][lane], sv = s2[k];
+            q0 = fma(f.x, sv.x, q0);
+            q1 = fma(f.y, sv.y, q1);
+        }
+        // then minus M y_{b+1} over the same columns
+        const double yv = ll_get<true>(&a.yll[2 * (c1 + 16 * wv + max(0, min(lane & 15, nc1 - 1 - 16 * wv)))],
+                                       lane < 16, epoch, &a.ex->err);
+        ys[wv][lane] = (16 * wv + lane < nc1 && lane < 16) ? yv : 0.0;
+        wave_lds_sync();
+        const double2* y2 = reinterpret_cast<const double2*>(ys[wv]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double2 yy = y2[k];
+            q0 = fma(-mrow[k].x, yy.x, q0);
+            q1 = fma(-mrow[k].y, yy.y, q1);
+        }
+        __syncthreads();   // every wave is past its reads of part
+        part[wv][lane] = q0 + q1;
+        __syncthreads();
+        if (wv != 0) return;
+        v += ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    } else {
+        if (wv != fw) return;
+        // column-oriented back substitution on the row-scaled block: entry j
+        // is final when step j reads it, and is broadcast through the scalar unit
+        double rrow[TB];
+#pragma unroll
+        for (int jp = 0; jp < TB / 2; ++jp) {
+            const double2 f = fm[jp][lane];
+            rrow[2 * jp] = f.x;
+            rrow[2 * jp + 1] = f.y;
+        }
+#pragma unroll
+        for (int j = TB - 1; j >= 0; --j) {
+            const double yj = readlane_d(v, j);
+            v = fma(-rrow[j], yj, v);
+        }
     }
     if (rowok) {
         ll_put(&a.yll[2 * (r0 + lane)], v, epoch);

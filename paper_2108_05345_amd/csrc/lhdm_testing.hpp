@@ -10,6 +10,8 @@
 
 namespace lhdm {
 
+constexpr int TRSV_TEST_MAX = 8192;   // largest n of the triangular-solve test entry
+
 // One-workgroup engine: the removal set is read from x (x <= 0 marks a
 // removed position) and deleted in one sweep, compaction included.
 __global__ __launch_bounds__(WG) void wg_test_downdate_kernel(Prob p, DevParams prm, int nP) {
@@ -161,11 +163,12 @@ static int test_downdate(hipStream_t st, int engine, int m, int nP, const double
 // The one-wave factorisations of the CholeskyQR2 panel on caller matrices
 // (column-major n x n in, column-major n x n out).
 __global__ __launch_bounds__(WG, 1) void test_cq_factors_kernel(int n, const double* G, const double* W, double* R,
-                                                                double* Ri, double* U, double* Li, double* sg,
-                                                                double* sin2) {
+                                                                double* Ri, double* U, double* Li, double* L,
+                                                                double* Ui, double* sg, double* sg2, double* sin2) {
     __shared__ double G_[CQ_MAX][CQ_MAX + 1], W_[CQ_MAX][CQ_MAX + 1], R_[CQ_MAX][CQ_MAX + 1],
-        Ri_[CQ_MAX][CQ_MAX + 1], U_[CQ_MAX][CQ_MAX + 1], Li_[CQ_MAX][CQ_MAX + 1];
-    __shared__ double sg_[CQ_MAX], rowbuf_[64];
+        Ri_[CQ_MAX][CQ_MAX + 1], U_[CQ_MAX][CQ_MAX + 1], Li_[CQ_MAX][CQ_MAX + 1], L_[CQ_MAX][CQ_MAX + 1],
+        Ui_[CQ_MAX][CQ_MAX + 1];
+    __shared__ double sg_[CQ_MAX], sg2_[CQ_MAX], rowbuf_[64];
     const int tid = threadIdx.x;
     for (int e = tid; e < CQ_SQ; e += WG) {
         const int i = e / CQ_MAX, j = e % CQ_MAX;
@@ -178,6 +181,8 @@ __global__ __launch_bounds__(WG, 1) void test_cq_factors_kernel(int n, const dou
         const double q = chol_inv_wave((CqRow*)G_, n, (CqRow*)R_, (CqRow*)Ri_, (lds_double*)rowbuf_);
         if (tid == 0) *sin2 = q;
         lu_rows_wave((CqRow*)W_, n, (CqRow*)U_, (CqRow*)Li_, (lds_double*)sg_);
+    } else if (wave_index() == 1) {   // the column elimination, as the solver runs it beside the row one
+        lu_inv_wave((CqRow*)W_, n, (CqRow*)L_, (CqRow*)Ui_, (lds_double*)sg2_);
     }
     __syncthreads();
     for (int e = tid; e < n * n; e += WG) {
@@ -186,16 +191,23 @@ __global__ __launch_bounds__(WG, 1) void test_cq_factors_kernel(int n, const dou
         Ri[e] = Ri_[i][j];
         U[e] = U_[i][j];
         Li[e] = Li_[i][j];
+        L[e] = L_[i][j];
+        Ui[e] = Ui_[i][j];
     }
-    if (tid < n) sg[tid] = sg_[tid];
+    if (tid < n) {
+        sg[tid] = sg_[tid];
+        sg2[tid] = sg2_[tid];
+    }
 }
 
 static int test_cq_factors(hipStream_t st, int n, const double* G, const double* W, double* R, double* Ri, double* U,
-                           double* Li, double* sg, double* sin2) {
-    if (n < 1 || n > CQ_MAX || !G || !W || !R || !Ri || !U || !Li || !sg || !sin2) return LHDM_EINVAL;
+                           double* Li, double* L, double* Ui, double* sg, double* sg2, double* sin2) {
+    if (n < 1 || n > CQ_MAX || !G || !W || !R || !Ri || !U || !Li || !L || !Ui || !sg || !sg2 || !sin2)
+        return LHDM_EINVAL;
     double* d = nullptr;
     HIPCHK(hipMalloc(&d, sizeof(double)));
-    hipLaunchKernelGGL(test_cq_factors_kernel, dim3(1), dim3(WG), 0, st, n, G, W, R, Ri, U, Li, sg, d);
+    hipLaunchKernelGGL(test_cq_factors_kernel, dim3(1), dim3(WG), 0, st, n, G, W, R, Ri, U, Li, L, Ui, sg, sg2,
+                       d);
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipMemcpyAsync(sin2, d, sizeof(double), hipMemcpyDeviceToHost, st);
     const hipError_t e3 = hipStreamSynchronize(st);
@@ -207,11 +219,71 @@ static int test_cq_factors(hipStream_t st, int n, const double* G, const double*
     return 0;
 }
 
+// The whole-device engine's chained triangular solve on a caller's n x n R
+// (slots = positions, R's leading dimension n) and right-hand side.
+static int test_trsv(hipStream_t st, int n, const double* R, const double* bt, double* y, int* inv_blocks) {
+    if (n < 1 || !R || !bt || !y) return LHDM_EINVAL;
+    if (n > TRSV_TEST_MAX) return LHDM_EUNSUPPORTED;
+    DevParams prm{};
+    prm.tau1 = 0.6;
+    prm.tau2 = 0.15;
+    prm.delta = 0.9;
+    prm.kkt_tol = 1e-9;
+    prm.kmax = 2;
+    prm.max_outer = 1 << 30;
+    prm.max_inner = 1 << 30;
+    const int m = n;   // kc = n: R's leading dimension is the caller's
+    std::vector<int> ident(n);
+    for (int c = 0; c < n; ++c) ident[c] = c;
+    const LargeLayout L = large_layout(m, n, prm.kmax);
+    DeviceBuffer buf;
+    HIPCHK(hipMalloc(&buf.ptr, L.total));
+    char* base = (char*)buf.ptr;
+    LgArgs a;
+    large_bind(a, L, base, m, n, prm);
+    Prob& p = a.p;
+    HIPCHK(hipMemsetAsync(base + L.flt, 0, L.slot - L.flt, st));
+    HIPCHK(hipMemcpyAsync(p.R, R, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.bt, bt, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.slot, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    Ctl c{};
+    c.nP = n;
+    c.nP0 = n;
+    c.nPa = n;
+    c.k = 1;   // the solve runs after an accepted column
+    c.kr = 1;
+    c.status = LHDM_STATUS_OK;
+    LgExtra ex{};
+    HIPCHK(hipMemcpyAsync(a.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(a.ex, &ex, sizeof(LgExtra), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(lg_trsv, dim3((n + TB - 1) / TB), dim3(WG), 0, st, a, 1, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&ex, a.ex, sizeof(LgExtra), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(y, p.ybuf, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (ex.err) return LHDM_EHIP;
+    if (inv_blocks) {
+        // full 64-row blocks at least TRSV_CHAIN places from the bottom
+        const int nb = (n + TB - 1) / TB, full = n / TB;
+        int cnt = 0;
+        for (int g = TRSV_CHAIN; g < nb; ++g)
+            if (nb - 1 - g < full) ++cnt;
+        *inv_blocks = cnt;
+    }
+    return 0;
+}
+
 }  // namespace lhdm
 
+extern "C" int lhdm_test_trsv(void* stream, int32_t n, const double* R, const double* bt, double* y,
+                              int32_t* inv_blocks) {
+    return lhdm::test_trsv((hipStream_t)stream, n, R, bt, y, inv_blocks);
+}
+
 extern "C" int lhdm_test_cq_factors(void* stream, int32_t n, const double* G, const double* W, double* R, double* Ri,
-                                    double* U, double* Li, double* sg, double* sin2) {
-    return lhdm::test_cq_factors((hipStream_t)stream, n, G, W, R, Ri, U, Li, sg, sin2);
+                                    double* U, double* Li, double* L, double* Ui, double* sg, double* sg2,
+                                    double* sin2) {
+    return lhdm::test_cq_factors((hipStream_t)stream, n, G, W, R, Ri, U, Li, L, Ui, sg, sg2, sin2);
 }
 
 extern "C" int lhdm_test_downdate(void* stream, int32_t engine, int32_t m, int32_t nP, const double* Q,

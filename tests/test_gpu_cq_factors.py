@@ -1,15 +1,17 @@
 """The small factorisations of the CholeskyQR2 panel, on the GPU.
 
-The test-only C-ABI entry ``lhdm_test_cq_factors`` runs the two one-wave
+The test-only C-ABI entry ``lhdm_test_cq_factors`` runs the one-wave
 factorisations used by the whole-device engine on caller matrices:
 - the Cholesky factor of a Gram matrix together with its inverse;
 - the LU factorisation without pivoting of W - S = L U (the signs S chosen
-  step by step) together with L^{-1}, which is how the Householder reflectors
-  and their compact-WY factor are rebuilt from an orthonormal basis.
+  step by step), by row elimination (U and L^{-1}) and by column elimination
+  (L and U^{-1}) side by side, which is how the Householder reflectors and
+  their compact-WY factor are rebuilt from an orthonormal basis.
 
 The results are checked against what defines them: R^T R = G, R R^{-1} = I,
-L^{-1} (W - S) = U with L^{-1} unit lower and |U[t][t]| >= 1.  They are also
-checked against numpy's Cholesky and a plain LU with the same sign rule.
+L^{-1} (W - S) = U with L^{-1} unit lower and |U[t][t]| >= 1, the two
+eliminations' signs equal and their factors each other's inverses.  They are
+also checked against numpy's Cholesky and a plain LU with the same sign rule.
 """
 import ctypes
 
@@ -34,14 +36,16 @@ def _run(lib, G, W):
     d = torch.device("cuda:0")
     tG = torch.from_numpy(np.asfortranarray(G).ravel(order="F").copy()).to(d)
     tW = torch.from_numpy(np.asfortranarray(W).ravel(order="F").copy()).to(d)
-    outs = [torch.zeros(n * n, dtype=torch.float64, device=d) for _ in range(4)]
+    outs = [torch.zeros(n * n, dtype=torch.float64, device=d) for _ in range(6)]
     sg = torch.zeros(n, dtype=torch.float64, device=d)
+    sg2 = torch.zeros(n, dtype=torch.float64, device=d)
     sin2 = ctypes.c_double()
     rc = lib.lhdm_test_cq_factors(torch.cuda.current_stream(d).cuda_stream, n, tG.data_ptr(), tW.data_ptr(),
-                                  *[o.data_ptr() for o in outs], sg.data_ptr(), ctypes.byref(sin2))
+                                  *[o.data_ptr() for o in outs], sg.data_ptr(), sg2.data_ptr(), ctypes.byref(sin2))
     assert rc == 0, rc
-    R, Ri, U, Li = [o.cpu().numpy().reshape(n, n, order="F") for o in outs]
-    return R, Ri, U, Li, sg.cpu().numpy(), sin2.value
+    R, Ri, U, Li, L, Ui = [o.cpu().numpy().reshape(n, n, order="F") for o in outs]
+    assert np.array_equal(sg.cpu().numpy(), sg2.cpu().numpy())
+    return R, Ri, U, Li, L, Ui, sg.cpu().numpy(), sin2.value
 
 
 def _lu_signed(W):
@@ -66,7 +70,7 @@ def test_factors_against_their_definitions(lib, n):
     G = X.T @ X
     Q, _ = np.linalg.qr(rng.standard_normal((400, n)))
     W = Q[:n, :].copy()
-    R, Ri, U, Li, sg, sin2 = _run(lib, G, W)
+    R, Ri, U, Li, L, Ui, sg, sin2 = _run(lib, G, W)
     # Cholesky and inverse
     assert np.array_equal(R, np.triu(R)) and (np.diag(R) > 0).all()
     assert np.abs(R.T @ R - G).max() <= 1e-14 * np.abs(G).max()
@@ -82,8 +86,12 @@ def test_factors_against_their_definitions(lib, n):
     assert np.array_equal(U, np.triu(U))
     assert np.abs(Li @ (W - np.diag(sg)) - U).max() <= 1e-13
     assert (np.abs(np.diag(U)) >= 1.0 - 1e-12).all()
-    L = np.linalg.inv(Li)
     assert np.abs(L - Lr).max() <= 1e-12 and np.abs(U - Ur).max() <= 1e-12
+    # the column elimination: L unit lower, U^{-1} upper, each the other's inverse
+    assert np.array_equal(L, np.tril(L)) and np.array_equal(np.diag(L), np.ones(n))
+    assert np.array_equal(Ui, np.triu(Ui))
+    assert np.abs(L @ Li - np.eye(n)).max() <= 1e-12
+    assert np.abs(U @ Ui - np.eye(n)).max() <= 1e-12
 
 
 def test_not_positive_definite(lib):
