@@ -43,6 +43,7 @@ struct LgExtra {
     int first;        // first removed position of the current downdate
     int ndown;        // number of new columns from `first` on
     int totrot;       // rotations of the current downdate
+    int cfok;         // epoch of the last downdate done in closed form
     int nrecomp;      // columns flagged for an exact norm recomputation
     int nvec;         // vectors of the dual update (r, added, dropped or trailing)
     int kadd;         // added directions in the dual update
@@ -288,6 +289,7 @@ __global__ __launch_bounds__(WG) void lg_init_ctl(LgArgs a, const unsigned long 
         a.ex->nrecomp = 0;
         a.ex->cq_ok = 0;
         a.ex->ncq = 0;
+        a.ex->cfok = 0;
     }
     ctl_store(s, a.ctl);
 }
@@ -3483,6 +3485,292 @@ __device__ __forceinline__ void givens_lane(double a, double b, int t, double& c
     }
 }
 
+// Algorithm 5 for a single removal, in closed form.  Deleting the column at
+// position p leaves, in rows p.., the carried row r (row p) over an upper
+// triangular T (rows p + 1.., one column to the left), and the new trailing
+// factor R' satisfies R'^T R' = T^T T + r r^T.  The rotation that zeroes T_aa
+// against the carried row (rho > 0, c = carried / rho, s = T_aa / rho, as the
+// chained path takes it) has a closed form: with v = T^{-T} r, sigma_a = 1 +
+// sum_{i<=a} v_i^2 and pi_a = prod_{i<a} (-sign T_ii), the carried entry is
+// pi_a T_aa v_a / sqrt(sigma_{a-1}), so
+//   c_a = pi_a sign(T_aa) v_a / sqrt(sigma_a),
+//   s_a = sign(T_aa) sqrt(sigma_{a-1} / sigma_a).
+// The serial part is one forward substitution for v, chained over the blocks
+// of 64 new columns (each block waits for the v of the blocks before it); the
+// sums and sign products are scans; each column then applies its rotations on
+// its own.  The forward substitution is backward stable, so the entry that
+// each column's last rotation leaves below its diagonal stays at rounding
+// level whatever the conditioning of T.  Values pass between blocks through
+// the epoch-tagged words of rotll past the chained path's 4 kc, which a single
+// removal never uses.  A block whose rotations are not finite or not of unit
+// norm (sigma overflowing, a zero pivot) makes every block leave its columns
+// unchanged for the chained path (lg_givens, launched next).  On success
+// ex->cfok = epoch and lg_givens has nothing left to do.
+//
+// One workgroup of four waves per 64 new columns.  Column j of the block is
+// new column idx = 64 b + j; its entries in rows p.. sit contiguously in its
+// storage, so every load and store below takes 64 consecutive rows of one
+// column (lane = row), and LDS turns them into columns for the lanes that
+// carry a column's recurrence.
+constexpr int CFW = 16;          // columns of the block per wave in the coalesced passes
+constexpr int CF_MAXROT = 4096;  // rotations a workgroup keeps in LDS (longer downdates: lg_givens)
+__global__ __launch_bounds__(WG) void lg_cfdown(LgArgs a, int epoch) {
+    const LgExtra* ex = a.ex;
+    if (ex->inner_done) return;   // launched before the host reads the inner decision
+    const int nd = ex->ndown, first = ex->first;
+    if (ex->totrot != nd || nd < 1 || nd > CF_MAXROT) return;
+    const int b = blockIdx.x, nb = (nd + GB - 1) / GB;
+    if (b >= nb) return;
+    const Prob& p = a.p;
+    const int tid = threadIdx.x, lane = tid & 63, wv = wave_index();
+    int* err = &a.ex->err;
+    const size_t kc = (size_t)p.kc;
+    u64* cf = a.rotll + 4 * kc;   // v at 2 i, c at 2 (kc + i), s at 2 (2 kc + i); block ends past 6 kc
+    u64* cfe = cf + 6 * kc;       // block b: sigma at 6 b, pi at 6 b + 2, ok at 6 b + 4
+    __shared__ double tl[2][GB][GB + 1];    // tiles [row][column]
+    __shared__ double2 rw[CF_MAXROT];       // rotations (c, s) 0 .. the block's last column
+    __shared__ double vb[GB];
+    __shared__ int okall_s;
+    const int kmax = nd - 1 - b * GB;   // the block's last valid column
+    // this wave's 16 columns: storage of column 16 wv + jj from row p on
+    const int jw = CFW * wv + (lane & (CFW - 1));
+    const int slw = p.slot[a.ocol[b * GB + min(jw, kmax)]];
+    double* hw[CFW];
+#pragma unroll
+    for (int jj = 0; jj < CFW; ++jj)
+        hw[jj] = p.R + (size_t)__builtin_amdgcn_readlane(slw, jj) * kc + first;
+    // wave 0's lane j carries column j: its r (row p) and storage
+    const int idc = min(b * GB + lane, nd - 1);
+    const bool valid = b * GB + lane < nd;
+    double* hc = p.R + (size_t)p.slot[a.ocol[idc]] * kc + first;
+    const double r0 = (wv == 0) ? hc[0] : 0.0;
+    // the block's diagonal tile T[64 b + k][column j] (rows clamped into storage)
+    {
+        const int rr = 1 + min(b * GB + lane, nd - 1);
+#pragma unroll
+        for (int jj = 0; jj < CFW; ++jj) tl[1][lane][CFW * wv + jj] = hw[jj][rr];
+    }
+    __syncthreads();
+    // its diagonal, and the strictly upper part scaled by the row's inverse
+    // diagonal entry (zero elsewhere), ahead of the wait for the blocks before
+    if (tid < GB) vb[tid] = tl[1][min(tid, kmax)][tid];
+    __syncthreads();
+    for (int e = tid; e < GB * GB; e += WG) {
+        const int k = e >> 6, j = e & (GB - 1);
+        tl[1][k][j] = (k < j) ? tl[1][k][j] / vb[k] : 0.0;
+    }
+    // forward substitution, the blocks before this one: lane k of every wave
+    // accumulates T[64 c + k][j] v_{64 c + k} for its 16 columns
+    double acc[CFW];
+#pragma unroll
+    for (int jj = 0; jj < CFW; ++jj) acc[jj] = 0.0;
+    if (b > 0) {
+        double tv[CFW];
+#pragma unroll
+        for (int jj = 0; jj < CFW; ++jj) tv[jj] = hw[jj][1 + lane];   // block 0's rows (below every column here)
+        for (int c = 0; c < b; ++c) {
+            double tn[CFW];
+            const int cn = min(c + 1, b - 1);
+#pragma unroll
+            for (int jj = 0; jj < CFW; ++jj) tn[jj] = hw[jj][1 + cn * GB + lane];
+            if (c != b - 1) ll_wait_word(&cf[2 * (c * GB + GB - 1) + 1], epoch, err);
+            // v of block c; wave 0 also takes block c - 1's rotations (long
+            // published) in the same round trip, for the rotation table
+            double vk = 0.0, ck = 0.0, sk = 0.0;
+            bool okv = false, okr = wv != 0 || c == 0;
+            for (long long it = 0;; ++it) {
+                if (!okv) okv = ll_try(&cf[2 * (c * GB + lane)], epoch, vk);
+                if (!okr) {
+                    const int kp = (c - 1) * GB + lane;
+                    okr = ll_try(&cf[2 * (kc + kp)], epoch, ck) && ll_try(&cf[2 * (2 * kc + kp)], epoch, sk);
+                }
+                if (__all(okv && okr)) break;
+                if (it > SPIN_LIMIT) {
+                    if (lane == 0) atomicExch(err, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (wv == 0 && c > 0) rw[(c - 1) * GB + lane] = double2{ck, sk};
+#pragma unroll
+            for (int jj = 0; jj < CFW; ++jj) {
+                acc[jj] = fma(tv[jj], vk, acc[jj]);
+                tv[jj] = tn[jj];
+            }
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < CFW; ++jj) tl[0][lane][CFW * wv + jj] = acc[jj];
+    __syncthreads();
+    if (wv == 0) {
+        // column j's sum over the rows, then this block's part: forward
+        // substitution on the column-scaled diagonal tile, each solved entry
+        // broadcast through the scalar unit
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < GB; ++k) s4[k & 3] += tl[0][k][lane];
+        double v = valid ? r0 - ((s4[0] + s4[1]) + (s4[2] + s4[3])) : 0.0;
+        double tc[GB];
+#pragma unroll
+        for (int k = 0; k < GB; ++k) tc[k] = tl[1][k][lane];
+        const double dg = vb[lane];   // T[idx][idx]
+        const double dl = 1.0 / dg;
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            const double vk = readlane_d(v, k);
+            v = fma(-tc[k], vk, v);
+        }
+        const double vv = valid ? v * dl : 0.0;
+        if (valid) ll_put(&cf[2 * (b * GB + lane)], vv, epoch);
+        // sigma and the sign product across the block (scans), continued from
+        // the previous block's end values
+        double s0 = 1.0, p0 = 1.0, ok0 = 1.0;
+        if (b > 0) {
+            s0 = ll_get<true>(&cfe[6 * (b - 1)], true, epoch, err);
+            p0 = ll_get<true>(&cfe[6 * (b - 1) + 2], true, epoch, err);
+            ok0 = ll_get<true>(&cfe[6 * (b - 1) + 4], true, epoch, err);
+            // the previous block's rotations, for the table
+            const int kp = (b - 1) * GB + lane;
+            const double ck = ll_get<true>(&cf[2 * (kc + kp)], true, epoch, err);
+            const double sk = ll_get<true>(&cf[2 * (2 * kc + kp)], true, epoch, err);
+            rw[kp] = double2{ck, sk};
+        }
+        double inc = vv * vv;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            vb[lane] = inc;
+            wave_lds_sync();
+            if (lane >= d) inc += vb[lane - d];
+            wave_lds_sync();
+        }
+        vb[lane] = inc;
+        wave_lds_sync();
+        const double exc = (lane > 0) ? vb[lane - 1] : 0.0;
+        const double sig = s0 + inc, sigm = s0 + exc;
+        const bool pos = dg > 0.0;
+        const unsigned long long pm = __ballot(valid && pos);
+        const int npos = __popcll(pm & ((1ull << lane) - 1ull));
+        const double pia = (npos & 1) ? -p0 : p0;
+        const double sg = pos ? 1.0 : -1.0;
+        const double rs = 1.0 / sqrt(sig);
+        const double cc = pia * sg * vv * rs, ss = sg * sqrt(sigm) * rs;
+        const bool good = !valid || (dg != 0.0 && fabs(fma(cc, cc, ss * ss) - 1.0) < 0x1p-40);
+        rw[b * GB + lane] = double2{cc, ss};
+        if (valid) {
+            ll_put(&cf[2 * (kc + b * GB + lane)], cc, epoch);
+            ll_put(&cf[2 * (2 * kc + b * GB + lane)], ss, epoch);
+            a.rotbuf[2 * a.roff[b * GB + lane]] = cc;
+            a.rotbuf[2 * a.roff[b * GB + lane] + 1] = ss;
+        }
+        const bool allgood = __all(good) && ok0 != 0.0;
+        const double send = readlane_d(sig, min(kmax, GB - 1));   // sigma at the block's last column
+        if (lane == 0) {
+            ll_put(&cfe[6 * b], send, epoch);
+            ll_put(&cfe[6 * b + 2], (__popcll(pm) & 1) ? -p0 : p0, epoch);
+            ll_put(&cfe[6 * b + 4], allgood ? 1.0 : 0.0, epoch);
+        }
+        // every block's rotations are known once the last block reports (the
+        // blocks are resident together; the wait is bounded): then apply them,
+        // or leave the columns to the chained path
+        const double okall = ll_get<true>(&cfe[6 * (nb - 1) + 4], true, epoch, err);
+        if (lane == 0) okall_s = okall != 0.0;
+    }
+    __syncthreads();
+    if (!okall_s) return;
+    if (b == 0 && tid == 0) a.ex->cfok = epoch;
+    // Apply the rotations, 64 rows at a time: rotation a meets rows p + a and
+    // p + a + 1; column j runs the carried entry down rows 1 .. idx + 1 of its
+    // column (lane j of wave 0), and its rows p .. p + idx + 1 are rewritten
+    // (the last one to the zero its own rotation made).  All four waves load
+    // and store the tiles (coalesced); the next tile's loads are in flight
+    // while the current one is rotated.
+    const int amax = min(nd - 1, b * GB + GB - 1);
+    const int ntile = amax / GB + 1;
+    double carry = r0;
+    const int idx = b * GB + lane;
+    auto load_tile = [&](int t, double (&ld)[CFW]) {
+#pragma unroll
+        for (int jj = 0; jj < CFW; ++jj) ld[jj] = hw[jj][1 + min(t * GB + lane, nd - 1)];
+    };
+    auto put_tile = [&](int buf, const double (&ld)[CFW]) {
+#pragma unroll
+        for (int jj = 0; jj < CFW; ++jj) tl[buf][lane][CFW * wv + jj] = ld[jj];
+    };
+    // wave 0 rotates its column's 64 rows of tile t, eight at a time: the
+    // next eight entries and rotations are read while the current ones run
+    constexpr int RB = 8;
+    auto rotate_tile = [&](int t) {
+        const int buf = t & 1;
+        double cq[RB], cn[RB];
+        double2 rq[RB], rn[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            cq[u] = tl[buf][u][lane];
+            rq[u] = rw[min(t * GB + u, amax)];
+        }
+#pragma unroll
+        for (int q = 0; q < GB / RB; ++q) {
+            if (q + 1 < GB / RB) {
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    cn[u] = tl[buf][RB * (q + 1) + u][lane];
+                    rn[u] = rw[min(t * GB + RB * (q + 1) + u, amax)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                // past the column's own rotation the carried entry is never
+                // stored again, so it keeps rotating (no branch); the row the
+                // own rotation zeroed is written as 0, later rows are not stored
+                const int aa = t * GB + RB * q + u;
+                const double nv = fma(rq[u].x, carry, rq[u].y * cq[u]);
+                carry = fma(-rq[u].y, carry, rq[u].x * cq[u]);
+                cq[u] = (aa <= idx) ? nv : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) tl[buf][RB * q + u][lane] = cq[u];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                cq[u] = cn[u];
+                rq[u] = rn[u];
+            }
+        }
+    };
+    // rows p + 64 t + lane of the wave's columns, written up to each column's idx + 1
+    auto store_tile = [&](int t) {
+        const int buf = t & 1;
+#pragma unroll
+        for (int jj = 0; jj < CFW; ++jj) {
+            const int j = CFW * wv + jj;
+            const int aa = t * GB + lane;
+            if (b * GB + j < nd && aa <= b * GB + j + 1) hw[jj][aa] = tl[buf][lane][j];
+        }
+    };
+    // two tiles in flight: tile t + 1 waits in registers while tile t is
+    // rotated, and tile t + 2's loads go out after tile t's stores
+    double ra[CFW], rb[CFW];
+    load_tile(0, ra);
+    if (ntile > 1) load_tile(1, rb);
+    put_tile(0, ra);
+    if (ntile > 2) load_tile(2, ra);
+    __syncthreads();
+    for (int t = 0; t < ntile; t += 2) {
+        if (wv == 0) rotate_tile(t);
+        __syncthreads();
+        store_tile(t);
+        if (t + 1 < ntile) put_tile(1, rb);
+        if (t + 3 < ntile) load_tile(t + 3, rb);
+        __syncthreads();
+        if (t + 1 >= ntile) break;
+        if (wv == 0) rotate_tile(t + 1);
+        __syncthreads();
+        store_tile(t + 1);
+        if (t + 2 < ntile) put_tile(0, ra);
+        if (t + 4 < ntile) load_tile(t + 4, ra);
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     const LgExtra* ex = a.ex;
     if (ex->inner_done) return;   // launched before the host reads the inner decision
@@ -3497,6 +3785,7 @@ __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     int* err = &a.ex->err;
     __shared__ double win[GW][64];
     __shared__ double rcl[RQ], rsl[RQ];
+    if (ex->cfok == epoch) return;   // done in closed form by lg_cfdown
     // lanes past the last new column read the last one's storage (never written)
     double* col = p.R + (size_t)p.slot[a.ocol[valid ? idx : nd - 1]] * p.kc;
     // A full own block's rows 1..64 are touched by no earlier block: they are
@@ -4255,6 +4544,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             // checking it on the device: the downdate of an inner step, and
             // x = y with the residual partials when the inner loop ends
             ++ep_g;
+            hipLaunchKernelGGL(lg_cfdown, dim3((p.kc + GB - 1) / GB), dim3(WG), 0, cs, a, ep_g);
             hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, cs, a, ep_g);
             hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, cs, a);
             HIPCHK(hipGetLastError());

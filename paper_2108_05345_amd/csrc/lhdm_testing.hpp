@@ -118,7 +118,9 @@ static int test_downdate(hipStream_t st, int engine, int m, int nP, const double
         int left = q, ep_g = 0, pub = 0;
         while (left > 0) {
             hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, st, a, ++pub);
-            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ++ep_g);
+            ++ep_g;
+            hipLaunchKernelGGL(lg_cfdown, dim3((p.kc + GB - 1) / GB), dim3(WG), 0, st, a, ep_g);
+            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, st, a, ep_g);
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(&c, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
             HIPCHK(hipMemcpyAsync(&ex, a.ex, sizeof(LgExtra), hipMemcpyDeviceToHost, st));

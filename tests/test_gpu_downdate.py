@@ -136,6 +136,19 @@ CASES = [
     (40, 12, "random:12", 14),             # every position
 ]
 
+SINGLE = [
+    # one removal (every inner step of the large workloads): the whole-device
+    # engine takes the closed form, chained over blocks of 64 new columns
+    (1024, 1000, "block:1@0", 15),
+    (1024, 1000, "block:1@300", 16),
+    (300, 257, "block:1@190", 19),         # a ragged last block
+    (700, 650, "block:1@649", 18),         # the last position: nothing to rotate
+    # this triangle's forward substitution overflows (entries of O(1) above an
+    # O(1) diagonal grow geometrically), so the closed form hands the removal
+    # to the chained rotations
+    (4096, 4000, "block:1@0", 17),
+]
+
 
 def _positions(spec, nP, seed):
     kind, arg = spec.split(":")
@@ -161,6 +174,16 @@ def test_multi_removal_sweep(lib, engine, case):
     rm = _positions(spec, nP, seed)
     assert len(rm) >= 2
     _compare(lib, engine, Q, R, bt, rm, want_sweeps=1)
+
+
+@pytest.mark.parametrize("engine", [1, 2])
+@pytest.mark.parametrize("case", SINGLE, ids=[f"{c[0]}x{c[1]}-{c[2]}" for c in SINGLE])
+def test_single_removal(lib, engine, case):
+    m, nP, spec, seed = case
+    if engine == 1 and m > 2048:
+        pytest.skip("the one-workgroup engine holds m <= 2048")
+    Q, R, bt = _state(m, nP, seed)
+    _compare(lib, engine, Q, R, bt, _positions(spec, nP, seed), want_sweeps=1)
 
 
 @pytest.mark.parametrize("case", [(4096, 4096, "random:64", 8), (4096, 3500, "random:33", 9)])
