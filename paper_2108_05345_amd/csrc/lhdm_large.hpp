@@ -4541,11 +4541,11 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             const int pi = next_pub();
             hipLaunchKernelGGL(lg_inner, dim3(1), dim3(WG), 0, cs, a, pi);
             // both continuations go out before the decision is read, each
-            // checking it on the device: the downdate of an inner step, and
-            // x = y with the residual partials when the inner loop ends
+            // checking it on the device: the downdate of an inner step (in
+            // closed form for one removal), and x = y with the residual
+            // partials when the inner loop ends
             ++ep_g;
             hipLaunchKernelGGL(lg_cfdown, dim3((p.kc + GB - 1) / GB), dim3(WG), 0, cs, a, ep_g);
-            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, cs, a, ep_g);
             hipLaunchKernelGGL(lg_residual_part, dim3(rgrid, RES_CHUNKS), dim3(WG), 0, cs, a);
             HIPCHK(hipGetLastError());
             if ((rc = wait_pub(pi))) return rc;
@@ -4557,6 +4557,10 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
                 if (mir->ctl.status == LHDM_STATUS_MAXITER) stop = true;
                 break;
             }
+            // the chained rotations, for a removal the closed form declined
+            // (launched once the inner step is known to go on, so the outer
+            // steps do not pay for it; it returns at once after lg_cfdown)
+            hipLaunchKernelGGL(lg_givens, dim3((p.kc + GB - 1) / GB), dim3(64), 0, cs, a, ep_g);
             if (ex_h()->totrot == ex_h()->ndown) {
                 // one rotation per column: bt is rotated with the compaction, and
                 // the Q rotations run on the other stream beside the triangular
