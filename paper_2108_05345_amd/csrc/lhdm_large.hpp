@@ -1969,14 +1969,19 @@ __device__ void inner_body(LgArgs& a, WgShared& s) {
     if (ex->pending) {
         wg.collect_removals();
     } else {
-        double mn = INFINITY;
+        // the smallest y and, in the same pass, the step length (the smallest
+        // ratio x / (x - y) over the positions with y <= 0, which are few)
+        double mn = INFINITY, al = INFINITY;
         const int nP = s.nP;
         for (int c0 = threadIdx.x; c0 < nP; c0 += WG * 8) {
             double v[8];   // eight loads in flight per thread
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = (c0 + WG * u < nP) ? p.ybuf[c0 + WG * u] : INFINITY;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) mn = fmin(mn, v[u]);
+            for (int u = 0; u < 8; ++u) {
+                mn = fmin(mn, v[u]);
+                if (v[u] <= 0.0) al = fmin(al, step_ratio(p.x[p.P[c0 + WG * u]], v[u]));
+            }
         }
         mn = wg.vmin(mn);
         if (mn > 0.0) {
@@ -1998,7 +2003,7 @@ __device__ void inner_body(LgArgs& a, WgShared& s) {
             ctl_store(s, a.ctl);
             return;
         }
-        wg.inner_step();
+        wg.inner_step(true, wg.vmin(al));
     }
     if (threadIdx.x == 0) {
         ex->pending = s.q > RQ;

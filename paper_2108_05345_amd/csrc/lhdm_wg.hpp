@@ -874,21 +874,28 @@ struct Wg {
     }
 
     // a6: one inner iteration: step length, new iterate, removal set.  Leaves
-    // the ascending removal positions in gp.rm[0..s.q).
-    __device__ __forceinline__ void inner_step() {
+    // the ascending removal positions in gp.rm[0..s.q).  have_al: the step
+    // length al_in was already taken (the minimum of the same ratios).
+    __device__ __forceinline__ void inner_step(bool have_al = false, double al_in = 0.0) {
 #pragma clang fp contract(off)
         const int nP = s.nP;
-        double al = INFINITY;
-        for (int c = tid; c < nP; c += WG) {
-            const double yc = yv[c];
-            if (yc <= 0.0) {
-                const double xc = gp.x[gp.P[c]];
-                al = fmin(al, step_ratio(xc, yc));
+        double al = al_in;
+        if (!have_al) {
+            al = INFINITY;
+            for (int c = tid; c < nP; c += WG) {
+                const double yc = yv[c];
+                if (yc <= 0.0) {
+                    const double xc = gp.x[gp.P[c]];
+                    al = fmin(al, step_ratio(xc, yc));
+                }
             }
+            al = vmin(al);
         }
-        al = vmin(al);
         const int chunk = (nP + WG - 1) / WG;
         const int c0 = tid * chunk, c1 = min(nP, c0 + chunk);
+        // the removal flags are taken from the new iterates as they are written
+        int mine = 0;
+        unsigned long long mask = 0;
         // the positions of a chunk are distinct columns, so a batch's loads all
         // go out before its stores (a store per position would order every
         // later gathered load behind it)
@@ -908,12 +915,16 @@ struct Wg {
                 if (cb + u < c1) {
                     double xn = xc[u] + al * (yc[u] - xc[u]);
                     if (yc[u] <= 0.0 && step_ratio(xc[u], yc[u]) == al) xn = 0.0;
-                    if (xn <= 0.0) xn = 0.0;
+                    if (xn <= 0.0) {
+                        xn = 0.0;
+                        ++mine;
+                        if (cb + u - c0 < 64) mask |= 1ull << (cb + u - c0);
+                    }
                     gp.x[j[u]] = xn;
                 }
             }
         }
-        collect_removals();
+        place_positions(mine, mask, chunk, c0, c1, [&](int c, int j) { return gp.x[j] <= 0.0; });
     }
 
     // gp.rm[0..s.q) = ascending passive positions whose x is <= 0.
@@ -946,6 +957,15 @@ struct Wg {
                     if (cb + u - c0 < 64) mask |= 1ull << (cb + u - c0);
                 }
         }
+        place_positions(mine, mask, chunk, c0, c1, pick);
+    }
+
+    // gp.rm[0..s.q) from each thread's count of picked positions in its chunk
+    // c0..c1 and, for chunks of at most 64 positions, their bit mask (longer
+    // chunks are scanned again with pick).
+    template <typename Pick>
+    __device__ __forceinline__ void place_positions(int mine, unsigned long long mask, int chunk, int c0, int c1,
+                                                    Pick pick) {
         // exclusive prefix sum of the counts in thread order: a scan within
         // each wave, then the totals of the waves before it
         int incl = mine;
