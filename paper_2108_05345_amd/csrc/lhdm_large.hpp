@@ -3702,16 +3702,20 @@ __global__ __launch_bounds__(WG) void lg_cfdown(LgArgs a, int epoch) {
         for (int jj = 0; jj < CFW; ++jj) tl[buf][lane][CFW * wv + jj] = ld[jj];
     };
     // wave 0 rotates its column's 64 rows of tile t, eight at a time: the
-    // next eight entries and rotations are read while the current ones run
+    // next eight entries and rotations are read while the current ones run.
+    // Table entries past amax (inside the table: amax + 1 rounds up to at most
+    // CF_MAXROT) are never written; their steps lie past every column's own
+    // rotation, so they only rotate carried entries that are not stored again.
     constexpr int RB = 8;
     auto rotate_tile = [&](int t) {
         const int buf = t & 1;
+        const double2* rt = rw + t * GB;
         double cq[RB], cn[RB];
         double2 rq[RB], rn[RB];
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
             cq[u] = tl[buf][u][lane];
-            rq[u] = rw[min(t * GB + u, amax)];
+            rq[u] = rt[u];
         }
 #pragma unroll
         for (int q = 0; q < GB / RB; ++q) {
@@ -3719,7 +3723,7 @@ __global__ __launch_bounds__(WG) void lg_cfdown(LgArgs a, int epoch) {
 #pragma unroll
                 for (int u = 0; u < RB; ++u) {
                     cn[u] = tl[buf][RB * (q + 1) + u][lane];
-                    rn[u] = rw[min(t * GB + RB * (q + 1) + u, amax)];
+                    rn[u] = rt[RB * (q + 1) + u];
                 }
             }
 #pragma unroll
