@@ -3692,7 +3692,6 @@ __global__ __launch_bounds__(WG) void lg_cfdown(LgArgs a, int epoch) {
     const int amax = min(nd - 1, b * GB + GB - 1);
     const int ntile = amax / GB + 1;
     double carry = r0;
-    const int idx = b * GB + lane;
     auto load_tile = [&](int t, double (&ld)[CFW]) {
 #pragma unroll
         for (int jj = 0; jj < CFW; ++jj) ld[jj] = hw[jj][1 + min(t * GB + lane, nd - 1)];
@@ -3728,13 +3727,12 @@ __global__ __launch_bounds__(WG) void lg_cfdown(LgArgs a, int epoch) {
             }
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
-                // past the column's own rotation the carried entry is never
-                // stored again, so it keeps rotating (no branch); the row the
-                // own rotation zeroed is written as 0, later rows are not stored
-                const int aa = t * GB + RB * q + u;
+                // past the column's own rotation the carried entry and the
+                // rows are never stored again (the row the own rotation zeroed
+                // is stored as 0 by store_tile), so every step runs unmasked
                 const double nv = fma(rq[u].x, carry, rq[u].y * cq[u]);
                 carry = fma(-rq[u].y, carry, rq[u].x * cq[u]);
-                cq[u] = (aa <= idx) ? nv : 0.0;
+                cq[u] = nv;
             }
 #pragma unroll
             for (int u = 0; u < RB; ++u) tl[buf][RB * q + u][lane] = cq[u];
@@ -3752,7 +3750,7 @@ __global__ __launch_bounds__(WG) void lg_cfdown(LgArgs a, int epoch) {
         for (int jj = 0; jj < CFW; ++jj) {
             const int j = CFW * wv + jj;
             const int aa = t * GB + lane;
-            if (b * GB + j < nd && aa <= b * GB + j + 1) hw[jj][aa] = tl[buf][lane][j];
+            if (b * GB + j < nd && aa <= b * GB + j + 1) hw[jj][aa] = (aa <= b * GB + j) ? tl[buf][lane][j] : 0.0;
         }
     };
     // two tiles in flight: tile t + 1 waits in registers while tile t is
