@@ -147,6 +147,9 @@ SINGLE = [
     # O(1) diagonal grow geometrically), so the closed form hands the removal
     # to the chained rotations
     (4096, 4000, "block:1@0", 17),
+    # more new columns (4399) than the closed form keeps rotations for (4096):
+    # the chained rotations again
+    (5000, 4500, "block:1@100", 20),
 ]
 
 
