@@ -3509,8 +3509,8 @@ __device__ __forceinline__ void givens_lane(double a, double b, int t, double& c
 // the epoch-tagged words of rotll past the chained path's 4 kc, which a single
 // removal never uses.  A block whose rotations are not finite or not of unit
 // norm (sigma overflowing, a zero pivot) makes every block leave its columns
-// unchanged for the chained path (lg_givens, launched next).  On success
-// ex->cfok = epoch and lg_givens has nothing left to do.
+// unchanged for the chained path (lg_givens, launched after it with the same
+// epoch).  On success ex->cfok = epoch and lg_givens has nothing left to do.
 //
 // One workgroup of four waves per 64 new columns.  Column j of the block is
 // new column idx = 64 b + j; its entries in rows p.. sit contiguously in its
