@@ -1957,6 +1957,10 @@ __global__ __launch_bounds__(WG) void lg_commit(LgArgs a) {
 // removal set, and the per-column layout of the downdate.  A downdating sweep
 // handles at most RQ positions; further removals of the same iteration (their
 // x is already 0) are swept by the next call before any new step is taken.
+// the inner step's register path: IFC positions per thread (n_P <= 4096), and
+// one count per (position slot, wave) in a 64-lane scan
+constexpr int IFC = 16, NWI = WG / 64;
+static_assert(IFC * NWI == 64, "the removal scan takes one count per lane of a wave");
 __device__ void inner_body(LgArgs& a, WgShared& s) {
     ctl_load(s, a.ctl);
     LgExtra* ex = a.ex;
@@ -1968,6 +1972,97 @@ __device__ void inner_body(LgArgs& a, WgShared& s) {
     const Prob& p = a.p;
     if (ex->pending) {
         wg.collect_removals();
+    } else if (s.nP > 0 && s.nP <= WG * IFC) {
+        // One inner iteration with the positions in registers: thread t owns
+        // positions t + WG u (coalesced).  y and P come in one round trip, x in
+        // a second one once the iteration is known to take a step.  The step
+        // length, the new iterate and the removal set are those of
+        // Wg::inner_step, in the same rounding.
+        const int nP = s.nP, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+        double yc[IFC], xc[IFC];
+        int jc[IFC];
+#pragma unroll
+        for (int u = 0; u < IFC; ++u) {
+            const int c = min(tid + WG * u, nP - 1);
+            yc[u] = p.ybuf[c];
+            jc[u] = p.P[c];
+        }
+        double mn = INFINITY;
+#pragma unroll
+        for (int u = 0; u < IFC; ++u)
+            if (tid + WG * u < nP) mn = fmin(mn, yc[u]);
+        mn = wg.vmin(mn);
+        if (mn > 0.0) {
+            if (tid == 0) ex->inner_done = 1;
+            return;
+        }
+        if (s.inner >= a.prm.max_inner) {
+            if (tid == 0) {
+                ex->inner_done = 1;
+                a.ctl->status = LHDM_STATUS_MAXITER;
+            }
+            return;
+        }
+        __syncthreads();
+        if (tid == 0) s.inner += 1;
+        if (a.prm.signflip && wg.sign_flip()) {
+            // y > 0 after the flip (Section 4.2): the inner loop ends, with no downdate
+            if (tid == 0) ex->inner_done = 1;
+            ctl_store(s, a.ctl);
+            return;
+        }
+#pragma unroll
+        for (int u = 0; u < IFC; ++u) xc[u] = p.x[jc[u]];
+        double al = INFINITY;
+#pragma unroll
+        for (int u = 0; u < IFC; ++u)
+            if (tid + WG * u < nP && yc[u] <= 0.0) al = fmin(al, step_ratio(xc[u], yc[u]));
+        al = wg.vmin(al);
+        unsigned fl = 0;   // bit u: position tid + WG u leaves the passive set
+        {
+#pragma clang fp contract(off)
+#pragma unroll
+            for (int u = 0; u < IFC; ++u) {
+                if (tid + WG * u < nP) {
+                    double xn = xc[u] + al * (yc[u] - xc[u]);
+                    if (yc[u] <= 0.0 && step_ratio(xc[u], yc[u]) == al) xn = 0.0;
+                    if (xn <= 0.0) {
+                        xn = 0.0;
+                        fl |= 1u << u;
+                    }
+                    p.x[jc[u]] = xn;
+                }
+            }
+        }
+        // rm = the flagged positions in ascending order, which is the order of
+        // (u, wave, lane): a count per (u, wave) from the wave's ballot, their
+        // exclusive scan by wave 0, then each flagged lane's rank in its ballot
+        __shared__ int ucnt[IFC * NWI], ubase[IFC * NWI];
+        unsigned long long bm[IFC];
+#pragma unroll
+        for (int u = 0; u < IFC; ++u) bm[u] = __ballot((fl >> u) & 1u);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < IFC; ++u) ucnt[u * NWI + wid] = __popcll(bm[u]);
+        }
+        __syncthreads();
+        if (wid == 0) {
+            const int v = ucnt[lane];
+            int incl = v;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int w = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += w;
+            }
+            ubase[lane] = incl - v;
+            if (lane == 63) s.q = incl;
+        }
+        __syncthreads();
+        const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int u = 0; u < IFC; ++u)
+            if ((fl >> u) & 1u) p.rm[ubase[u * NWI + wid] + __popcll(bm[u] & below)] = tid + WG * u;
+        __syncthreads();
     } else {
         // the smallest y and, in the same pass, the step length (the smallest
         // ratio x / (x - y) over the positions with y <= 0, which are few)
