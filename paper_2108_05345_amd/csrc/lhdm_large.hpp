@@ -4502,8 +4502,8 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         HIPCHK(hipGetDevice(&dev));
         if (side_dev != dev) {
             HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+            HIPCHK(hipEventCreate(&ev_fork));
+            HIPCHK(hipEventCreate(&ev_join));
             side_dev = dev;
         }
     }
@@ -4603,7 +4603,10 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
                 pblk = (m - mir->ctl.nP + GRAM_ROWS - 1) / GRAM_ROWS;   // the blocks of rows >= n_P
             }
         }
-        hipLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, cs, a, (const double*)a.gpart, pblk, cqb);
+        // the fork and join events are the launches' own end events
+        // (hipExtLaunchKernelGGL), so no marker goes onto either stream
+        hipExtLaunchKernelGGL(lg_panel_b, dim3(1), dim3(WG), 0, cs, nullptr, ev_fork, 0, a, (const double*)a.gpart,
+                              pblk, cqb);
         // the triangular solve needs R, bt and the accepted count only: it runs
         // beside the Q update and the commit, on two streams.  The longer of
         // the two branches follows lg_panel_b on its stream and the other one
@@ -4612,7 +4615,6 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
         // about two thirds of m, where the two cross on a 4096-row instance.
         const bool solve_direct = 3 * mir->ctl.nP > 2 * m;
         hipStream_t qs = solve_direct ? os : cs, ts = solve_direct ? cs : os;
-        HIPCHK(hipEventRecord(ev_fork, cs));
         HIPCHK(hipStreamWaitEvent(os, ev_fork, 0));
         ++ep_t;
         hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, ts, a, ep_t, 1);
@@ -4632,10 +4634,9 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             hipLaunchKernelGGL(lg_qup2<16>, dim3((m + 15) / 16), dim3(WG), 0, qs, a);
         }
         hipLaunchKernelGGL(lg_commit_copy, dim3(256), dim3(WG), 0, qs, a);
-        hipLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, qs, a);
+        hipExtLaunchKernelGGL(lg_commit, dim3(1), dim3(WG), 0, qs, nullptr, ev_join, 0, a);
         HIPCHK(hipGetLastError());
         // the loop continues on the solve's stream once the other branch is in
-        HIPCHK(hipEventRecord(ev_join, qs));
         HIPCHK(hipStreamWaitEvent(ts, ev_join, 0));
         if (!solve_direct) std::swap(cs, os);
         bool restart = false;
@@ -4668,15 +4669,14 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
                 // the Q rotations run on the other stream beside the triangular
                 // solve, which is the longer of the two and so follows the
                 // compaction directly (no event wait on its path)
-                hipLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, cs, a, 1);
-                HIPCHK(hipEventRecord(ev_fork, cs));
+                hipExtLaunchKernelGGL(lg_compact, dim3(1), dim3(WG), 0, cs, nullptr, ev_fork, 0, a, 1);
                 HIPCHK(hipStreamWaitEvent(os, ev_fork, 0));
                 ++ep_t;
                 hipLaunchKernelGGL(lg_trsv, dim3(tgrid), dim3(WG), 0, cs, a, ep_t, 0);
                 HIPCHK(hipGetLastError());
-                hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, os, a, 1);
+                hipExtLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, os, nullptr, ev_join,
+                                      0, a, 1);
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipEventRecord(ev_join, os));
                 HIPCHK(hipStreamWaitEvent(cs, ev_join, 0));
             } else {
                 hipLaunchKernelGGL(lg_qrot, dim3((m + 1 + 63) / 64), dim3(64 * (1 + QNL)), 0, cs, a, 0);
