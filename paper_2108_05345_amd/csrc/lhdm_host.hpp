@@ -167,4 +167,11 @@ inline void kprof_drain() {
     k.next = 0;
 }
 
+// kprof_drain once half of the event pool is taken: for waits on the host's
+// critical path (two event calls per timed launch), the rest drained at the end.
+inline void kprof_drain_if_half() {
+    KernelProfile& k = kprof();
+    if (!k.pending.empty() && 2 * k.next >= (int)k.pool.size()) kprof_drain();
+}
+
 }  // namespace lhdm

@@ -4477,7 +4477,7 @@ static int large_solve(hipStream_t st, int m, int n, const double* A, long long 
             }
             __builtin_ia32_pause();
         }
-        kprof_drain();
+        kprof_drain_if_half();
         const LgExtra* hx = reinterpret_cast<const LgExtra*>(mir->ex_head);
         return hx->err ? LHDM_EHIP : 0;
     };
