@@ -3875,7 +3875,7 @@ __global__ __launch_bounds__(WG) void lg_cfdown(LgArgs a, int epoch) {
 
 __global__ __launch_bounds__(64) void lg_givens(LgArgs a, int epoch) {
     const LgExtra* ex = a.ex;
-    if (ex->inner_done) return;   // launched before the host reads the inner decision
+    if (ex->inner_done) return;   // no inner step (the solver launches it only for one)
     const Prob& p = a.p;
     const int nd = ex->ndown, first = ex->first;
     const int nb = (nd + GB - 1) / GB;
