@@ -327,3 +327,20 @@ def test_device_engine_tall_panel_fallback(lhdm):
     P = _passive(r)
     xs, *_ = np.linalg.lstsq(inst.A[:, P], inst.b, rcond=None)
     assert np.abs(xs - x[P]).max() <= 1e-8 * np.abs(xs).max()
+
+
+def test_device_engine_more_than_4096_passive(lhdm):
+    # the inner iteration keeps at most 4096 passive positions in registers (16
+    # per thread); beyond that it takes the strided loop.  A dense planted
+    # solution on a 4608-row instance ends with more than 4096 passive columns;
+    # checked through KKT and the final LS subproblem
+    inst = make_small(4608, 5200, 4400, 61, kind="uniform", noise_std=1e-2)
+    A, b = _dev(inst.A, inst.b)
+    r = lhdm.solve(A, b)
+    print(f"[wide passive] {r.info}", flush=True)
+    assert r.info["status"] == 0 and r.info["kkt_residual"] <= KKT
+    P = _passive(r)
+    assert len(P) > 4096
+    x = r.x.cpu().numpy()
+    xs, *_ = np.linalg.lstsq(inst.A[:, P], inst.b, rcond=None)
+    assert np.abs(xs - x[P]).max() <= 1e-8 * np.abs(xs).max()
