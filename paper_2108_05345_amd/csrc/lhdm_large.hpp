@@ -2974,27 +2974,38 @@ __global__ __launch_bounds__(WG) void lg_residual_part(LgArgs a) {
     const int c0 = chunk * per, c1 = min(nP, c0 + per);
     if (accept && blockIdx.x == 0)
         for (int cc = c0 + threadIdx.x; cc < c1; cc += WG) p.x[p.P[cc]] = p.ybuf[cc];
-    if (row >= p.m) return;
-    // eight columns' loads go out together; the sum keeps the column order
-    constexpr int RB = 8;
+    // the chunk's column indices and coefficients are staged in LDS (RS at a
+    // time), so that the column loads do not wait on the index loads; eight
+    // columns' loads go out together and the sum keeps the column order
+    constexpr int RS = 128, RB = 8;
+    __shared__ int js[RS];
+    __shared__ double xs[RS];
     double acc = 0.0;
-    for (int cb = c0; cb < c1; cb += RB) {
-        int j[RB];
-#pragma unroll
-        for (int u = 0; u < RB; ++u) j[u] = p.P[min(cb + u, c1 - 1)];
-        double av[RB], xv[RB];
-#pragma unroll
-        for (int u = 0; u < RB; ++u) {
-            double sg;
-            const double* col = col_ptr(p, j[u], sg);
-            av[u] = sg * col[row];
-            xv[u] = accept ? p.ybuf[min(cb + u, c1 - 1)] : p.x[j[u]];
+    for (int s0 = c0; s0 < c1; s0 += RS) {
+        const int ns = min(RS, c1 - s0);
+        __syncthreads();   // the previous stage is consumed
+        for (int t = threadIdx.x; t < ns; t += WG) {
+            const int j = p.P[s0 + t];
+            js[t] = j;
+            xs[t] = accept ? p.ybuf[s0 + t] : p.x[j];
         }
+        __syncthreads();
+        if (row < p.m) {
+            for (int cb = 0; cb < ns; cb += RB) {
+                double av[RB];
 #pragma unroll
-        for (int u = 0; u < RB; ++u)
-            if (cb + u < c1) acc += av[u] * xv[u];
+                for (int u = 0; u < RB; ++u) {
+                    double sg;
+                    const double* col = col_ptr(p, js[min(cb + u, ns - 1)], sg);
+                    av[u] = sg * col[row];
+                }
+#pragma unroll
+                for (int u = 0; u < RB; ++u)
+                    if (cb + u < ns) acc += av[u] * xs[cb + u];
+            }
+        }
     }
-    a.rpart[(size_t)chunk * p.m + row] = acc;
+    if (row < p.m) a.rpart[(size_t)chunk * p.m + row] = acc;
 }
 
 __global__ __launch_bounds__(WG) void lg_residual_sum(LgArgs a) {
